@@ -1,0 +1,203 @@
+/*
+ * sia.h -- C ABI of the MI355X (gfx950) HSAW spread-interdiction library.
+ *
+ * Method: Nguyen, Cano, Dinh, Vu, "Blocking Self-avoiding Walks Stops
+ * Cyber-epidemics: A Scalable GPU-based Approach" (KDD 2017,
+ * arXiv 1702.05854).  The library runs the data-parallel hot path of eSIA
+ * (Algorithm 6, edges) and nSIA (Algorithm 9, nodes) for a fixed sample
+ * count: sample Hitting Self-avoiding Walks (HSAWs) under the Linear
+ * Threshold model, count how many kept walks hold each edge / node, and pick
+ * k of them greedily by marginal coverage.
+ *
+ * Conventions for every entry point:
+ *  - Every call returns sia_status; 0 is success.  On failure a message for
+ *    the calling thread is available from sia_last_error().
+ *  - "device pointer" = memory the HIP runtime allocated on the current
+ *    device; "host pointer" = ordinary CPU memory.  The caller owns every
+ *    array it passes; the library never frees caller memory.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *    ordered on that stream; calls that return host results synchronise it
+ *    before returning.
+ *  - Graph: n nodes 0..n-1, m directed edges in in-edge CSC order.  Column v
+ *    lists the in-edges (u,v) of v at positions col_off[v] .. col_off[v+1]-1;
+ *    row_idx[j] is u, w[j] is the LT weight w(u,v).  An edge id is its CSC
+ *    position j.  Limits: 2 <= n < 2^31, 0 <= m < 2^32.
+ *  - Random stream: Philox4x64-10 keyed by (seed, attempt id).  The start
+ *    draw of attempt a is 64-bit word 0 of the block with counter (0,1,0,0);
+ *    the live in-edge of node x in attempt a is chosen by the high 32 bits of
+ *    word 0 of the block with counter (x,0,0,0).  Results therefore depend
+ *    only on (graph, sources, mode, k, attempt range, seed).
+ */
+#ifndef SIA_H
+#define SIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SIA_OK = 0,
+    SIA_EINVAL = -1,     /* malformed argument or graph structure */
+    SIA_EWEIGHTS = -2,   /* a weight outside [0,1]/NaN, or an in-weight sum above 1 */
+    SIA_ENOMEM = -3,     /* device or host allocation failed */
+    SIA_EDEVICE = -4,    /* HIP runtime error */
+    SIA_ENOTREADY = -5,  /* reserved: result not ready */
+    SIA_ECANCELLED = -6, /* reserved: request cancelled */
+    SIA_EBUSY = -7       /* reserved: no free slot */
+} sia_status;
+
+typedef enum {
+    SIA_EDGES = 0, /* eSIA: ids are CSC edge positions (Definition "edge_remove") */
+    SIA_NODES = 1  /* nSIA: ids are node ids (Definition "node_remove") */
+} sia_mode;
+
+typedef struct sia_graph sia_graph; /* opaque; device-resident, immutable */
+
+/* Counters and estimates of one run.  Integer fields are exact. */
+typedef struct {
+    uint64_t attempts;     /* walk attempts made (N) */
+    uint64_t hits;         /* attempts that ended at a source: kept HSAWs */
+    uint64_t dead_ends;    /* attempts that found no live in-edge */
+    uint64_t cycles;       /* attempts whose walk returned to a visited node */
+    uint64_t steps;        /* live-edge draws of the plain walk (Algorithm 1):
+                              a hit or dead end after t draws counts t; a walk
+                              whose t-th draw repeats a node counts t */
+    uint64_t evaluations;  /* live-edge evaluations the device performed
+                              (cycle detection and re-walks make it >= steps) */
+    uint64_t walk_ids;     /* ids over all kept walks */
+    uint64_t covered;      /* kept walks hit by the selected set, = sum of gains */
+    double spread_est;     /* |X| + |V\X| * hits / N  (expected spread, p == 1) */
+    double suspension_est; /* |V\X| * covered / N  (Theorem "lem:rr_edge") */
+    double suspension_nodes_est; /* suspension_est + |selected & X| (nodes) */
+    float ms_sample;       /* device time of the sampling kernel (HIP events,
+                              on hip_stream), 0 unless timing was requested */
+    float ms_count;        /* coverage counting + inverted index */
+    float ms_greedy;       /* greedy rounds */
+    float ms_total;        /* whole call on the device */
+} sia_stats;
+
+/* Kept walks returned by sia_sample, in CSR form, allocated by the library
+ * in host memory; release with sia_walks_free. */
+typedef struct {
+    uint64_t n_walks;  /* kept HSAWs */
+    uint64_t n_ids;
+    uint64_t *attempt; /* [n_walks] attempt id of each kept walk (unordered) */
+    uint64_t *off;     /* [n_walks+1] offsets into ids */
+    uint32_t *ids;     /* [n_ids] edges: CSC positions j_1..j_{l-1} (walk
+                          order from the start); nodes: v_1..v_l */
+    sia_stats stats;
+} sia_walks;
+
+/* Library version string. */
+const char *sia_version(void);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *sia_last_error(void);
+
+/*
+ * Check the query arguments of sia_solve / sia_sample on the host without
+ * touching the GPU (also done inside those calls).
+ *   n, m             graph sizes
+ *   mode             SIA_EDGES or SIA_NODES
+ *   sources          host pointer, n_sources node ids (any order); must be
+ *                    distinct, in [0,n), with 1 <= n_sources <= n-1
+ *   k                budget; 1 <= k <= m (edges) or <= n (nodes); k = 0 is
+ *                    accepted here when the caller does not select (sampling)
+ *   n_attempts       1 <= n_attempts < 2^32
+ *   attempt_offset   first attempt id; offset + n_attempts must not overflow
+ * Returns SIA_OK or SIA_EINVAL.
+ */
+sia_status sia_check_query(int64_t n, int64_t m, int mode, const int32_t *sources,
+                           int64_t n_sources, int64_t k, uint64_t n_attempts,
+                           uint64_t attempt_offset);
+
+/*
+ * Ingest a graph (a1): copy it into library-owned HBM and build, for every
+ * column v, the integer live-edge table of the LT model (Section 2.1, the
+ * live-edge equivalence): q_j = round-half-even(w_j * 2^32), thr_j = the
+ * running sum of q over the column, clamped to 2^32 - 1.  Edge j is live
+ * with probability (thr_j - thr_{j-1}) / 2^32, no edge with
+ * (2^32 - thr_last) / 2^32.
+ *   col_off   int64[n+1], col_off[0] = 0, non-decreasing, col_off[n] = m
+ *   row_idx   int32[m] in [0,n)
+ *   w         float[m] in [0,1]; each column's sum must be <= 1 + 2^-20
+ *             (the LT constraint up to fp32 rounding)
+ *   inputs_on_device  0: the three arrays are host pointers (validated on
+ *             the host, then copied); 1: device pointers (validated by a
+ *             kernel).  The caller may free them when the call returns.
+ *   out       receives the handle (NULL on failure).
+ * Errors: SIA_EINVAL (structure), SIA_EWEIGHTS (weights), SIA_ENOMEM,
+ * SIA_EDEVICE.
+ */
+sia_status sia_graph_create(int64_t n, int64_t m, const int64_t *col_off,
+                            const int32_t *row_idx, const float *w,
+                            int inputs_on_device, void *hip_stream,
+                            sia_graph **out);
+
+/* Release a graph and all its device memory (NULL is a no-op). */
+sia_status sia_graph_destroy(sia_graph *g);
+
+/* n and m of a graph (either pointer may be NULL). */
+sia_status sia_graph_info(const sia_graph *g, int64_t *n, int64_t *m);
+
+/* Copy the threshold table thr[m] (see sia_graph_create) to host memory
+ * thr_host (caller-allocated, m entries).  Test hook. */
+sia_status sia_graph_thresholds(const sia_graph *g, uint32_t *thr_host, void *hip_stream);
+
+/* Device conversion q[i] = round-half-even(w[i] * 2^32) for count values
+ * (w, q device pointers; w in [0,1], other values give q = 0).  Exposes the
+ * ingest kernel's conversion for exhaustive checks.  Test hook. */
+sia_status sia_quantize(const float *w_dev, uint64_t *q_dev, uint64_t count, void *hip_stream);
+
+/*
+ * Sample HSAWs (Algorithm 1 semantics, Definition "self_walk"): for every
+ * attempt a in [attempt_offset, attempt_offset + n_attempts): start at the
+ * floor(x0 * |V\X| / 2^64)-th non-source node in ascending id order and
+ * follow the live in-edge of each node until the walk reaches a source
+ * (kept), finds no live edge (dead end) or returns to a node already on it
+ * (cycle).  Kept walks go to *out (library-allocated host memory).
+ *   sources    host pointer, see sia_check_query
+ *   out        filled on success; free with sia_walks_free
+ */
+sia_status sia_sample(const sia_graph *g, int mode, const int32_t *sources,
+                      int64_t n_sources, uint64_t n_attempts, uint64_t attempt_offset,
+                      uint64_t seed, sia_walks *out, void *hip_stream);
+
+/* Free the arrays of a sia_walks filled by sia_sample (NULL-safe). */
+void sia_walks_free(sia_walks *w);
+
+/*
+ * Greedy max-coverage (Algorithm 4 / Algorithm 7) on given walks: k rounds,
+ * each taking the id with the largest number of not-yet-covered walks
+ * holding it (ties: lowest id), then covering those walks.  Rounds where
+ * every gain is zero take the lowest id not yet selected, so exactly k ids
+ * are returned.
+ *   id_space   ids are in [0, id_space); 1 <= k <= id_space
+ *   walk_off   host uint64[n_walks+1], ids host uint32[walk_off[n_walks]];
+ *              each walk holds an id at most once
+ *   selected   host int64[k] (out), gains host uint64[k] (out)
+ */
+sia_status sia_greedy(int64_t id_space, const uint64_t *walk_off, const uint32_t *ids,
+                      uint64_t n_walks, int64_t k, int64_t *selected, uint64_t *gains,
+                      void *hip_stream);
+
+/*
+ * The whole hot path for one query (eSIA / nSIA with a fixed sample count):
+ * sample as sia_sample, count coverage, greedy as sia_greedy over the kept
+ * walks, and the estimates of Theorem "lem:rr_edge" / "lem:rr_node".
+ *   selected   host int64[k] (out); gains host uint64[k] (out)
+ *   stats      host (out, may be NULL)
+ *   timing     nonzero: record HIP events around the phases into stats
+ */
+sia_status sia_solve(const sia_graph *g, int mode, const int32_t *sources,
+                     int64_t n_sources, int64_t k, uint64_t n_attempts,
+                     uint64_t attempt_offset, uint64_t seed, int64_t *selected,
+                     uint64_t *gains, sia_stats *stats, int timing, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIA_H */
