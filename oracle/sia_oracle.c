@@ -134,9 +134,11 @@ int orc_quantize(const float *w, int64_t count, uint64_t *q_out)
 }
 
 /* Weight validation: the LT model needs sum_u w(u,v) <= 1 for every v
- * (Section 2.1).  fp32 rounding of exact weights can lift a column sum by
- * a relative 2^-24 at most, so a column is rejected when the sum of its
- * weights (exact in double for the degrees we accept) exceeds 1 + 2^-20. */
+ * (Section 2.1).  The check is made on the integer table: with real weights
+ * summing to at most 1, fp32 rounding adds at most 2^-24 (2^8 units of q)
+ * and the rounding of each q_j at most 1/2, so a column is rejected when
+ *     sum_j q_j > 2^32 + 2^12 + floor(deg / 2).
+ * Every weight must lie in [0,1] (NaN rejected).                        */
 int orc_thresholds(int64_t n, const int64_t *col_off, const float *w,
                    uint32_t *thr_out)
 {
@@ -146,18 +148,16 @@ int orc_thresholds(int64_t n, const int64_t *col_off, const float *w,
         int64_t lo = col_off[v], hi = col_off[v + 1];
         if (hi < lo)
             return ORC_EINVAL;
-        double colsum = 0.0;
         uint64_t run = 0;
         for (int64_t j = lo; j < hi; ++j) {
             float x = w[j];
             if (!(x >= 0.0f && x <= 1.0f))
                 return ORC_EWEIGHTS;
-            colsum += (double)x;
             uint64_t qj = (uint64_t)llrint(ldexp((double)x, 32));
             run += qj;
             thr_out[j] = run > 0xFFFFFFFFULL ? 0xFFFFFFFFU : (uint32_t)run;
         }
-        if (colsum > 1.0 + ldexp(1.0, -20))
+        if (run > (1ULL << 32) + (1ULL << 12) + (uint64_t)(hi - lo) / 2)
             return ORC_EWEIGHTS;
     }
     return ORC_OK;

@@ -1,0 +1,371 @@
+// C ABI entry points (declared in include/sia.h): argument checks, the
+// host-side source tables, and orchestration of the device phases.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+
+namespace sia {
+
+namespace {
+thread_local std::string g_last_error;
+
+// Run f(); convert failures into a status and a thread-local message.
+template <class F>
+sia_status guarded(F &&f)
+{
+    try {
+        g_last_error.clear();
+        f();
+        return SIA_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return SIA_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return SIA_EDEVICE;
+    }
+}
+
+// Make g's device current for the duration of a call.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev)
+    {
+        SIA_HIP(hipGetDevice(&prev));
+        if (prev != dev) SIA_HIP(hipSetDevice(dev));
+    }
+    ~DeviceScope()
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr uint32_t kMaxBuckets = 1u << 16;
+}  // namespace
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+void DevBuf::ensure(size_t want)
+{
+    if (want == 0) want = 1;
+    if (ptr && bytes >= want) return;
+    release();
+    SIA_HIP(hipMalloc(&ptr, want));
+    bytes = want;
+}
+
+void DevBuf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+void check_query(int64_t n, int64_t m, int mode, const int32_t *sources, int64_t n_sources,
+                 int64_t k, uint64_t n_attempts, uint64_t attempt_offset)
+{
+    SIA_REQUIRE(n >= 2 && n < (int64_t(1) << 31), SIA_EINVAL, "n must be in [2, 2^31)");
+    SIA_REQUIRE(m >= 0 && m < (int64_t(1) << 32), SIA_EINVAL, "m must be in [0, 2^32)");
+    SIA_REQUIRE(mode == SIA_EDGES || mode == SIA_NODES, SIA_EINVAL, "mode must be SIA_EDGES or SIA_NODES");
+    SIA_REQUIRE(sources != nullptr, SIA_EINVAL, "sources is NULL");
+    SIA_REQUIRE(n_sources >= 1 && n_sources <= n - 1, SIA_EINVAL,
+                "n_sources must be in [1, n-1]");
+    const int64_t id_space = mode == SIA_EDGES ? m : n;
+    SIA_REQUIRE(k >= 0 && k <= id_space, SIA_EINVAL,
+                "k must be in [1, m] (edges) or [1, n] (nodes)");
+    SIA_REQUIRE(n_attempts >= 1 && n_attempts < (uint64_t(1) << 32), SIA_EINVAL,
+                "n_attempts must be in [1, 2^32)");
+    SIA_REQUIRE(attempt_offset <= ~uint64_t(0) - n_attempts, SIA_EINVAL,
+                "attempt_offset + n_attempts overflows");
+    std::vector<int32_t> s(sources, sources + n_sources);
+    std::sort(s.begin(), s.end());
+    SIA_REQUIRE(s.front() >= 0 && s.back() < n, SIA_EINVAL, "a source is outside [0, n)");
+    SIA_REQUIRE(std::adjacent_find(s.begin(), s.end()) == s.end(), SIA_EINVAL,
+                "sources must be distinct");
+}
+
+SourceTables build_source_tables(int64_t n, const int32_t *sources, int64_t n_sources)
+{
+    SourceTables st;
+    st.sorted.assign(sources, sources + n_sources);
+    std::sort(st.sorted.begin(), st.sorted.end());
+    st.t.resize(n_sources);
+    for (int64_t i = 0; i < n_sources; ++i)
+        st.t[i] = static_cast<uint32_t>(st.sorted[i] - i);  // non-sources below s_i
+    st.n_ns = static_cast<uint64_t>(n - n_sources);
+    uint32_t shift = 0;
+    while (((st.n_ns + (uint64_t(1) << shift) - 1) >> shift) > kMaxBuckets) ++shift;
+    st.shift = shift;
+    const uint64_t nb = ((st.n_ns + (uint64_t(1) << shift) - 1) >> shift) + 1;
+    st.bucket.resize(nb);
+    uint64_t c = 0;
+    for (uint64_t b = 0; b < nb; ++b) {
+        const uint64_t lo = b << shift;
+        while (c < static_cast<uint64_t>(n_sources) && st.t[c] < lo) ++c;
+        st.bucket[b] = static_cast<uint32_t>(c);
+    }
+    return st;
+}
+
+}  // namespace sia
+
+using namespace sia;
+
+extern "C" {
+
+const char *sia_version(void) { return "sia 0.1 (gfx950)"; }
+
+const char *sia_last_error(void) { return g_last_error.c_str(); }
+
+sia_status sia_check_query(int64_t n, int64_t m, int mode, const int32_t *sources,
+                           int64_t n_sources, int64_t k, uint64_t n_attempts,
+                           uint64_t attempt_offset)
+{
+    return guarded([&] { check_query(n, m, mode, sources, n_sources, k, n_attempts, attempt_offset); });
+}
+
+sia_status sia_graph_create(int64_t n, int64_t m, const int64_t *col_off, const int32_t *row_idx,
+                            const float *w, int inputs_on_device, void *hip_stream,
+                            sia_graph **out)
+{
+    return guarded([&] {
+        SIA_REQUIRE(out != nullptr, SIA_EINVAL, "out is NULL");
+        *out = nullptr;
+        SIA_REQUIRE(n >= 2 && n < (int64_t(1) << 31), SIA_EINVAL, "n must be in [2, 2^31)");
+        SIA_REQUIRE(m >= 0 && m < (int64_t(1) << 32), SIA_EINVAL, "m must be in [0, 2^32)");
+        SIA_REQUIRE(col_off != nullptr, SIA_EINVAL, "col_off is NULL");
+        SIA_REQUIRE(m == 0 || (row_idx != nullptr && w != nullptr), SIA_EINVAL,
+                    "row_idx / w is NULL");
+        std::unique_ptr<sia_graph> g(new sia_graph);
+        g->n = n;
+        g->m = m;
+        // host structure checks need no device; run them before touching HIP
+        if (!inputs_on_device) host_check_structure(n, m, col_off, row_idx);
+        SIA_HIP(hipGetDevice(&g->device));
+        ingest_graph(g.get(), col_off, row_idx, w, inputs_on_device != 0,
+                     static_cast<hipStream_t>(hip_stream));
+        *out = g.release();
+    });
+}
+
+sia_status sia_graph_destroy(sia_graph *g)
+{
+    return guarded([&] {
+        if (!g) return;
+        DeviceScope ds(g->device);
+        delete g;
+    });
+}
+
+sia_status sia_graph_info(const sia_graph *g, int64_t *n, int64_t *m)
+{
+    return guarded([&] {
+        SIA_REQUIRE(g != nullptr, SIA_EINVAL, "graph is NULL");
+        if (n) *n = g->n;
+        if (m) *m = g->m;
+    });
+}
+
+sia_status sia_graph_thresholds(const sia_graph *g, uint32_t *thr_host, void *hip_stream)
+{
+    return guarded([&] {
+        SIA_REQUIRE(g != nullptr && thr_host != nullptr, SIA_EINVAL, "NULL argument");
+        DeviceScope ds(g->device);
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (!g->m) return;
+        std::vector<EdgeRec> tmp(static_cast<size_t>(g->m));
+        SIA_HIP(hipMemcpyAsync(tmp.data(), g->edges.ptr, sizeof(EdgeRec) * g->m,
+                               hipMemcpyDeviceToHost, s));
+        SIA_HIP(hipStreamSynchronize(s));
+        for (int64_t j = 0; j < g->m; ++j) thr_host[j] = tmp[j].thr;
+    });
+}
+
+sia_status sia_quantize(const float *w_dev, uint64_t *q_dev, uint64_t count, void *hip_stream)
+{
+    return guarded([&] {
+        SIA_REQUIRE(count == 0 || (w_dev && q_dev), SIA_EINVAL, "NULL argument");
+        quantize_device(w_dev, q_dev, count, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+void sia_walks_free(sia_walks *w)
+{
+    if (!w) return;
+    std::free(w->attempt);
+    std::free(w->off);
+    std::free(w->ids);
+    w->attempt = nullptr;
+    w->off = nullptr;
+    w->ids = nullptr;
+    w->n_walks = w->n_ids = 0;
+}
+
+sia_status sia_sample(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
+                      uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
+                      sia_walks *out, void *hip_stream)
+{
+    return guarded([&] {
+        SIA_REQUIRE(cg != nullptr && out != nullptr, SIA_EINVAL, "NULL argument");
+        std::memset(out, 0, sizeof(*out));
+        sia_graph *g = const_cast<sia_graph *>(cg);
+        check_query(g->n, g->m, mode, sources, n_sources, 0, n_attempts, attempt_offset);
+        std::lock_guard<std::mutex> lock(g->mu);
+        DeviceScope ds(g->device);
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        const SourceTables st = build_source_tables(g->n, sources, n_sources);
+        const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, false);
+
+        std::vector<uint64_t> att(r.walks), off(r.walks);
+        std::vector<uint32_t> len(r.walks), ids(r.ids);
+        if (r.walks) {
+            SIA_HIP(hipMemcpyAsync(att.data(), g->ws.walk_attempt.ptr, 8 * r.walks, hipMemcpyDeviceToHost, s));
+            SIA_HIP(hipMemcpyAsync(off.data(), g->ws.walk_off.ptr, 8 * r.walks, hipMemcpyDeviceToHost, s));
+            SIA_HIP(hipMemcpyAsync(len.data(), g->ws.walk_len.ptr, 4 * r.walks, hipMemcpyDeviceToHost, s));
+        }
+        if (r.ids)
+            SIA_HIP(hipMemcpyAsync(ids.data(), g->ws.ids.ptr, 4 * r.ids, hipMemcpyDeviceToHost, s));
+        SIA_HIP(hipStreamSynchronize(s));
+
+        std::vector<uint64_t> order(r.walks);
+        std::iota(order.begin(), order.end(), uint64_t(0));
+        std::sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) { return att[a] < att[b]; });
+        out->attempt = static_cast<uint64_t *>(std::malloc(8 * std::max<uint64_t>(r.walks, 1)));
+        out->off = static_cast<uint64_t *>(std::malloc(8 * (r.walks + 1)));
+        out->ids = static_cast<uint32_t *>(std::malloc(4 * std::max<uint64_t>(r.ids, 1)));
+        if (!out->attempt || !out->off || !out->ids) {
+            sia_walks_free(out);
+            throw std::bad_alloc();
+        }
+        uint64_t pos = 0;
+        for (uint64_t i = 0; i < r.walks; ++i) {
+            const uint64_t w = order[i];
+            out->attempt[i] = att[w];
+            out->off[i] = pos;
+            std::memcpy(out->ids + pos, ids.data() + off[w], 4 * static_cast<size_t>(len[w]));
+            pos += len[w];
+        }
+        out->off[r.walks] = pos;
+        out->n_walks = r.walks;
+        out->n_ids = pos;
+        sia_stats &S = out->stats;
+        S.attempts = n_attempts;
+        S.hits = r.hits;
+        S.dead_ends = r.dead;
+        S.cycles = r.cycles;
+        S.steps = r.steps;
+        S.evaluations = r.evals;
+        S.walk_ids = r.ids;
+        const double n_ns = static_cast<double>(st.n_ns);
+        S.spread_est = static_cast<double>(n_sources) + n_ns * r.hits / static_cast<double>(n_attempts);
+    });
+}
+
+sia_status sia_greedy(int64_t id_space, const uint64_t *walk_off, const uint32_t *ids,
+                      uint64_t n_walks, int64_t k, int64_t *selected, uint64_t *gains,
+                      void *hip_stream)
+{
+    return guarded([&] {
+        SIA_REQUIRE(id_space >= 1 && id_space < (int64_t(1) << 32), SIA_EINVAL,
+                    "id_space must be in [1, 2^32)");
+        SIA_REQUIRE(k >= 1 && k <= id_space, SIA_EINVAL, "k must be in [1, id_space]");
+        SIA_REQUIRE(walk_off != nullptr && selected != nullptr && gains != nullptr, SIA_EINVAL,
+                    "NULL argument");
+        const uint64_t n_ids = walk_off[n_walks];
+        SIA_REQUIRE(walk_off[0] == 0, SIA_EINVAL, "walk_off[0] must be 0");
+        SIA_REQUIRE(n_ids == 0 || ids != nullptr, SIA_EINVAL, "ids is NULL");
+        std::vector<uint32_t> len(n_walks);
+        for (uint64_t w = 0; w < n_walks; ++w) {
+            SIA_REQUIRE(walk_off[w + 1] >= walk_off[w], SIA_EINVAL, "walk_off must be non-decreasing");
+            len[w] = static_cast<uint32_t>(walk_off[w + 1] - walk_off[w]);
+        }
+        for (uint64_t e = 0; e < n_ids; ++e)
+            SIA_REQUIRE(ids[e] < static_cast<uint64_t>(id_space), SIA_EINVAL, "an id is outside [0, id_space)");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        Workspace ws;
+        ws.walk_off.ensure(8 * std::max<uint64_t>(n_walks, 1));
+        ws.walk_len.ensure(4 * std::max<uint64_t>(n_walks, 1));
+        ws.ids.ensure(4 * std::max<uint64_t>(n_ids, 1));
+        if (n_walks) {
+            SIA_HIP(hipMemcpyAsync(ws.walk_off.ptr, walk_off, 8 * n_walks, hipMemcpyHostToDevice, s));
+            SIA_HIP(hipMemcpyAsync(ws.walk_len.ptr, len.data(), 4 * n_walks, hipMemcpyHostToDevice, s));
+        }
+        if (n_ids) SIA_HIP(hipMemcpyAsync(ws.ids.ptr, ids, 4 * n_ids, hipMemcpyHostToDevice, s));
+        run_greedy(ws, id_space, n_walks, n_ids, k, selected, gains, s, false);
+    });
+}
+
+sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
+                     int64_t k, uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
+                     int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
+                     void *hip_stream)
+{
+    return guarded([&] {
+        SIA_REQUIRE(cg != nullptr && selected != nullptr && gains != nullptr, SIA_EINVAL,
+                    "NULL argument");
+        sia_graph *g = const_cast<sia_graph *>(cg);
+        check_query(g->n, g->m, mode, sources, n_sources, k, n_attempts, attempt_offset);
+        SIA_REQUIRE(k >= 1, SIA_EINVAL, "k must be >= 1");
+        std::lock_guard<std::mutex> lock(g->mu);
+        DeviceScope ds(g->device);
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing) {
+            SIA_HIP(hipEventCreate(&e0));
+            SIA_HIP(hipEventCreate(&e1));
+            SIA_HIP(hipEventRecord(e0, s));
+        }
+        const SourceTables st = build_source_tables(g->n, sources, n_sources);
+        const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, timing != 0);
+        const int64_t id_space = mode == SIA_EDGES ? g->m : g->n;
+        const GreedyResult gr = run_greedy(g->ws, id_space, r.walks, r.ids, k, selected, gains, s,
+                                           timing != 0);
+        float ms_total = 0.f;
+        if (timing) {
+            SIA_HIP(hipEventRecord(e1, s));
+            SIA_HIP(hipEventSynchronize(e1));
+            SIA_HIP(hipEventElapsedTime(&ms_total, e0, e1));
+            SIA_HIP(hipEventDestroy(e0));
+            SIA_HIP(hipEventDestroy(e1));
+        }
+        if (stats) {
+            sia_stats S{};
+            S.attempts = n_attempts;
+            S.hits = r.hits;
+            S.dead_ends = r.dead;
+            S.cycles = r.cycles;
+            S.steps = r.steps;
+            S.evaluations = r.evals;
+            S.walk_ids = r.ids;
+            uint64_t covered = 0;
+            int64_t src_selected = 0;
+            for (int64_t i = 0; i < k; ++i) {
+                covered += gains[i];
+                if (mode == SIA_NODES &&
+                    std::binary_search(st.sorted.begin(), st.sorted.end(), static_cast<int32_t>(selected[i])))
+                    ++src_selected;
+            }
+            S.covered = covered;
+            const double n_ns = static_cast<double>(st.n_ns), N = static_cast<double>(n_attempts);
+            S.spread_est = static_cast<double>(n_sources) + n_ns * static_cast<double>(r.hits) / N;
+            S.suspension_est = n_ns * static_cast<double>(covered) / N;
+            S.suspension_nodes_est = S.suspension_est + static_cast<double>(src_selected);
+            S.ms_sample = r.ms;
+            S.ms_count = gr.ms_count;
+            S.ms_greedy = gr.ms_greedy;
+            S.ms_total = ms_total;
+            *stats = S;
+        }
+    });
+}
+
+}  // extern "C"

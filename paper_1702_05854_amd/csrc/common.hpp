@@ -1,0 +1,138 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sia.h"
+
+namespace sia {
+
+// ------------------------------------------------------------ errors
+void set_error(const std::string &msg);
+void clear_error();
+
+struct Error {
+    sia_status status;
+    std::string msg;
+};
+
+#define SIA_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::sia::Error{e_ == hipErrorOutOfMemory ? SIA_ENOMEM : SIA_EDEVICE,    \
+                               std::string(#call) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+
+#define SIA_REQUIRE(cond, status, msg)                                                  \
+    do {                                                                                \
+        if (!(cond)) throw ::sia::Error{(status), (msg)};                               \
+    } while (0)
+
+// ------------------------------------------------------------ device layout
+// One 16-byte record per node: where its in-edges start, how many, the last
+// cumulative threshold (so the dead-end test needs no extra load), and the
+// float scale deg/thr_last used as the first guess of the threshold search.
+struct NodeRec {
+    uint32_t off;
+    uint32_t deg;
+    uint32_t thr_last;
+    float guess_scale;
+};
+static_assert(sizeof(NodeRec) == 16, "NodeRec layout");
+
+// One 8-byte record per edge: cumulative threshold and tail node u, so the
+// probe that certifies the choice also yields the next node.
+struct EdgeRec {
+    uint32_t thr;
+    uint32_t row;
+};
+static_assert(sizeof(EdgeRec) == 8, "EdgeRec layout");
+
+// ------------------------------------------------------------ device buffers
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t want);  // grow-only, contents not preserved
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+    ~DevBuf() { release(); }
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+};
+
+struct Workspace {
+    DevBuf walk_attempt, walk_off, walk_len, ids;  // sampler output
+    DevBuf counters;                               // sampler / greedy scalars
+    DevBuf src_sorted, src_t, bucket, bitmap;      // per-query source tables
+    DevBuf cnt, cur, inv, covered;                 // coverage + inverted index
+    DevBuf lvl1, lvl2, flag1, flag2, dirty1, dirty2, sel, gain, scan_tmp;
+    uint64_t walk_cap = 0, id_cap = 0;
+};
+
+}  // namespace sia
+
+struct sia_graph {
+    int64_t n = 0, m = 0;
+    int device = 0;
+    sia::DevBuf nodes;  // NodeRec[n]
+    sia::DevBuf edges;  // EdgeRec[m]
+    sia::Workspace ws;
+    std::mutex mu;      // one query at a time per graph handle
+};
+
+namespace sia {
+
+// Per-query source tables, built on the host.
+struct SourceTables {
+    std::vector<int32_t> sorted;   // ascending sources
+    std::vector<uint32_t> t;       // t_i = s_i - i (non-sources below s_i)
+    std::vector<uint32_t> bucket;  // bucket[b] = #{i : t_i < b << shift}
+    uint32_t shift = 0;
+    uint64_t n_ns = 0;
+};
+void check_query(int64_t n, int64_t m, int mode, const int32_t *sources, int64_t n_sources,
+                 int64_t k, uint64_t n_attempts, uint64_t attempt_offset);
+SourceTables build_source_tables(int64_t n, const int32_t *sources, int64_t n_sources);
+
+// Stats slots written by the sampler.
+enum StatSlot {
+    ST_WALKS = 0, ST_IDS = 1, ST_HITS = 2, ST_DEAD = 3, ST_CYCLE = 4, ST_STEPS = 5,
+    ST_EVALS = 6, ST_OVERFLOW = 7, ST_NEXT = 8, ST_FAULTS = 9, ST_COUNT = 16
+};
+
+struct SampleResult {
+    uint64_t walks = 0, ids = 0, hits = 0, dead = 0, cycles = 0, steps = 0, evals = 0;
+    float ms = 0.f;
+};
+
+// Upload sources, build bitmap, run the sampler (rerunning with larger
+// buffers if the output did not fit).  Results stay in g->ws.
+SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
+                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing);
+
+struct GreedyResult {
+    float ms_count = 0.f, ms_greedy = 0.f;
+};
+// Coverage counts + inverted index + k greedy rounds over the walks held in
+// g->ws (walk_off / walk_len / ids, n_walks walks, n_ids ids).  Writes k
+// selected ids and gains to host arrays.
+GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
+                        int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s,
+                        bool timing);
+
+// Ingest: host structure checks (no device needed) and the device kernels.
+void host_check_structure(int64_t n, int64_t m, const int64_t *col_off, const int32_t *row_idx);
+void ingest_graph(sia_graph *g, const int64_t *col_off, const int32_t *row_idx, const float *w,
+                  bool on_device, hipStream_t s);
+void quantize_device(const float *w, uint64_t *q, uint64_t count, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace sia

@@ -1,0 +1,224 @@
+"""Thin ctypes binding of ``libsia.so`` (the C ABI in ``include/sia.h``).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  Device arrays are torch tensors on a ROCm device (their
+``data_ptr()`` is passed through); host arrays are numpy arrays.  The stream
+is ``torch.cuda.current_stream().cuda_stream`` unless one is given.
+
+The library must be built (``python -m paper_1702_05854_amd.build``); loading
+fails loudly when it is missing -- there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsia.so")
+
+EDGES = 0
+NODES = 1
+MODES = {"edges": EDGES, "nodes": NODES, EDGES: EDGES, NODES: NODES}
+
+STATUS = {0: "SIA_OK", -1: "SIA_EINVAL", -2: "SIA_EWEIGHTS", -3: "SIA_ENOMEM",
+          -4: "SIA_EDEVICE", -5: "SIA_ENOTREADY", -6: "SIA_ECANCELLED", -7: "SIA_EBUSY"}
+
+
+class SiaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Stats(C.Structure):
+    _fields_ = [("attempts", C.c_uint64), ("hits", C.c_uint64), ("dead_ends", C.c_uint64),
+                ("cycles", C.c_uint64), ("steps", C.c_uint64), ("evaluations", C.c_uint64),
+                ("walk_ids", C.c_uint64), ("covered", C.c_uint64),
+                ("spread_est", C.c_double), ("suspension_est", C.c_double),
+                ("suspension_nodes_est", C.c_double),
+                ("ms_sample", C.c_float), ("ms_count", C.c_float), ("ms_greedy", C.c_float),
+                ("ms_total", C.c_float)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class _Walks(C.Structure):
+    _fields_ = [("n_walks", C.c_uint64), ("n_ids", C.c_uint64),
+                ("attempt", C.POINTER(C.c_uint64)), ("off", C.POINTER(C.c_uint64)),
+                ("ids", C.POINTER(C.c_uint32)), ("stats", Stats)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsia.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1702_05854_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        p, i64, u64, i32 = C.c_void_p, C.c_int64, C.c_uint64, C.c_int
+        L.sia_version.restype = C.c_char_p
+        L.sia_last_error.restype = C.c_char_p
+        L.sia_check_query.argtypes = [i64, i64, i32, p, i64, i64, u64, u64]
+        L.sia_graph_create.argtypes = [i64, i64, p, p, p, i32, p, C.POINTER(p)]
+        L.sia_graph_destroy.argtypes = [p]
+        L.sia_graph_info.argtypes = [p, C.POINTER(i64), C.POINTER(i64)]
+        L.sia_graph_thresholds.argtypes = [p, p, p]
+        L.sia_quantize.argtypes = [p, p, u64, p]
+        L.sia_sample.argtypes = [p, i32, p, i64, u64, u64, u64, C.POINTER(_Walks), p]
+        L.sia_walks_free.argtypes = [C.POINTER(_Walks)]
+        L.sia_walks_free.restype = None
+        L.sia_greedy.argtypes = [i64, p, p, u64, i64, p, p, p]
+        L.sia_solve.argtypes = [p, i32, p, i64, i64, u64, u64, u64, p, p, C.POINTER(Stats), i32, p]
+        for name in ("sia_check_query", "sia_graph_create", "sia_graph_destroy", "sia_graph_info",
+                     "sia_graph_thresholds", "sia_quantize", "sia_sample", "sia_greedy",
+                     "sia_solve"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise SiaError(rc, lib().sia_last_error().decode())
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def check_query(n, m, mode, sources, k, n_attempts, attempt_offset=0):
+    src = _host(sources, np.int32)
+    _check(lib().sia_check_query(n, m, MODES[mode], _hptr(src), src.shape[0], k, n_attempts,
+                                 attempt_offset))
+
+
+class Graph:
+    """A device-resident graph (ingest + LT threshold tables built on the GPU).
+
+    ``col_off`` int64[n+1], ``row_idx`` int32[m], ``w`` float32[m]: either all
+    torch tensors on the current ROCm device, or host arrays (numpy / CPU
+    tensors)."""
+
+    def __init__(self, col_off, row_idx, w, stream=None):
+        self._h = C.c_void_p()
+        on_dev = hasattr(col_off, "is_cuda") and col_off.is_cuda
+        if on_dev:
+            import torch
+            col_off = col_off.to(torch.int64).contiguous()
+            row_idx = row_idx.to(torch.int32).contiguous()
+            w = w.to(torch.float32).contiguous()
+            n, m = col_off.numel() - 1, row_idx.numel()
+            args = [C.c_void_p(col_off.data_ptr()), C.c_void_p(row_idx.data_ptr()),
+                    C.c_void_p(w.data_ptr())]
+        else:
+            col_off = _host(col_off.cpu().numpy() if hasattr(col_off, "cpu") else col_off, np.int64)
+            row_idx = _host(row_idx.cpu().numpy() if hasattr(row_idx, "cpu") else row_idx, np.int32)
+            w = _host(w.cpu().numpy() if hasattr(w, "cpu") else w, np.float32)
+            n, m = col_off.shape[0] - 1, row_idx.shape[0]
+            args = [_hptr(col_off), _hptr(row_idx), _hptr(w)]
+        _check(lib().sia_graph_create(n, m, *args, 1 if on_dev else 0, _stream(stream),
+                                      C.byref(self._h)))
+        self.n, self.m = n, m
+
+    def close(self):
+        if self._h:
+            _check(lib().sia_graph_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def thresholds(self, stream=None):
+        thr = np.zeros(self.m, dtype=np.uint32)
+        _check(lib().sia_graph_thresholds(self._h, _hptr(thr), _stream(stream)))
+        return thr
+
+
+class Walks:
+    """Kept walks in CSR form (sorted by attempt id) plus the run's counters."""
+
+    def __init__(self, attempt, off, ids, stats):
+        self.attempt, self.off, self.ids, self.stats = attempt, off, ids, stats
+
+    @property
+    def n_walks(self):
+        return self.attempt.shape[0]
+
+    def walk(self, i):
+        return self.ids[int(self.off[i]):int(self.off[i + 1])]
+
+
+def sample(graph: Graph, sources, mode, n_attempts, attempt_offset=0, seed=2017, stream=None):
+    src = _host(sources, np.int32)
+    w = _Walks()
+    L = lib()
+    _check(L.sia_sample(graph.handle, MODES[mode], _hptr(src), src.shape[0], n_attempts,
+                        attempt_offset, seed, C.byref(w), _stream(stream)))
+    try:
+        nw, ni = int(w.n_walks), int(w.n_ids)
+        attempt = np.ctypeslib.as_array(w.attempt, (nw,)).copy() if nw else np.zeros(0, np.uint64)
+        off = np.ctypeslib.as_array(w.off, (nw + 1,)).copy()
+        ids = np.ctypeslib.as_array(w.ids, (ni,)).copy() if ni else np.zeros(0, np.uint32)
+        return Walks(attempt, off, ids, w.stats.as_dict())
+    finally:
+        L.sia_walks_free(C.byref(w))
+
+
+def greedy(id_space, walk_off, ids, k, stream=None):
+    off = _host(walk_off, np.uint64)
+    ids = _host(ids, np.uint32)
+    sel = np.zeros(k, dtype=np.int64)
+    gains = np.zeros(k, dtype=np.uint64)
+    _check(lib().sia_greedy(id_space, _hptr(off), _hptr(ids), off.shape[0] - 1, k, _hptr(sel),
+                            _hptr(gains), _stream(stream)))
+    return sel, gains
+
+
+def solve(graph: Graph, sources, mode, k, n_attempts, attempt_offset=0, seed=2017, timing=False,
+          stream=None):
+    src = _host(sources, np.int32)
+    sel = np.zeros(k, dtype=np.int64)
+    gains = np.zeros(k, dtype=np.uint64)
+    st = Stats()
+    _check(lib().sia_solve(graph.handle, MODES[mode], _hptr(src), src.shape[0], k, n_attempts,
+                           attempt_offset, seed, _hptr(sel), _hptr(gains), C.byref(st),
+                           1 if timing else 0, _stream(stream)))
+    return dict(selected=sel, gains=gains, stats=st.as_dict())
+
+
+def quantize(w_dev, q_dev, stream=None):
+    """Device conversion q = round-half-even(w * 2^32) (test hook)."""
+    _check(lib().sia_quantize(C.c_void_p(w_dev.data_ptr()), C.c_void_p(q_dev.data_ptr()),
+                              w_dev.numel(), _stream(stream)))
+
+
+def version():
+    return lib().sia_version().decode()

@@ -1,0 +1,86 @@
+"""The C ABI library loads, exports every declared symbol, and its host-side
+argument checks answer without a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1702_05854_amd import sia
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sia.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(sia.LIB_PATH):
+        from paper_1702_05854_amd import build
+        build.build()
+    return sia.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sia_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for n in ("sia_graph_create", "sia_graph_destroy", "sia_sample", "sia_greedy", "sia_solve",
+              "sia_last_error", "sia_check_query", "sia_graph_thresholds"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert L.sia_version().decode().startswith("sia")
+
+
+def test_check_query_rejects_bad_arguments(L):
+    src = [1, 5, 9]
+    ok = dict(n=100, m=500, mode="edges", sources=src, k=10, n_attempts=1000, attempt_offset=0)
+    sia.check_query(**ok)
+    sia.check_query(**{**ok, "k": 0})                 # sampling-only queries
+    bad = [
+        {"n": 1}, {"n": 1 << 31}, {"m": -1}, {"sources": [1, 1]}, {"sources": [100]},
+        {"sources": [-1]}, {"sources": list(range(100))}, {"k": 501}, {"mode": "nodes", "k": 101},
+        {"n_attempts": 0}, {"n_attempts": 1 << 32}, {"attempt_offset": (1 << 64) - 10},
+    ]
+    for b in bad:
+        with pytest.raises(sia.SiaError) as e:
+            sia.check_query(**{**ok, **b})
+        assert e.value.status == -1, b
+        assert L.sia_last_error().decode() != ""
+
+
+def test_graph_create_rejects_bad_structure_on_host(L):
+    h = C.c_void_p()
+    def create(col, row, w, n=None):
+        col = np.asarray(col, np.int64)
+        row = np.asarray(row, np.int32)
+        w = np.asarray(w, np.float32)
+        n = len(col) - 1 if n is None else n
+        return L.sia_graph_create(n, len(row), col.ctypes.data_as(C.c_void_p),
+                                  row.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p),
+                                  0, None, C.byref(h))
+    assert create([1, 1, 2], [0, 1], [0.5, 0.5]) == -1       # col_off[0] != 0
+    assert create([0, 2, 1], [0, 1], [0.5, 0.5]) == -1       # decreasing
+    assert create([0, 1, 1], [0, 1], [0.5, 0.5]) == -1       # col_off[n] != m
+    assert create([0, 1, 2], [0, 7], [0.5, 0.5]) == -1       # row out of range
+    assert create([0, 1], [0], [0.5], n=1) == -1             # n < 2
+    assert L.sia_graph_create(3, 0, None, None, None, 0, None, C.byref(h)) == -1
+    assert not h.value
+    assert "row_idx" in L.sia_last_error().decode() or L.sia_last_error()
+
+
+def test_greedy_rejects_bad_arguments(L):
+    off = np.array([0, 2], np.uint64)
+    ids = np.array([0, 9], np.uint32)
+    with pytest.raises(sia.SiaError):
+        sia.greedy(5, off, ids, 2, stream=0)                       # id 9 outside [0, 5)
+    with pytest.raises(sia.SiaError):
+        sia.greedy(10, off, ids, 11, stream=0)                     # k > id_space

@@ -1,0 +1,245 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle,
+element by element (bit-exact: all quantities are integers)."""
+import numpy as np
+import pytest
+
+from oracle import cpu
+from tiny import catalogue, csc_from_edges, random_tiny
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CAT = catalogue()
+SEED = 2017
+
+
+@pytest.fixture(scope="module")
+def sia():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_05854_amd import sia as _sia
+    _sia.lib()
+    return _sia
+
+
+def omode(mode):
+    return cpu.MODE_EDGES if mode == "edges" else cpu.MODE_NODES
+
+
+def assert_walks_equal(got, ref, label):
+    assert got.stats["hits"] == ref.hits, label
+    assert got.stats["dead_ends"] == ref.dead_ends, label
+    assert got.stats["cycles"] == ref.cycles, label
+    assert got.stats["steps"] == ref.steps, label
+    assert got.stats["evaluations"] >= got.stats["steps"], label
+    assert np.array_equal(got.attempt, ref.attempt), label
+    assert np.array_equal(got.off, ref.off), label
+    assert np.array_equal(got.ids, ref.ids), label
+
+
+# ------------------------------------------------------------------ ingest
+@pytest.mark.parametrize("case", CAT, ids=[c[0] for c in CAT])
+def test_thresholds_match_oracle(sia, case):
+    name, n, edges, src = case
+    col, row, w = csc_from_edges(n, edges)
+    g = sia.Graph(col, row, w)
+    assert np.array_equal(g.thresholds(), cpu.Graph(col, row, w).thr), name
+    gd = sia.Graph(torch.from_numpy(col).cuda(), torch.from_numpy(row).cuda(),
+                   torch.from_numpy(w).cuda())
+    assert np.array_equal(gd.thresholds(), cpu.Graph(col, row, w).thr), name
+
+
+def test_thresholds_big_columns_and_device_inputs(sia):
+    # one column above the one-workgroup threshold, plus ragged small ones
+    rng = np.random.default_rng(1)
+    n = 40000
+    degs = rng.integers(0, 5, n)
+    degs[7] = 70_001
+    degs[123] = 16_385
+    col = np.zeros(n + 1, np.int64)
+    col[1:] = np.cumsum(degs)
+    m = int(col[-1])
+    row = rng.integers(0, n, m).astype(np.int32)
+    w = np.empty(m, np.float32)
+    for v in range(n):
+        d = degs[v]
+        if d:
+            x = rng.uniform(0.01, 1, d)
+            w[col[v]:col[v + 1]] = (x * rng.uniform(0.2, 1.0) / x.sum()).astype(np.float32)
+    ref = cpu.Graph(col, row, w).thr
+    g = sia.Graph(torch.from_numpy(col).cuda(), torch.from_numpy(row).cuda(), torch.from_numpy(w).cuda())
+    assert np.array_equal(g.thresholds(), ref)
+
+
+def test_quantize_exhaustive_all_fp32_in_unit_interval(sia):
+    """Every fp32 value in [0, 1] (bit patterns 0 .. 0x3F800000) converts to
+    the same integer on the device as in the oracle."""
+    end = 0x3F800001
+    chunk = 1 << 26
+    for base in range(0, end, chunk):
+        cnt = min(chunk, end - base)
+        bits = torch.arange(base, base + cnt, dtype=torch.int64, device="cuda").to(torch.int32)
+        wdev = bits.view(torch.float32)
+        qdev = torch.empty(cnt, dtype=torch.int64, device="cuda")
+        sia.quantize(wdev, qdev)
+        torch.cuda.synchronize()
+        got = qdev.cpu().numpy().view(np.uint64)
+        ref = cpu.quantize(wdev.cpu().numpy())
+        assert np.array_equal(got, ref), hex(base)
+
+
+def test_invalid_weights_rejected(sia):
+    col = np.array([0, 2, 3, 3], np.int64)
+    row = np.array([1, 2, 0], np.int32)
+    for w in ([0.7, 0.4, 0.5], [np.nan, 0.1, 0.5], [-0.5, 0.1, 0.5], [0.5, 0.5, 1.5]):
+        with pytest.raises(sia.SiaError) as e:
+            sia.Graph(col, row, np.array(w, np.float32))
+        assert e.value.status == -2
+        with pytest.raises(sia.SiaError) as e:
+            sia.Graph(torch.from_numpy(col).cuda(), torch.from_numpy(row).cuda(),
+                      torch.tensor(w, dtype=torch.float32, device="cuda"))
+        assert e.value.status == -2
+    with pytest.raises(sia.SiaError) as e:
+        sia.Graph(torch.tensor([0, 2, 1, 3], device="cuda"),
+                  torch.tensor([1, 2, 0], dtype=torch.int32, device="cuda"),
+                  torch.tensor([0.1, 0.1, 0.1], device="cuda"))
+    assert e.value.status == -1
+    with pytest.raises(sia.SiaError) as e:
+        sia.Graph(torch.tensor([0, 2, 3, 3], device="cuda"),
+                  torch.tensor([1, 5, 0], dtype=torch.int32, device="cuda"),
+                  torch.tensor([0.1, 0.1, 0.1], device="cuda"))
+    assert e.value.status == -1
+
+
+# ------------------------------------------------------------------ sampler
+@pytest.mark.parametrize("case", CAT, ids=[c[0] for c in CAT])
+@pytest.mark.parametrize("mode", ["edges", "nodes"])
+def test_sample_matches_oracle_tiny(sia, case, mode):
+    name, n, edges, src = case
+    col, row, w = csc_from_edges(n, edges)
+    g = sia.Graph(col, row, w)
+    og = cpu.Graph(col, row, w)
+    for offset, N in ((0, 20_000), (987_654_321_000, 3_333)):
+        got = sia.sample(g, src, mode, N, offset, SEED)
+        ref = og.sample(np.array(src, np.int32), omode(mode), N, offset, SEED)
+        assert_walks_equal(got, ref, (name, mode, offset))
+
+
+@pytest.mark.parametrize("mode", ["edges", "nodes"])
+def test_sample_matches_oracle_random_graphs(sia, mode):
+    for seed in range(20):
+        n = 30 + seed * 7
+        edges = random_tiny(n, 3.0 / n, 500 + seed, "inv" if seed % 2 else "rand", max_deg=6)
+        rng = np.random.default_rng(seed)
+        src = sorted(rng.choice(n, size=1 + seed % 4, replace=False).tolist())
+        col, row, w = csc_from_edges(n, edges)
+        g = sia.Graph(col, row, w)
+        og = cpu.Graph(col, row, w)
+        N = 5000 + 37 * seed
+        got = sia.sample(g, src, mode, N, seed * 1000, SEED + seed)
+        ref = og.sample(np.array(src, np.int32), omode(mode), N, seed * 1000, SEED + seed)
+        assert_walks_equal(got, ref, (seed, mode))
+
+
+def test_sample_er1k_full(sia):
+    from paper_1702_05854_amd import workloads
+    wl = workloads.load("er1k")
+    col, row, w = wl.host()
+    g = sia.Graph(wl.col_off.cuda(), wl.row_idx.cuda(), wl.w.cuda())
+    og = cpu.Graph(col, row, w)
+    for mode in ("edges", "nodes"):
+        got = sia.sample(g, wl.sources, mode, wl.n_attempts, 0, wl.seed)
+        ref = og.sample(wl.sources, omode(mode), wl.n_attempts, 0, wl.seed)
+        assert_walks_equal(got, ref, mode)
+
+
+def test_sample_split_equals_whole(sia):
+    from paper_1702_05854_amd import workloads
+    wl = workloads.load("er1k")
+    g = sia.Graph(*wl.host())
+    whole = sia.sample(g, wl.sources, "edges", 50_000, 100, 7)
+    a = sia.sample(g, wl.sources, "edges", 20_001, 100, 7)
+    b = sia.sample(g, wl.sources, "edges", 29_999, 20_101, 7)
+    assert np.array_equal(whole.attempt, np.concatenate([a.attempt, b.attempt]))
+    assert np.array_equal(whole.ids, np.concatenate([a.ids, b.ids]))
+    for key in ("hits", "dead_ends", "cycles", "steps"):
+        assert whole.stats[key] == a.stats[key] + b.stats[key]
+
+
+# ------------------------------------------------------------------ greedy
+@pytest.mark.parametrize("seed", range(6))
+def test_greedy_matches_oracle(sia, seed):
+    rng = np.random.default_rng(seed)
+    id_space = [7, 1000, 1025, 70_000, 1_048_577, 3_000_000][seed]
+    n_walks = [50, 3000, 4000, 20_000, 50_000, 100_000][seed]
+    hot = rng.integers(0, id_space, 64)
+    walks = []
+    for i in range(n_walks):
+        L = min(int(rng.integers(1, 12)), id_space)
+        pool = np.unique(np.concatenate([hot[: L // 2], rng.integers(0, id_space, L)]))
+        if pool.shape[0] < L:
+            pool = rng.choice(id_space, L, replace=False)
+        u = rng.permutation(pool)[:L]
+        walks.append(u.astype(np.uint32))
+    off = np.zeros(n_walks + 1, np.uint64)
+    off[1:] = np.cumsum([w.shape[0] for w in walks])
+    ids = np.concatenate(walks)
+    k = min(id_space, [7, 50, 200, 300, 100, 1000][seed])
+    got_sel, got_gain = sia.greedy(id_space, off, ids, k)
+    ref_sel, ref_gain = cpu.greedy_csr(id_space, off, ids, k)
+    assert np.array_equal(got_sel, ref_sel)
+    assert np.array_equal(got_gain, ref_gain)
+
+
+def test_greedy_empty_and_exhaustive(sia):
+    sel, gains = sia.greedy(5, np.zeros(1, np.uint64), np.zeros(0, np.uint32), 5)
+    assert sel.tolist() == [0, 1, 2, 3, 4] and gains.tolist() == [0] * 5
+    off = np.array([0, 2, 3], np.uint64)
+    ids = np.array([1, 2, 3], np.uint32)
+    sel, gains = sia.greedy(6, off, ids, 6)
+    assert sel.tolist() == [1, 3, 0, 2, 4, 5] and gains.tolist() == [1, 1, 0, 0, 0, 0]
+
+
+# ------------------------------------------------------------------ solve
+@pytest.mark.parametrize("mode", ["edges", "nodes"])
+def test_solve_er1k_matches_oracle(sia, mode):
+    from paper_1702_05854_amd import workloads
+    wl = workloads.load("er1k")
+    col, row, w = wl.host()
+    g = sia.Graph(wl.col_off.cuda(), wl.row_idx.cuda(), wl.w.cuda())
+    og = cpu.Graph(col, row, w)
+    got = sia.solve(g, wl.sources, mode, wl.k, wl.n_attempts, 0, wl.seed, timing=True)
+    ref = cpu.solve(og, wl.sources, omode(mode), wl.k, wl.n_attempts, 0, wl.seed)
+    assert np.array_equal(got["selected"], ref["selected"])
+    assert np.array_equal(got["gains"], ref["gains"])
+    st = got["stats"]
+    assert st["covered"] == ref["covered"]
+    assert st["hits"] == ref["walks"].hits and st["steps"] == ref["walks"].steps
+    assert st["spread_est"] == ref["spread"]
+    assert st["suspension_est"] == ref["suspension"]
+    assert st["suspension_nodes_est"] == ref["suspension_nodes"]
+    assert st["ms_sample"] > 0 and st["ms_total"] >= st["ms_sample"]
+
+
+def test_solve_edge_cases(sia):
+    # every non-source but one is a source; k = id space; N = 1
+    col, row, w = csc_from_edges(4, [(1, 0, 0.3), (2, 0, 0.3), (3, 0, 0.4)])
+    g = sia.Graph(col, row, w)
+    og = cpu.Graph(col, row, w)
+    for mode, k in (("edges", 3), ("nodes", 4)):
+        for N in (1, 2, 1000):
+            got = sia.solve(g, [1, 2, 3], mode, k, N, 5, 11)
+            ref = cpu.solve(og, [1, 2, 3], omode(mode), k, N, 5, 11)
+            assert np.array_equal(got["selected"], ref["selected"]), (mode, N)
+            assert np.array_equal(got["gains"], ref["gains"]), (mode, N)
+    # all weights zero: every attempt is a dead end after one draw
+    col, row, w = csc_from_edges(5, [(1, 0, 0.0), (2, 1, 0.0), (0, 2, 0.0)])
+    g = sia.Graph(col, row, w)
+    got = sia.solve(g, [4], "edges", 3, 10_000, 0, 3)
+    assert got["stats"]["dead_ends"] == 10_000 == got["stats"]["steps"]
+    assert got["selected"].tolist() == [0, 1, 2] and got["gains"].tolist() == [0, 0, 0]
+    # graph without edges
+    g = sia.Graph(np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    got = sia.solve(g, [0], "nodes", 2, 1000, 0, 3)
+    assert got["stats"]["dead_ends"] == 1000 and got["selected"].tolist() == [0, 1]
