@@ -8,12 +8,16 @@
 //              selected, so the largest key is the largest marginal gain with
 //              the lowest id on ties, and zero-gain rounds take the lowest
 //              id not selected yet;
-//   lvl1/lvl2 = maxima of key over 1024 ids / 1024 lvl1 entries.
+//   L1/L2/L3 = maxima of key over 64 ids / 64 L1 entries / 64 L2 entries.
 //
-// Each round: pick = max over lvl2 (one workgroup), cover = the picked id's
-// uncovered walks are marked and their ids' counts decremented (the dirty
-// lvl1 blocks are queued), then only the dirty lvl1 / lvl2 maxima are
-// recomputed.  All state stays in HBM; the host only launches.
+// Each round is four kernels.  pick+cover: every workgroup reads L3 and
+// derives the same pick; workgroup 0 records it; all waves then take the
+// picked id's walks (one wave per walk), mark the uncovered ones and
+// decrement the counts of their ids, queueing each touched L1 block once.
+// Then one refresh kernel per level: one wave per queued block recomputes its
+// maximum and queues the parent block once.  Kernel boundaries order the
+// phases (and make the writes of one phase visible to every XCD in the
+// next); nothing is read back until the last round.
 #include "common.hpp"
 
 #include <algorithm>
@@ -23,17 +27,15 @@ namespace sia {
 namespace {
 
 constexpr int kWave = 64;
-constexpr uint32_t kL1 = 1024;  // ids per level-1 block
-constexpr uint32_t kL2 = 1024;  // level-1 blocks per level-2 block
 constexpr uint32_t kSelected = 0xFFFFFFFFu;
 constexpr uint32_t kScanTile = 4096;  // 256 threads x 16
 
 struct GreedyState {
-    uint32_t cur_id;
-    uint32_t cur_gain;
-    uint32_t n_dirty1;
-    uint32_t n_dirty2;
+    uint32_t n_queued[3][2];  // queued blocks per level, by round parity
+    uint32_t error;
 };
+
+constexpr uint32_t kB = 64;  // fan-in of every level
 
 __device__ __forceinline__ uint64_t key_of(uint32_t c, uint32_t id)
 {
@@ -128,138 +130,136 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t *in, uint64_t 
 }
 
 // ---- inverted index: cur[id] counts down from the inclusive prefix sum to
-// the start of id's list; walk w is listed under each of its ids.
-__global__ void k_fill(const uint64_t *walk_off, const uint32_t *walk_len, uint64_t n_walks,
-                       const uint32_t *ids, uint32_t *cur, uint32_t *inv)
+// the start of id's list; walk w is listed under each of its ids.  One wave
+// per walk.
+__global__ __launch_bounds__(256) void k_fill(const uint64_t *walk_off, const uint32_t *walk_len,
+                                              uint64_t n_walks, const uint32_t *ids, uint32_t *cur,
+                                              uint32_t *inv)
 {
-    uint64_t w = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (; w < n_walks; w += stride) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
+    for (uint64_t w = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
+         w < n_walks; w += waves) {
         const uint64_t o = walk_off[w];
         const uint32_t L = walk_len[w];
-        for (uint32_t e = 0; e < L; ++e) {
+        for (uint32_t e = lane; e < L; e += kWave) {
             const uint32_t p = atomicSub(&cur[ids[o + e]], 1u) - 1u;
             inv[p] = static_cast<uint32_t>(w);
         }
     }
 }
 
-// ---- level maxima: one wave per block
-__global__ __launch_bounds__(256) void k_lvl1(const uint32_t *cnt, uint64_t id_space, uint64_t n1,
-                                              const uint32_t *list, const GreedyState *st,
-                                              uint64_t *lvl1, uint32_t *flag1, uint32_t *flag2,
-                                              uint32_t *dirty2, GreedyState *st_out)
+// ---- full build of one level: out[i] = max over in[i*64 .. i*64+63]
+// (level 1 reads keys of the counts directly).
+__global__ __launch_bounds__(256) void k_build_level(const uint32_t *cnt, const uint64_t *in,
+                                                     uint64_t n_in, uint64_t *out, uint64_t n_out)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
-    const uint64_t todo = list ? st->n_dirty1 : n1;
     for (uint64_t i = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
-         i < todo; i += waves) {
-        const uint64_t b = list ? list[i] : i;
-        uint64_t best = 0;
-        for (uint32_t k = lane; k < kL1; k += kWave) {
-            const uint64_t id = b * kL1 + k;
-            if (id < id_space) {
-                const uint64_t key = key_of(cnt[id], static_cast<uint32_t>(id));
-                best = key > best ? key : best;
-            }
-        }
-        best = wave_max_u64(best);
-        if (lane == 0) {
-            lvl1[b] = best;
-            if (list) {
-                flag1[b] = 0;
-                const uint32_t p = static_cast<uint32_t>(b / kL2);
-                if (atomicExch(&flag2[p], 1u) == 0u)
-                    dirty2[atomicAdd(&st_out->n_dirty2, 1u)] = p;
-            }
-        }
+         i < n_out; i += waves) {
+        const uint64_t c = i * kB + lane;
+        uint64_t v = 0;
+        if (c < n_in) v = cnt ? key_of(cnt[c], static_cast<uint32_t>(c)) : in[c];
+        v = wave_max_u64(v);
+        if (lane == 0) out[i] = v;
     }
 }
 
-__global__ __launch_bounds__(256) void k_lvl2(const uint64_t *lvl1, uint64_t n1, uint64_t n2,
-                                              const uint32_t *list, const GreedyState *st,
-                                              uint64_t *lvl2, uint32_t *flag2)
+struct Tree {
+    uint32_t *cnt;
+    uint64_t id_space;
+    uint64_t *lvl[3];    // L1, L2, L3 maxima
+    uint64_t n[3];       // entries per level
+    uint32_t *flag[3];   // block queued this round, per level
+    uint32_t *queue[3];  // two queues per level (round parity), n[l] entries each
+};
+
+__device__ __forceinline__ void enqueue(const Tree &T, GreedyState *st, int level, uint32_t par,
+                                        uint64_t b)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
-    const uint64_t todo = list ? st->n_dirty2 : n2;
-    for (uint64_t i = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
-         i < todo; i += waves) {
-        const uint64_t p = list ? list[i] : i;
-        uint64_t best = 0;
-        for (uint32_t k = lane; k < kL2; k += kWave) {
-            const uint64_t b = p * kL2 + k;
-            if (b < n1) best = lvl1[b] > best ? lvl1[b] : best;
-        }
-        best = wave_max_u64(best);
-        if (lane == 0) {
-            lvl2[p] = best;
-            if (list) flag2[p] = 0;
-        }
-    }
+    if (T.flag[level][b] == 0u && atomicExch(&T.flag[level][b], 1u) == 0u)
+        T.queue[level][par * T.n[level] + atomicAdd(&st->n_queued[level][par], 1u)] =
+            static_cast<uint32_t>(b);
 }
 
-// ---- one greedy round
-__global__ __launch_bounds__(1024) void k_pick(const uint64_t *lvl2, uint64_t n2, uint32_t *cnt,
-                                               uint32_t *flag1, uint32_t *dirty1, int64_t round,
-                                               int64_t *sel, uint64_t *gain, GreedyState *st)
+__global__ __launch_bounds__(256) void k_pick_cover(Tree T, GreedyState *st, int64_t round,
+                                                    int64_t *sel, uint64_t *gain, const uint32_t *cur,
+                                                    const uint32_t *inv, const uint64_t *walk_off,
+                                                    const uint32_t *walk_len, const uint32_t *ids,
+                                                    uint32_t *covered)
 {
-    __shared__ uint64_t sh[16];
+    __shared__ uint64_t sh[4];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const uint32_t par = static_cast<uint32_t>(round & 1);
+    // every workgroup derives the same pick from L3
     uint64_t best = 0;
-    for (uint64_t i = threadIdx.x; i < n2; i += blockDim.x) best = lvl2[i] > best ? lvl2[i] : best;
+    const uint64_t *l3 = T.lvl[2];
+    for (uint64_t i = threadIdx.x; i < T.n[2]; i += blockDim.x) best = l3[i] > best ? l3[i] : best;
     best = wave_max_u64(best);
-    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = best;
+    if (lane == 0) sh[wid] = best;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < static_cast<int>(blockDim.x / kWave); ++k) best = sh[k] > best ? sh[k] : best;
-        best = sh[0] > best ? sh[0] : best;
-        if (best == 0) {  // unreachable while rounds < id space; never index with it
-            st->cur_gain = 0;
-            st->n_dirty1 = 0;
-            st->n_dirty2 = 0;
+    best = sh[0];
+    for (int k = 1; k < 4; ++k) best = sh[k] > best ? sh[k] : best;
+    if (best == 0) {  // unreachable while rounds < id space; never index with it
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->error = 1;
             sel[round] = -1;
             gain[round] = 0;
-            return;
         }
-        const uint32_t id = 0xFFFFFFFFu - static_cast<uint32_t>(best);
-        const uint32_t g = static_cast<uint32_t>(best >> 32) - 1u;
+        return;
+    }
+    const uint32_t id = 0xFFFFFFFFu - static_cast<uint32_t>(best);
+    const uint32_t g = static_cast<uint32_t>(best >> 32) - 1u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         sel[round] = id;
         gain[round] = g;
-        st->cur_id = id;
-        st->cur_gain = g;
-        cnt[id] = kSelected;
-        const uint32_t b = id / kL1;
-        flag1[b] = 1;
-        dirty1[0] = b;
-        st->n_dirty1 = 1;
-        st->n_dirty2 = 0;
+        T.cnt[id] = kSelected;
+        enqueue(T, st, 0, par, id / kB);
+        // the queues of the next round start empty
+        for (int l = 0; l < 3; ++l) st->n_queued[l][par ^ 1u] = 0;
+    }
+    if (g == 0) return;
+    // cover the picked id's walks: one wave per listed walk
+    const uint32_t lo = cur[id], hi = cur[id + 1];
+    const uint32_t gw = blockIdx.x * (blockDim.x / kWave) + wid;
+    const uint32_t nw = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t p = lo + gw; p < hi; p += nw) {
+        const uint32_t w = inv[p];
+        uint32_t old = 1;
+        if (lane == 0) old = atomicExch(&covered[w], 1u);
+        old = __shfl(old, 0, kWave);
+        if (old != 0u) continue;
+        const uint64_t o = walk_off[w];
+        const uint32_t L = walk_len[w];
+        for (uint32_t e = lane; e < L; e += kWave) {
+            const uint32_t x = ids[o + e];
+            if (x == id) continue;
+            atomicSub(&T.cnt[x], 1u);
+            enqueue(T, st, 0, par, x / kB);
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void k_cover(const GreedyState *st_in, const uint32_t *cur,
-                                               const uint32_t *inv, const uint64_t *walk_off,
-                                               const uint32_t *walk_len, const uint32_t *ids,
-                                               uint32_t *covered, uint32_t *cnt, uint32_t *flag1,
-                                               uint32_t *dirty1, GreedyState *st)
+// Recompute the queued blocks of one level; queue their parents.
+__global__ __launch_bounds__(256) void k_refresh(Tree T, GreedyState *st, int64_t round, int level)
 {
-    if (st_in->cur_gain == 0) return;
-    const uint32_t id = st_in->cur_id;
-    const uint32_t lo = cur[id], hi = cur[id + 1];
-    uint32_t p = lo + blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (; p < hi; p += stride) {
-        const uint32_t w = inv[p];
-        if (atomicExch(&covered[w], 1u) != 0u) continue;
-        const uint64_t o = walk_off[w];
-        const uint32_t L = walk_len[w];
-        for (uint32_t e = 0; e < L; ++e) {
-            const uint32_t x = ids[o + e];
-            if (x == id) continue;
-            atomicSub(&cnt[x], 1u);
-            const uint32_t b = x / kL1;
-            if (flag1[b] == 0u && atomicExch(&flag1[b], 1u) == 0u)
-                dirty1[atomicAdd(&st->n_dirty1, 1u)] = b;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t par = static_cast<uint32_t>(round & 1);
+    const uint32_t todo = st->n_queued[level][par];
+    const uint32_t waves = (gridDim.x * blockDim.x) / kWave;
+    const uint64_t n_in = level == 0 ? T.id_space : T.n[level - 1];
+    const uint64_t *in = level == 0 ? nullptr : T.lvl[level - 1];
+    for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < todo; i += waves) {
+        const uint64_t b = T.queue[level][par * T.n[level] + i];
+        const uint64_t c = b * kB + lane;
+        uint64_t v = 0;
+        if (c < n_in) v = level == 0 ? key_of(T.cnt[c], static_cast<uint32_t>(c)) : in[c];
+        v = wave_max_u64(v);
+        if (lane == 0) {
+            T.lvl[level][b] = v;
+            T.flag[level][b] = 0u;
+            if (level < 2) enqueue(T, st, level + 1, par, b / kB);
         }
     }
 }
@@ -279,7 +279,7 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
     SIA_REQUIRE(n_ids < 0xFFFFFFFFull && n_walks < 0xFFFFFFFFull, SIA_EINVAL,
                 "too many walk ids for 32-bit inverted index offsets");
     const uint64_t S = static_cast<uint64_t>(id_space);
-    const uint64_t n1 = (S + kL1 - 1) / kL1, n2 = (n1 + kL2 - 1) / kL2;
+    const uint64_t n1 = (S + kB - 1) / kB, n2 = (n1 + kB - 1) / kB, n3 = (n2 + kB - 1) / kB;
     const uint64_t n_tiles = (S + kScanTile - 1) / kScanTile;
     const int cus = device_cu_count();
 
@@ -287,12 +287,9 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
     ws.cur.ensure(sizeof(uint32_t) * (S + 1));
     ws.inv.ensure(sizeof(uint32_t) * std::max<uint64_t>(n_ids, 1));
     ws.covered.ensure(sizeof(uint32_t) * std::max<uint64_t>(n_walks, 1));
-    ws.lvl1.ensure(sizeof(uint64_t) * n1);
-    ws.lvl2.ensure(sizeof(uint64_t) * n2);
-    ws.flag1.ensure(sizeof(uint32_t) * n1);
-    ws.flag2.ensure(sizeof(uint32_t) * n2);
-    ws.dirty1.ensure(sizeof(uint32_t) * n1);
-    ws.dirty2.ensure(sizeof(uint32_t) * n2);
+    ws.lvl1.ensure(sizeof(uint64_t) * (n1 + n2 + n3));
+    ws.flag1.ensure(sizeof(uint32_t) * (n1 + n2 + n3));
+    ws.dirty1.ensure(sizeof(uint32_t) * 2 * (n1 + n2 + n3));
     ws.sel.ensure(sizeof(int64_t) * k);
     ws.gain.ensure(sizeof(uint64_t) * k);
     ws.scan_tmp.ensure(sizeof(uint32_t) * n_tiles + sizeof(GreedyState) + 64);
@@ -300,7 +297,21 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
     GreedyState *st = reinterpret_cast<GreedyState *>(
         ws.scan_tmp.as<char>() + ((sizeof(uint32_t) * n_tiles + 63) / 64) * 64);
 
-    uint32_t *cnt = ws.cnt.as<uint32_t>(), *cur = ws.cur.as<uint32_t>();
+    Tree T;
+    T.cnt = ws.cnt.as<uint32_t>();
+    T.id_space = S;
+    T.n[0] = n1;
+    T.n[1] = n2;
+    T.n[2] = n3;
+    T.lvl[0] = ws.lvl1.as<uint64_t>();
+    T.flag[0] = ws.flag1.as<uint32_t>();
+    T.queue[0] = ws.dirty1.as<uint32_t>();
+    for (int l = 1; l < 3; ++l) {
+        T.lvl[l] = T.lvl[l - 1] + T.n[l - 1];
+        T.flag[l] = T.flag[l - 1] + T.n[l - 1];
+        T.queue[l] = T.queue[l - 1] + 2 * T.n[l - 1];
+    }
+    uint32_t *cnt = T.cnt, *cur = ws.cur.as<uint32_t>();
     const uint32_t *ids = ws.ids.as<uint32_t>();
 
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -322,47 +333,41 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
     SIA_HIP(hipGetLastError());
     SIA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(cur + S), static_cast<int>(n_ids), 1, s));
     if (n_walks) {
-        hipLaunchKernelGGL(k_fill, dim3(grid_for(n_walks, 256, cus * 32)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(n_walks * kWave, 256, cus * 32)), dim3(256), 0, s,
                            ws.walk_off.as<uint64_t>(), ws.walk_len.as<uint32_t>(), n_walks, ids,
                            cur, ws.inv.as<uint32_t>());
         SIA_HIP(hipGetLastError());
     }
     // greedy state
     SIA_HIP(hipMemsetAsync(ws.covered.ptr, 0, sizeof(uint32_t) * std::max<uint64_t>(n_walks, 1), s));
-    SIA_HIP(hipMemsetAsync(ws.flag1.ptr, 0, sizeof(uint32_t) * n1, s));
-    SIA_HIP(hipMemsetAsync(ws.flag2.ptr, 0, sizeof(uint32_t) * n2, s));
-    hipLaunchKernelGGL(k_lvl1, dim3(grid_for(n1 * kWave, 256, cus * 16)), dim3(256), 0, s, cnt, S,
-                       n1, nullptr, st, ws.lvl1.as<uint64_t>(), ws.flag1.as<uint32_t>(),
-                       ws.flag2.as<uint32_t>(), ws.dirty2.as<uint32_t>(), st);
-    hipLaunchKernelGGL(k_lvl2, dim3(grid_for(n2 * kWave, 256, cus * 16)), dim3(256), 0, s,
-                       ws.lvl1.as<uint64_t>(), n1, n2, nullptr, st, ws.lvl2.as<uint64_t>(),
-                       ws.flag2.as<uint32_t>());
+    SIA_HIP(hipMemsetAsync(ws.flag1.ptr, 0, sizeof(uint32_t) * (n1 + n2 + n3), s));
+    SIA_HIP(hipMemsetAsync(st, 0, sizeof(GreedyState), s));
+    hipLaunchKernelGGL(k_build_level, dim3(grid_for(n1 * kWave, 256, cus * 32)), dim3(256), 0, s,
+                       cnt, nullptr, S, T.lvl[0], n1);
+    hipLaunchKernelGGL(k_build_level, dim3(grid_for(n2 * kWave, 256, cus * 32)), dim3(256), 0, s,
+                       nullptr, T.lvl[0], n1, T.lvl[1], n2);
+    hipLaunchKernelGGL(k_build_level, dim3(grid_for(n3 * kWave, 256, cus * 32)), dim3(256), 0, s,
+                       nullptr, T.lvl[1], n2, T.lvl[2], n3);
     SIA_HIP(hipGetLastError());
     if (timing) SIA_HIP(hipEventRecord(ev[1], s));
 
-    const unsigned cover_grid = static_cast<unsigned>(cus * 2);
-    const unsigned lvl_grid = static_cast<unsigned>(cus);
+    const unsigned grid = static_cast<unsigned>(cus * 2);
     for (int64_t r = 0; r < k; ++r) {
-        hipLaunchKernelGGL(k_pick, dim3(1), dim3(1024), 0, s, ws.lvl2.as<uint64_t>(), n2, cnt,
-                           ws.flag1.as<uint32_t>(), ws.dirty1.as<uint32_t>(), r,
-                           ws.sel.as<int64_t>(), ws.gain.as<uint64_t>(), st);
-        hipLaunchKernelGGL(k_cover, dim3(cover_grid), dim3(256), 0, s, st, cur,
+        hipLaunchKernelGGL(k_pick_cover, dim3(grid), dim3(256), 0, s, T, st, r,
+                           ws.sel.as<int64_t>(), ws.gain.as<uint64_t>(), cur,
                            ws.inv.as<uint32_t>(), ws.walk_off.as<uint64_t>(),
-                           ws.walk_len.as<uint32_t>(), ids, ws.covered.as<uint32_t>(), cnt,
-                           ws.flag1.as<uint32_t>(), ws.dirty1.as<uint32_t>(), st);
-        hipLaunchKernelGGL(k_lvl1, dim3(lvl_grid), dim3(256), 0, s, cnt, S, n1,
-                           ws.dirty1.as<uint32_t>(), st, ws.lvl1.as<uint64_t>(),
-                           ws.flag1.as<uint32_t>(), ws.flag2.as<uint32_t>(),
-                           ws.dirty2.as<uint32_t>(), st);
-        hipLaunchKernelGGL(k_lvl2, dim3(lvl_grid), dim3(256), 0, s, ws.lvl1.as<uint64_t>(), n1,
-                           n2, ws.dirty2.as<uint32_t>(), st, ws.lvl2.as<uint64_t>(),
-                           ws.flag2.as<uint32_t>());
+                           ws.walk_len.as<uint32_t>(), ids, ws.covered.as<uint32_t>());
+        for (int l = 0; l < 3; ++l)
+            hipLaunchKernelGGL(k_refresh, dim3(l == 0 ? grid : cus), dim3(256), 0, s, T, st, r, l);
     }
     SIA_HIP(hipGetLastError());
     if (timing) SIA_HIP(hipEventRecord(ev[2], s));
+    GreedyState hst;
     SIA_HIP(hipMemcpyAsync(selected, ws.sel.ptr, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
     SIA_HIP(hipMemcpyAsync(gains, ws.gain.ptr, sizeof(uint64_t) * k, hipMemcpyDeviceToHost, s));
+    SIA_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
     SIA_HIP(hipStreamSynchronize(s));
+    SIA_REQUIRE(hst.error == 0, SIA_EDEVICE, "greedy state inconsistent");
     for (int64_t i = 0; i < k; ++i)
         SIA_REQUIRE(selected[i] >= 0, SIA_EDEVICE, "greedy state inconsistent");
     GreedyResult res;

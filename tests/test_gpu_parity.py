@@ -192,6 +192,21 @@ def test_greedy_matches_oracle(sia, seed):
     assert np.array_equal(got_gain, ref_gain)
 
 
+def test_greedy_large_id_space(sia):
+    """id space above 64^3 (more than 64 top-level entries) with a ragged tail."""
+    rng = np.random.default_rng(9)
+    id_space = 20_000_003
+    n_walks = 30_000
+    walks = [np.unique(rng.integers(id_space - 300_000, id_space, rng.integers(1, 9))).astype(np.uint32)
+             for _ in range(n_walks)]
+    off = np.zeros(n_walks + 1, np.uint64)
+    off[1:] = np.cumsum([w.shape[0] for w in walks])
+    ids = np.concatenate(walks)
+    got = sia.greedy(id_space, off, ids, 300)
+    ref = cpu.greedy_csr(id_space, off, ids, 300)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
 def test_greedy_empty_and_exhaustive(sia):
     sel, gains = sia.greedy(5, np.zeros(1, np.uint64), np.zeros(0, np.uint32), 5)
     assert sel.tolist() == [0, 1, 2, 3, 4] and gains.tolist() == [0] * 5
