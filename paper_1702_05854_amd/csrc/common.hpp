@@ -37,12 +37,13 @@ struct Error {
 // ------------------------------------------------------------ device layout
 // One 16-byte record per node: where its in-edges start, how many, the last
 // cumulative threshold (so the dead-end test needs no extra load), and the
-// float scale deg/thr_last used as the first guess of the threshold search.
+// source tag: equal to the running query's tag exactly when the node is one
+// of its sources (so membership comes with the record the walk loads anyway).
 struct NodeRec {
     uint32_t off;
     uint32_t deg;
     uint32_t thr_last;
-    float guess_scale;
+    uint32_t tag;
 };
 static_assert(sizeof(NodeRec) == 16, "NodeRec layout");
 
@@ -81,6 +82,7 @@ struct Workspace {
 struct sia_graph {
     int64_t n = 0, m = 0;
     int device = 0;
+    uint32_t tag = 0;   // tag of the last query that marked its sources
     sia::DevBuf nodes;  // NodeRec[n]
     sia::DevBuf edges;  // EdgeRec[m]
     sia::Workspace ws;
@@ -112,20 +114,24 @@ struct SampleResult {
     float ms = 0.f;
 };
 
-// Upload sources, build bitmap, run the sampler (rerunning with larger
-// buffers if the output did not fit).  Results stay in g->ws.
+// Upload sources, tag them in the node records, run the sampler (rerunning
+// with larger buffers if the output did not fit).  Results stay in g->ws.
+// With count_ids, ws.cnt[id_space] receives the coverage count of every id
+// (number of kept walks holding it).
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
-                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing);
+                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing,
+                         bool count_ids);
 
 struct GreedyResult {
     float ms_count = 0.f, ms_greedy = 0.f;
 };
-// Coverage counts + inverted index + k greedy rounds over the walks held in
-// g->ws (walk_off / walk_len / ids, n_walks walks, n_ids ids).  Writes k
+// Inverted index + k greedy rounds over the walks held in ws (walk_off /
+// walk_len / ids, n_walks walks, n_ids ids).  counts_ready: ws.cnt already
+// holds the coverage counts; otherwise they are counted here.  Writes k
 // selected ids and gains to host arrays.
 GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
                         int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s,
-                        bool timing);
+                        bool timing, bool counts_ready);
 
 // Ingest: host structure checks (no device needed) and the device kernels.
 void host_check_structure(int64_t n, int64_t m, const int64_t *col_off, const int32_t *row_idx);

@@ -274,7 +274,8 @@ unsigned grid_for(uint64_t items, unsigned block, unsigned cap)
 }  // namespace
 
 GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
-                        int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s, bool timing)
+                        int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s, bool timing,
+                        bool counts_ready)
 {
     SIA_REQUIRE(n_ids < 0xFFFFFFFFull && n_walks < 0xFFFFFFFFull, SIA_EINVAL,
                 "too many walk ids for 32-bit inverted index offsets");
@@ -319,9 +320,9 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
         for (auto &e : ev) SIA_HIP(hipEventCreate(&e));
         SIA_HIP(hipEventRecord(ev[0], s));
     }
-    // counts
-    SIA_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * S, s));
-    if (n_ids) {
+    // counts (unless the sampler already produced them)
+    if (!counts_ready) SIA_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * S, s));
+    if (n_ids && !counts_ready) {
         hipLaunchKernelGGL(k_count, dim3(grid_for(n_ids, 256, cus * 64)), dim3(256), 0, s, ids,
                            n_ids, cnt);
         SIA_HIP(hipGetLastError());

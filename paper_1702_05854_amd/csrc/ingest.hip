@@ -3,7 +3,7 @@
 // j = lo..hi-1:  q_j = round-half-even(w_j * 2^32),  thr_j = min(sum of q over
 // lo..j, 2^32 - 1).  Edge j is live with probability (thr_j - thr_{j-1})/2^32.
 //
-// Layout built here (device): NodeRec[n] {off, deg, thr_last, deg/thr_last}
+// Layout built here (device): NodeRec[n] {off, deg, thr_last, source tag 0}
 // and EdgeRec[m] {thr, tail}.  One wave per column (wave-wide uint64 prefix
 // sums); columns above kBigDeg in-edges are finished by one workgroup each.
 #include "common.hpp"
@@ -66,8 +66,7 @@ __device__ __forceinline__ NodeRec make_node(uint64_t lo, uint64_t deg, uint64_t
     r.off = static_cast<uint32_t>(lo);
     r.deg = static_cast<uint32_t>(deg);
     r.thr_last = static_cast<uint32_t>(qsum > 0xFFFFFFFFull ? 0xFFFFFFFFull : qsum);
-    r.guess_scale = (deg && r.thr_last) ? static_cast<float>(deg) / static_cast<float>(r.thr_last)
-                                        : 0.0f;
+    r.tag = 0;
     return r;
 }
 

@@ -15,12 +15,15 @@
 //    (the paper's heuristics had false negatives because its draws depended
 //    on the step, not the node).
 //  * A kept walk is re-walked to emit its ids, so no per-lane path storage
-//    is needed either.
+//    is needed either; coverage counts are incremented as the ids are
+//    written.
 //
 // One lane per attempt; persistent waves refill idle lanes from a global
 // attempt counter in chunks; kept walks are appended with one pair of
-// atomics per wave.  Per evaluation the lane gathers the 16-byte node record
-// and one or two 8-byte edge records (threshold + tail).
+// atomics per wave.  Every iteration a lane computes one Philox block (its
+// start draw, or the draw of the node it evaluates) and, when evaluating,
+// gathers the 16-byte node record (which also carries the source tag) and
+// one or two 8-byte edge records (threshold + tail).
 #include "common.hpp"
 #include "philox.hpp"
 
@@ -33,16 +36,23 @@ namespace {
 constexpr int kWave = 64;
 constexpr uint64_t kChunk = 256;
 
-enum Phase : uint32_t { PH_DETECT = 0, PH_MU_POS = 1, PH_MU_A = 2, PH_MU_B = 3, PH_EMIT = 4 };
+enum Phase : uint32_t {
+    PH_START = 0,   // compute the start node
+    PH_DETECT = 1,  // walk with Brent's cycle detection
+    PH_MU_POS = 2,  // cycle found: advance the second pointer lambda steps
+    PH_MU_A = 3,    // advance the first pointer
+    PH_MU_B = 4,    // advance the second pointer, compare
+    PH_EMIT = 5     // kept walk: re-walk and write its ids
+};
 
 struct SampleArgs {
     const NodeRec *nodes;
     const EdgeRec *edges;
-    const uint32_t *bitmap;   // source membership, n bits
     const uint32_t *src_t;    // t_i = s_i - i over sorted sources
     const uint32_t *bucket;   // bucket[b] = #{i : t_i < b << bucket_shift}
     uint32_t n_src;
     uint32_t bucket_shift;
+    uint32_t tag;             // source tag of this query in NodeRec::tag
     uint64_t n_ns;
     uint64_t seed;
     uint64_t attempt_offset;
@@ -53,6 +63,7 @@ struct SampleArgs {
     uint64_t *walk_off;
     uint32_t *walk_len;
     uint32_t *ids;
+    uint32_t *cnt;            // coverage counts (nullptr: not counted)
     uint64_t walk_cap;
     uint64_t id_cap;
 };
@@ -99,7 +110,8 @@ __device__ __forceinline__ bool select_edge(const EdgeRec *__restrict__ edges, c
                                             uint32_t r, uint32_t &j, uint32_t &u)
 {
     if (R.deg == 0 || r >= R.thr_last) return false;
-    uint32_t g = __float2uint_rz(static_cast<float>(r) * R.guess_scale);
+    const float scale = static_cast<float>(R.deg) * __builtin_amdgcn_rcpf(static_cast<float>(R.thr_last));
+    uint32_t g = __float2uint_rz(static_cast<float>(r) * scale);
     if (g >= R.deg) g = R.deg - 1;
     const uint32_t base = R.off;
     EdgeRec e = edges[base + g];
@@ -138,7 +150,7 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
     // lane state
     bool active = false;
     uint64_t a = 0, out_pos = 0;
-    uint32_t phase = PH_DETECT, x1 = 0, cur = 0, tort = 0, power = 1, lam = 0, t = 0, lambda = 0,
+    uint32_t phase = PH_START, x1 = 0, cur = 0, tort = 0, power = 1, lam = 0, t = 0, lambda = 0,
              cnt = 0, pa = 0, pb = 0;
     uint32_t hits = 0, dead = 0, cycles = 0, faults = 0;
     uint64_t steps = 0, evals = 0;
@@ -165,7 +177,47 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
             const uint32_t rank = lanes_below(idle);
             if (!active && rank < take) {
                 a = A.attempt_offset + chunk_next + rank;
-                const uint64_t idx = __umul64hi(start_draw(A.seed, a), A.n_ns);
+                phase = PH_START;
+                active = true;
+            }
+            chunk_next += take;
+            idle = __ballot(!active);
+        }
+        if (__ballot(active) == 0) break;
+
+        // ---- stage 1: choose this iteration's draw; start draws; load the record
+        bool hit_now = false, do_eval = false;
+        uint32_t y = 0;
+        NodeRec R = {0u, 0u, 0u, 0u};
+        uint64_t word = 0;
+        if (active) {
+            if (phase == PH_DETECT) {
+                y = cur;
+                if (t > 0) {
+                    ++lam;
+                    if (cur == tort) {  // Brent: cycle of length lam (tort is never a source)
+                        lambda = lam;
+                        cnt = lam;
+                        pa = x1;
+                        pb = x1;
+                        phase = PH_MU_POS;
+                        y = pb;
+                    } else if (lam == power) {
+                        tort = cur;
+                        power <<= 1;
+                        lam = 0;
+                    }
+                }
+            } else if (phase == PH_MU_A) {
+                y = pa;
+            } else if (phase == PH_EMIT) {
+                y = cur;
+            } else {
+                y = pb;
+            }
+            word = phase == PH_START ? philox_word0(0, 1, A.seed, a) : philox_word0(y, 0, A.seed, a);
+            if (phase == PH_START) {
+                const uint64_t idx = __umul64hi(word, A.n_ns);
                 uint32_t c = A.bucket[idx >> A.bucket_shift];
                 while (c < A.n_src && A.src_t[c] <= idx) ++c;
                 x1 = static_cast<uint32_t>(idx + c);
@@ -175,52 +227,17 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
                 lam = 0;
                 t = 0;
                 phase = PH_DETECT;
-                active = true;
-            }
-            chunk_next += take;
-            idle = __ballot(!active);
-        }
-        if (__ballot(active) == 0) break;
-
-        // ---- stage 1: per-phase checks, choose the node to evaluate
-        bool hit_now = false, do_eval = false;
-        uint32_t y = 0;
-        if (active) {
-            do_eval = true;
-            if (phase == PH_DETECT) {
-                y = cur;
-                if (t > 0) {
-                    const uint32_t word = A.bitmap[cur >> 5];
-                    if ((word >> (cur & 31u)) & 1u) {
-                        hit_now = true;
-                        do_eval = false;
-                    } else {
-                        ++lam;
-                        if (cur == tort) {  // Brent: cycle of length lam
-                            lambda = lam;
-                            cnt = lam;
-                            pa = x1;
-                            pb = x1;
-                            phase = PH_MU_POS;
-                            do_eval = false;
-                        } else if (lam == power) {
-                            tort = cur;
-                            power <<= 1;
-                            lam = 0;
-                        }
-                    }
-                }
-                if (do_eval && t > A.guard_evals) {  // unreachable for a correct walk
+            } else {
+                R = A.nodes[y];
+                do_eval = true;
+                if (phase == PH_DETECT && t > 0 && R.tag == A.tag) {
+                    hit_now = true;
+                    do_eval = false;
+                } else if (phase == PH_DETECT && t > A.guard_evals) {  // unreachable for a correct walk
                     ++faults;
                     active = false;
                     do_eval = false;
                 }
-            } else if (phase == PH_MU_A) {
-                y = pa;
-            } else if (phase == PH_EMIT) {
-                y = cur;
-            } else {
-                y = pb;
             }
         }
 
@@ -249,7 +266,10 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
                     A.walk_off[widx] = ioff;
                     A.walk_len[widx] = len;
                     out_pos = ioff;
-                    if (MODE == SIA_NODES) A.ids[out_pos++] = x1;
+                    if (MODE == SIA_NODES) {
+                        A.ids[out_pos++] = x1;
+                        if (A.cnt) atomicAdd(&A.cnt[x1], 1u);
+                    }
                     phase = PH_EMIT;
                     cur = x1;
                     cnt = t;
@@ -260,12 +280,10 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
             }
         }
 
-        // ---- stage 3: one live-edge evaluation per lane
+        // ---- stage 3: one live-edge evaluation per evaluating lane
         if (do_eval) {
-            const uint32_t r = node_draw(A.seed, a, y);
-            const NodeRec R = A.nodes[y];
             uint32_t j = 0, u = 0;
-            const bool live = select_edge(A.edges, R, r, j, u);
+            const bool live = select_edge(A.edges, R, static_cast<uint32_t>(word >> 32), j, u);
             ++evals;
             if (phase == PH_DETECT) {
                 ++t;
@@ -307,7 +325,9 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
                     phase = PH_MU_A;
                 }
             } else {  // PH_EMIT
-                A.ids[out_pos++] = (MODE == SIA_EDGES) ? j : u;
+                const uint32_t id = (MODE == SIA_EDGES) ? j : u;
+                A.ids[out_pos++] = id;
+                if (A.cnt) atomicAdd(&A.cnt[id], 1u);
                 cur = u;
                 if (--cnt == 0) active = false;
             }
@@ -332,13 +352,17 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
     }
 }
 
-__global__ void k_mark_sources(const int32_t *src, uint32_t n_src, uint32_t *bitmap)
+__global__ void k_tag_sources(const int32_t *src, uint32_t n_src, NodeRec *nodes, uint32_t tag)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_src) {
-        const uint32_t v = static_cast<uint32_t>(src[i]);
-        atomicOr(&bitmap[v >> 5], 1u << (v & 31u));
-    }
+    if (i < n_src) nodes[src[i]].tag = tag;
+}
+
+__global__ void k_clear_tags(NodeRec *nodes, uint64_t n)
+{
+    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (; i < n; i += stride) nodes[i].tag = 0;
 }
 
 template <int MODE>
@@ -356,16 +380,16 @@ int persistent_blocks()
 }  // namespace
 
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
-                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing)
+                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing,
+                         bool count_ids)
 {
     Workspace &ws = g->ws;
     const uint32_t n_src = static_cast<uint32_t>(st.sorted.size());
-    const uint64_t bitmap_words = (static_cast<uint64_t>(g->n) + 31) / 32;
+    const uint64_t id_space = mode == SIA_EDGES ? static_cast<uint64_t>(g->m) : static_cast<uint64_t>(g->n);
 
     ws.src_sorted.ensure(sizeof(int32_t) * n_src);
     ws.src_t.ensure(sizeof(uint32_t) * n_src);
     ws.bucket.ensure(sizeof(uint32_t) * st.bucket.size());
-    ws.bitmap.ensure(sizeof(uint32_t) * bitmap_words);
     ws.counters.ensure(sizeof(uint64_t) * ST_COUNT);
     SIA_HIP(hipMemcpyAsync(ws.src_sorted.ptr, st.sorted.data(), sizeof(int32_t) * n_src,
                            hipMemcpyHostToDevice, s));
@@ -373,10 +397,17 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
                            hipMemcpyHostToDevice, s));
     SIA_HIP(hipMemcpyAsync(ws.bucket.ptr, st.bucket.data(), sizeof(uint32_t) * st.bucket.size(),
                            hipMemcpyHostToDevice, s));
-    SIA_HIP(hipMemsetAsync(ws.bitmap.ptr, 0, sizeof(uint32_t) * bitmap_words, s));
-    hipLaunchKernelGGL(k_mark_sources, dim3((n_src + 255) / 256), dim3(256), 0, s,
-                       ws.src_sorted.as<int32_t>(), n_src, ws.bitmap.as<uint32_t>());
+    // a fresh tag per query marks exactly its sources
+    if (++g->tag == 0) {
+        hipLaunchKernelGGL(k_clear_tags, dim3(device_cu_count() * 8), dim3(256), 0, s,
+                           g->nodes.as<NodeRec>(), static_cast<uint64_t>(g->n));
+        SIA_HIP(hipGetLastError());
+        g->tag = 1;
+    }
+    hipLaunchKernelGGL(k_tag_sources, dim3((n_src + 255) / 256), dim3(256), 0, s,
+                       ws.src_sorted.as<int32_t>(), n_src, g->nodes.as<NodeRec>(), g->tag);
     SIA_HIP(hipGetLastError());
+    if (count_ids) ws.cnt.ensure(sizeof(uint32_t) * std::max<uint64_t>(id_space, 1));
 
     if (!ws.walk_cap) {
         ws.walk_cap = std::min<uint64_t>(n_attempts, std::max<uint64_t>(1u << 20, n_attempts / 16));
@@ -390,15 +421,16 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
         ws.walk_len.ensure(sizeof(uint32_t) * ws.walk_cap);
         ws.ids.ensure(sizeof(uint32_t) * ws.id_cap);
         SIA_HIP(hipMemsetAsync(ws.counters.ptr, 0, sizeof(uint64_t) * ST_COUNT, s));
+        if (count_ids) SIA_HIP(hipMemsetAsync(ws.cnt.ptr, 0, sizeof(uint32_t) * id_space, s));
 
         SampleArgs A;
         A.nodes = g->nodes.as<NodeRec>();
         A.edges = g->edges.as<EdgeRec>();
-        A.bitmap = ws.bitmap.as<uint32_t>();
         A.src_t = ws.src_t.as<uint32_t>();
         A.bucket = ws.bucket.as<uint32_t>();
         A.n_src = n_src;
         A.bucket_shift = st.shift;
+        A.tag = g->tag;
         A.n_ns = st.n_ns;
         A.seed = seed;
         A.attempt_offset = attempt_offset;
@@ -409,6 +441,7 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
         A.walk_off = ws.walk_off.as<uint64_t>();
         A.walk_len = ws.walk_len.as<uint32_t>();
         A.ids = ws.ids.as<uint32_t>();
+        A.cnt = count_ids ? ws.cnt.as<uint32_t>() : nullptr;
         A.walk_cap = ws.walk_cap;
         A.id_cap = ws.id_cap;
 
