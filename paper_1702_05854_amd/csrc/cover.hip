@@ -1,26 +1,28 @@
 // Coverage counts and greedy max-coverage (Algorithm 4 for edges, Algorithm 7
 // for nodes) over the kept walks.
 //
-//   cnt[id]  = number of not-yet-covered walks holding id (Cov of one id);
-//   inv      = inverted index id -> walks, built by a counting sort driven by
-//              cnt (offsets = prefix sums of the initial counts);
-//   key(id)  = ((cnt+1) << 32) | (2^32-1-id) for an unselected id, 0 once
-//              selected, so the largest key is the largest marginal gain with
-//              the lowest id on ties, and zero-gain rounds take the lowest
-//              id not selected yet;
-//   L1/L2/L3 = maxima of key over 64 ids / 64 L1 entries / 64 L2 entries.
+//   cnt[id] = number of not-yet-covered walks holding id (Cov of one id),
+//             exact at all times; 0xFFFFFFFF once id is selected;
+//   inv     = inverted index id -> walks, a counting sort driven by cnt;
+//   key(id) = ((cnt+1) << 32) | (2^32-1-id) for an unselected id, 0 once
+//             selected: the largest key is the largest marginal gain with the
+//             lowest id on ties, and once every gain is zero the lowest id not
+//             selected yet (exactly k picks).
 //
-// Each round is four kernels.  pick+cover: every workgroup reads L3 and
-// derives the same pick; workgroup 0 records it; all waves then take the
-// picked id's walks (one wave per walk), mark the uncovered ones and
-// decrement the counts of their ids, queueing each touched L1 block once.
-// Then one refresh kernel per level: one wave per queued block recomputes its
-// maximum and queues the parent block once.  Kernel boundaries order the
-// phases (and make the writes of one phase visible to every XCD in the
-// next); nothing is read back until the last round.
+// Lazy greedy.  Covering walks only lowers counts, so a key computed once is
+// an upper bound forever.  A pool holds the ids whose keys may be the
+// largest, and tau bounds the key of every id outside the pool.  One
+// workgroup then runs rounds back to back: recompute the pool's keys from the
+// exact counts, and if the best exceeds tau it is the true argmax of the
+// round -- record it, mark its walks covered and decrement the counts of
+// their ids.  When the best no longer exceeds tau, grid-wide kernels rebuild
+// the pool from the current counts (a histogram of counts chooses the
+// threshold; ties at the threshold are resolved by ascending id).  The
+// result is exactly the greedy of Algorithm 4 / 7.
 #include "common.hpp"
 
 #include <algorithm>
+#include <cstddef>
 
 namespace sia {
 
@@ -31,11 +33,23 @@ constexpr uint32_t kSelected = 0xFFFFFFFFu;
 constexpr uint32_t kScanTile = 4096;  // 256 threads x 16
 
 struct GreedyState {
-    uint32_t n_queued[3][2];  // queued blocks per level, by round parity
+    uint32_t pool_n;    // ids in the pool
+    uint32_t next_id;   // first tied id left out of the pool (tie case)
+    uint32_t rounds;    // rounds completed so far
     uint32_t error;
 };
 
-constexpr uint32_t kB = 64;  // fan-in of every level
+// Count histogram: counts 0..4095 exactly; above, 512 bins per octave.
+constexpr uint32_t kExact = 4096;
+constexpr uint32_t kPerOctave = 512;
+constexpr uint32_t kBins = kExact + 20 * kPerOctave;  // octaves 2^12 .. 2^31
+
+__device__ __forceinline__ uint32_t count_bin(uint32_t c)
+{
+    if (c < kExact) return c;
+    const uint32_t L = 32u - __clz(c);  // bit length, 13..32
+    return kExact + (L - 13u) * kPerOctave + ((c >> (L - 10u)) & (kPerOctave - 1u));
+}
 
 __device__ __forceinline__ uint64_t key_of(uint32_t c, uint32_t id)
 {
@@ -149,119 +163,143 @@ __global__ __launch_bounds__(256) void k_fill(const uint64_t *walk_off, const ui
     }
 }
 
-// ---- full build of one level: out[i] = max over in[i*64 .. i*64+63]
-// (level 1 reads keys of the counts directly).
-__global__ __launch_bounds__(256) void k_build_level(const uint32_t *cnt, const uint64_t *in,
-                                                     uint64_t n_in, uint64_t *out, uint64_t n_out)
+// ---- pool rebuild
+__global__ __launch_bounds__(1024) void k_hist(const uint32_t *cnt, uint64_t S, uint32_t *hist)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
-    for (uint64_t i = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
-         i < n_out; i += waves) {
-        const uint64_t c = i * kB + lane;
-        uint64_t v = 0;
-        if (c < n_in) v = cnt ? key_of(cnt[c], static_cast<uint32_t>(c)) : in[c];
-        v = wave_max_u64(v);
-        if (lane == 0) out[i] = v;
-    }
-}
-
-struct Tree {
-    uint32_t *cnt;
-    uint64_t id_space;
-    uint64_t *lvl[3];    // L1, L2, L3 maxima
-    uint64_t n[3];       // entries per level
-    uint32_t *flag[3];   // block queued this round, per level
-    uint32_t *queue[3];  // two queues per level (round parity), n[l] entries each
-};
-
-__device__ __forceinline__ void enqueue(const Tree &T, GreedyState *st, int level, uint32_t par,
-                                        uint64_t b)
-{
-    if (T.flag[level][b] == 0u && atomicExch(&T.flag[level][b], 1u) == 0u)
-        T.queue[level][par * T.n[level] + atomicAdd(&st->n_queued[level][par], 1u)] =
-            static_cast<uint32_t>(b);
-}
-
-__global__ __launch_bounds__(256) void k_pick_cover(Tree T, GreedyState *st, int64_t round,
-                                                    int64_t *sel, uint64_t *gain, const uint32_t *cur,
-                                                    const uint32_t *inv, const uint64_t *walk_off,
-                                                    const uint32_t *walk_len, const uint32_t *ids,
-                                                    uint32_t *covered)
-{
-    __shared__ uint64_t sh[4];
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    const uint32_t par = static_cast<uint32_t>(round & 1);
-    // every workgroup derives the same pick from L3
-    uint64_t best = 0;
-    const uint64_t *l3 = T.lvl[2];
-    for (uint64_t i = threadIdx.x; i < T.n[2]; i += blockDim.x) best = l3[i] > best ? l3[i] : best;
-    best = wave_max_u64(best);
-    if (lane == 0) sh[wid] = best;
+    __shared__ uint32_t h[kBins];
+    for (uint32_t i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    best = sh[0];
-    for (int k = 1; k < 4; ++k) best = sh[k] > best ? sh[k] : best;
-    if (best == 0) {  // unreachable while rounds < id space; never index with it
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st->error = 1;
-            sel[round] = -1;
-            gain[round] = 0;
-        }
-        return;
+    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (; i < S; i += stride) {
+        const uint32_t c = cnt[i];
+        if (c != kSelected) atomicAdd(&h[count_bin(c)], 1u);
     }
-    const uint32_t id = 0xFFFFFFFFu - static_cast<uint32_t>(best);
-    const uint32_t g = static_cast<uint32_t>(best >> 32) - 1u;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sel[round] = id;
-        gain[round] = g;
-        T.cnt[id] = kSelected;
-        enqueue(T, st, 0, par, id / kB);
-        // the queues of the next round start empty
-        for (int l = 0; l < 3; ++l) st->n_queued[l][par ^ 1u] = 0;
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < kBins; b += blockDim.x)
+        if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+// Pool += every unselected id with cnt >= c_min (c_min >= 1).
+__global__ void k_collect(const uint32_t *cnt, uint64_t S, uint32_t c_min, uint32_t *pool,
+                          GreedyState *st)
+{
+    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (; i < S; i += stride) {
+        const uint32_t c = cnt[i];
+        if (c != kSelected && c >= c_min) pool[atomicAdd(&st->pool_n, 1u)] = static_cast<uint32_t>(i);
     }
-    if (g == 0) return;
-    // cover the picked id's walks: one wave per listed walk
-    const uint32_t lo = cur[id], hi = cur[id + 1];
-    const uint32_t gw = blockIdx.x * (blockDim.x / kWave) + wid;
-    const uint32_t nw = gridDim.x * (blockDim.x / kWave);
-    for (uint32_t p = lo + gw; p < hi; p += nw) {
-        const uint32_t w = inv[p];
-        uint32_t old = 1;
-        if (lane == 0) old = atomicExch(&covered[w], 1u);
-        old = __shfl(old, 0, kWave);
-        if (old != 0u) continue;
-        const uint64_t o = walk_off[w];
-        const uint32_t L = walk_len[w];
-        for (uint32_t e = lane; e < L; e += kWave) {
-            const uint32_t x = ids[o + e];
-            if (x == id) continue;
-            atomicSub(&T.cnt[x], 1u);
-            enqueue(T, st, 0, par, x / kB);
+}
+
+// Ties: per tile of 4096 ids, how many have cnt == c.
+__global__ __launch_bounds__(256) void k_tie_count(const uint32_t *cnt, uint64_t S, uint32_t c,
+                                                   uint32_t *tile_counts)
+{
+    __shared__ uint32_t sh[4];
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
+    uint32_t k = 0;
+    for (int i = 0; i < 16; ++i)
+        if (base + i < S && cnt[base + i] == c) ++k;
+    uint32_t total;
+    block_excl_scan_256(k, sh, total);
+    if (threadIdx.x == 0) tile_counts[blockIdx.x] = total;
+}
+
+// Ties: the first R ids (ascending) with cnt == c go to pool[pool_base ..];
+// the (R+1)-th one is recorded in st->next_id.
+__global__ __launch_bounds__(256) void k_tie_emit(const uint32_t *cnt, uint64_t S, uint32_t c,
+                                                  const uint32_t *tile_offs, uint32_t R,
+                                                  uint32_t pool_base, uint32_t *pool, GreedyState *st)
+{
+    __shared__ uint32_t sh[4];
+    if (tile_offs[blockIdx.x] > R) return;  // uniform per block
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
+    uint32_t k = 0;
+    for (int i = 0; i < 16; ++i)
+        if (base + i < S && cnt[base + i] == c) ++k;
+    uint32_t total;
+    uint32_t q = tile_offs[blockIdx.x] + block_excl_scan_256(k, sh, total);
+    for (int i = 0; i < 16; ++i) {
+        if (base + i < S && cnt[base + i] == c) {
+            if (q < R) pool[pool_base + q] = static_cast<uint32_t>(base + i);
+            else if (q == R) st->next_id = static_cast<uint32_t>(base + i);
+            ++q;
         }
     }
 }
 
-// Recompute the queued blocks of one level; queue their parents.
-__global__ __launch_bounds__(256) void k_refresh(Tree T, GreedyState *st, int64_t round, int level)
+// ---- lazy rounds: one workgroup, rounds [st->rounds, k) while certified
+constexpr int kLazyThreads = 1024;
+
+__device__ __forceinline__ uint32_t load_count(const uint32_t *p)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t par = static_cast<uint32_t>(round & 1);
-    const uint32_t todo = st->n_queued[level][par];
-    const uint32_t waves = (gridDim.x * blockDim.x) / kWave;
-    const uint64_t n_in = level == 0 ? T.id_space : T.n[level - 1];
-    const uint64_t *in = level == 0 ? nullptr : T.lvl[level - 1];
-    for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < todo; i += waves) {
-        const uint64_t b = T.queue[level][par * T.n[level] + i];
-        const uint64_t c = b * kB + lane;
-        uint64_t v = 0;
-        if (c < n_in) v = level == 0 ? key_of(T.cnt[c], static_cast<uint32_t>(c)) : in[c];
-        v = wave_max_u64(v);
-        if (lane == 0) {
-            T.lvl[level][b] = v;
-            T.flag[level][b] = 0u;
-            if (level < 2) enqueue(T, st, level + 1, par, b / kB);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kLazyThreads) void k_lazy(uint32_t *cnt, const uint32_t *pool,
+                                                       uint64_t tau, int64_t k, int64_t *sel,
+                                                       uint64_t *gain, const uint32_t *cur,
+                                                       const uint32_t *inv, const uint64_t *walk_off,
+                                                       const uint32_t *walk_len, const uint32_t *ids,
+                                                       uint32_t *covered, GreedyState *st)
+{
+    __shared__ uint64_t sh[kLazyThreads / kWave];
+    __shared__ uint32_t queue[kLazyThreads];
+    __shared__ uint32_t qn;
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    constexpr int kWaves = kLazyThreads / kWave;
+    const uint32_t P = st->pool_n;
+    int64_t r = st->rounds;
+    for (; r < k; ++r) {
+        // exact keys of the pool; the largest is this round's pick if it beats tau
+        uint64_t best = 0;
+        for (uint32_t i = threadIdx.x; i < P; i += kLazyThreads) {
+            const uint32_t id = pool[i];
+            const uint64_t key = key_of(load_count(&cnt[id]), id);
+            best = key > best ? key : best;
         }
+        best = wave_max_u64(best);
+        if (lane == 0) sh[wid] = best;
+        if (threadIdx.x == 0) qn = 0;
+        __syncthreads();
+        best = sh[0];
+        for (int w = 1; w < kWaves; ++w) best = sh[w] > best ? sh[w] : best;
+        if (best <= tau) break;  // uniform: every thread saw the same values
+        const uint32_t id = 0xFFFFFFFFu - static_cast<uint32_t>(best);
+        const uint32_t g = static_cast<uint32_t>(best >> 32) - 1u;
+        if (threadIdx.x == 0) {
+            sel[r] = id;
+            gain[r] = g;
+            atomicExch(&cnt[id], kSelected);
+        }
+        if (g > 0) {
+            const uint32_t lo = cur[id], hi = cur[id + 1];
+            for (uint32_t b0 = lo; b0 < hi; b0 += kLazyThreads) {
+                const uint32_t p = b0 + threadIdx.x;
+                if (p < hi) {
+                    const uint32_t w = inv[p];
+                    if (atomicExch(&covered[w], 1u) == 0u) queue[atomicAdd(&qn, 1u)] = w;
+                }
+                __syncthreads();
+                const uint32_t n = qn;
+                for (uint32_t qi = wid; qi < n; qi += kWaves) {
+                    const uint32_t w = queue[qi];
+                    const uint64_t o = walk_off[w];
+                    const uint32_t L = walk_len[w];
+                    for (uint32_t e = lane; e < L; e += kWave) {
+                        const uint32_t x = ids[o + e];
+                        if (x != id) atomicSub(&cnt[x], 1u);
+                    }
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) qn = 0;
+                __syncthreads();
+            }
+        }
+        __syncthreads();
     }
+    if (threadIdx.x == 0) st->rounds = static_cast<uint32_t>(r);
 }
 
 unsigned grid_for(uint64_t items, unsigned block, unsigned cap)
@@ -273,6 +311,21 @@ unsigned grid_for(uint64_t items, unsigned block, unsigned cap)
 
 }  // namespace
 
+namespace {
+
+uint64_t bin_lo(uint32_t b)
+{
+    if (b < kExact) return b;
+    const uint32_t o = (b - kExact) / kPerOctave, r = (b - kExact) % kPerOctave;
+    const uint32_t L = o + 13;  // bit length
+    return (static_cast<uint64_t>(kPerOctave + r)) << (L - 10);
+}
+
+constexpr uint64_t kPoolTarget = 4096;
+constexpr uint64_t kPoolMax = 16384;
+
+}  // namespace
+
 GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
                         int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s, bool timing,
                         bool counts_ready)
@@ -280,7 +333,6 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
     SIA_REQUIRE(n_ids < 0xFFFFFFFFull && n_walks < 0xFFFFFFFFull, SIA_EINVAL,
                 "too many walk ids for 32-bit inverted index offsets");
     const uint64_t S = static_cast<uint64_t>(id_space);
-    const uint64_t n1 = (S + kB - 1) / kB, n2 = (n1 + kB - 1) / kB, n3 = (n2 + kB - 1) / kB;
     const uint64_t n_tiles = (S + kScanTile - 1) / kScanTile;
     const int cus = device_cu_count();
 
@@ -288,31 +340,16 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
     ws.cur.ensure(sizeof(uint32_t) * (S + 1));
     ws.inv.ensure(sizeof(uint32_t) * std::max<uint64_t>(n_ids, 1));
     ws.covered.ensure(sizeof(uint32_t) * std::max<uint64_t>(n_walks, 1));
-    ws.lvl1.ensure(sizeof(uint64_t) * (n1 + n2 + n3));
-    ws.flag1.ensure(sizeof(uint32_t) * (n1 + n2 + n3));
-    ws.dirty1.ensure(sizeof(uint32_t) * 2 * (n1 + n2 + n3));
+    ws.lvl1.ensure(sizeof(uint32_t) * (kBins + kPoolMax));   // histogram + pool
     ws.sel.ensure(sizeof(int64_t) * k);
     ws.gain.ensure(sizeof(uint64_t) * k);
     ws.scan_tmp.ensure(sizeof(uint32_t) * n_tiles + sizeof(GreedyState) + 64);
     uint32_t *tiles = ws.scan_tmp.as<uint32_t>();
     GreedyState *st = reinterpret_cast<GreedyState *>(
         ws.scan_tmp.as<char>() + ((sizeof(uint32_t) * n_tiles + 63) / 64) * 64);
-
-    Tree T;
-    T.cnt = ws.cnt.as<uint32_t>();
-    T.id_space = S;
-    T.n[0] = n1;
-    T.n[1] = n2;
-    T.n[2] = n3;
-    T.lvl[0] = ws.lvl1.as<uint64_t>();
-    T.flag[0] = ws.flag1.as<uint32_t>();
-    T.queue[0] = ws.dirty1.as<uint32_t>();
-    for (int l = 1; l < 3; ++l) {
-        T.lvl[l] = T.lvl[l - 1] + T.n[l - 1];
-        T.flag[l] = T.flag[l - 1] + T.n[l - 1];
-        T.queue[l] = T.queue[l - 1] + 2 * T.n[l - 1];
-    }
-    uint32_t *cnt = T.cnt, *cur = ws.cur.as<uint32_t>();
+    uint32_t *hist = ws.lvl1.as<uint32_t>();
+    uint32_t *pool = hist + kBins;
+    uint32_t *cnt = ws.cnt.as<uint32_t>(), *cur = ws.cur.as<uint32_t>();
     const uint32_t *ids = ws.ids.as<uint32_t>();
 
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -339,38 +376,75 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
                            cur, ws.inv.as<uint32_t>());
         SIA_HIP(hipGetLastError());
     }
-    // greedy state
     SIA_HIP(hipMemsetAsync(ws.covered.ptr, 0, sizeof(uint32_t) * std::max<uint64_t>(n_walks, 1), s));
-    SIA_HIP(hipMemsetAsync(ws.flag1.ptr, 0, sizeof(uint32_t) * (n1 + n2 + n3), s));
     SIA_HIP(hipMemsetAsync(st, 0, sizeof(GreedyState), s));
-    hipLaunchKernelGGL(k_build_level, dim3(grid_for(n1 * kWave, 256, cus * 32)), dim3(256), 0, s,
-                       cnt, nullptr, S, T.lvl[0], n1);
-    hipLaunchKernelGGL(k_build_level, dim3(grid_for(n2 * kWave, 256, cus * 32)), dim3(256), 0, s,
-                       nullptr, T.lvl[0], n1, T.lvl[1], n2);
-    hipLaunchKernelGGL(k_build_level, dim3(grid_for(n3 * kWave, 256, cus * 32)), dim3(256), 0, s,
-                       nullptr, T.lvl[1], n2, T.lvl[2], n3);
-    SIA_HIP(hipGetLastError());
     if (timing) SIA_HIP(hipEventRecord(ev[1], s));
 
-    const unsigned grid = static_cast<unsigned>(cus * 2);
-    for (int64_t r = 0; r < k; ++r) {
-        hipLaunchKernelGGL(k_pick_cover, dim3(grid), dim3(256), 0, s, T, st, r,
+    std::vector<uint32_t> h(kBins);
+    GreedyState hs{};
+    int64_t done = 0;
+    while (done < k) {
+        // ---- rebuild the pool from the current counts
+        SIA_HIP(hipMemsetAsync(hist, 0, sizeof(uint32_t) * kBins, s));
+        hipLaunchKernelGGL(k_hist, dim3(cus), dim3(1024), 0, s, cnt, S, hist);
+        SIA_HIP(hipGetLastError());
+        SIA_HIP(hipMemcpyAsync(h.data(), hist, sizeof(uint32_t) * kBins, hipMemcpyDeviceToHost, s));
+        SIA_HIP(hipStreamSynchronize(s));
+        // highest bin b* with at least kPoolTarget ids at or above it (or bin 0)
+        uint64_t above = 0;
+        int64_t bstar = kBins - 1;
+        for (; bstar > 0; --bstar) {
+            if (above + h[bstar] >= kPoolTarget) break;
+            above += h[bstar];
+        }
+        const uint64_t ge = above + h[bstar];
+        uint64_t tau;
+        uint32_t pool_n;
+        SIA_HIP(hipMemsetAsync(st, 0, offsetof(GreedyState, rounds), s));  // pool_n, next_id
+        if (ge <= kPoolMax && bstar > 0) {
+            const uint64_t c_lo = bin_lo(static_cast<uint32_t>(bstar));
+            hipLaunchKernelGGL(k_collect, dim3(cus * 8), dim3(256), 0, s, cnt, S,
+                               static_cast<uint32_t>(c_lo), pool, st);
+            tau = (c_lo << 32) | 0xFFFFFFFFull;  // bound for every count <= c_lo - 1
+            pool_n = static_cast<uint32_t>(ge);
+        } else {
+            // ties at an exact count c: all ids above c, then the lowest-id ones at c
+            SIA_REQUIRE(bstar < static_cast<int64_t>(kExact), SIA_EDEVICE,
+                        "greedy pool: more tied high counts than the pool holds");
+            const uint32_t c = static_cast<uint32_t>(bstar);
+            const uint32_t R = static_cast<uint32_t>(std::min<uint64_t>(kPoolTarget, ge) - above);
+            if (above) {
+                hipLaunchKernelGGL(k_collect, dim3(cus * 8), dim3(256), 0, s, cnt, S, c + 1, pool, st);
+            }
+            hipLaunchKernelGGL(k_tie_count, dim3(n_tiles), dim3(256), 0, s, cnt, S, c, tiles);
+            hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(256), 0, s, tiles, n_tiles);
+            hipLaunchKernelGGL(k_tie_emit, dim3(n_tiles), dim3(256), 0, s, cnt, S, c, tiles, R,
+                               static_cast<uint32_t>(above), pool, st);
+            SIA_HIP(hipGetLastError());
+            SIA_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+            SIA_HIP(hipStreamSynchronize(s));
+            pool_n = static_cast<uint32_t>(above + R);
+            tau = ge > above + R ? ((static_cast<uint64_t>(c) + 1) << 32) | (0xFFFFFFFFu - hs.next_id)
+                                 : (c ? (static_cast<uint64_t>(c) << 32) | 0xFFFFFFFFull : 0ull);
+            SIA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(&st->pool_n),
+                                      static_cast<int>(pool_n), 1, s));
+        }
+        SIA_HIP(hipGetLastError());
+        // ---- certified rounds, back to back
+        hipLaunchKernelGGL(k_lazy, dim3(1), dim3(kLazyThreads), 0, s, cnt, pool, tau, k,
                            ws.sel.as<int64_t>(), ws.gain.as<uint64_t>(), cur,
                            ws.inv.as<uint32_t>(), ws.walk_off.as<uint64_t>(),
-                           ws.walk_len.as<uint32_t>(), ids, ws.covered.as<uint32_t>());
-        for (int l = 0; l < 3; ++l)
-            hipLaunchKernelGGL(k_refresh, dim3(l == 0 ? grid : cus), dim3(256), 0, s, T, st, r, l);
+                           ws.walk_len.as<uint32_t>(), ids, ws.covered.as<uint32_t>(), st);
+        SIA_HIP(hipGetLastError());
+        SIA_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+        SIA_HIP(hipStreamSynchronize(s));
+        SIA_REQUIRE(static_cast<int64_t>(hs.rounds) > done, SIA_EDEVICE, "greedy made no progress");
+        done = hs.rounds;
     }
-    SIA_HIP(hipGetLastError());
     if (timing) SIA_HIP(hipEventRecord(ev[2], s));
-    GreedyState hst;
     SIA_HIP(hipMemcpyAsync(selected, ws.sel.ptr, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
     SIA_HIP(hipMemcpyAsync(gains, ws.gain.ptr, sizeof(uint64_t) * k, hipMemcpyDeviceToHost, s));
-    SIA_HIP(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
     SIA_HIP(hipStreamSynchronize(s));
-    SIA_REQUIRE(hst.error == 0, SIA_EDEVICE, "greedy state inconsistent");
-    for (int64_t i = 0; i < k; ++i)
-        SIA_REQUIRE(selected[i] >= 0, SIA_EDEVICE, "greedy state inconsistent");
     GreedyResult res;
     if (timing) {
         SIA_HIP(hipEventElapsedTime(&res.ms_count, ev[0], ev[1]));

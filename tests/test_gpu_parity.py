@@ -207,6 +207,32 @@ def test_greedy_large_id_space(sia):
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
+@pytest.mark.parametrize("case", ["ties", "all", "hot"])
+def test_greedy_ties_and_many_rounds(sia, case):
+    """Many rounds with large tie groups (the pool is rebuilt many times and
+    ties are broken by ascending id), every id selected, and a few very hot ids."""
+    rng = np.random.default_rng({"ties": 1, "all": 2, "hot": 3}[case])
+    if case == "ties":
+        id_space, n_walks, k = 40_000, 25_000, 12_000
+        walks = [rng.choice(id_space, rng.integers(1, 3), replace=False) for _ in range(n_walks)]
+    elif case == "all":
+        id_space, n_walks, k = 5_000, 8_000, 5_000
+        walks = [rng.choice(id_space, rng.integers(1, 6), replace=False) for _ in range(n_walks)]
+    else:
+        id_space, n_walks, k = 2_000_000, 10_000, 2000
+        hot = rng.choice(id_space, 10, replace=False)
+        walks = [np.unique(np.concatenate([hot[rng.integers(0, 10, 2)],
+                                           rng.integers(0, id_space, rng.integers(1, 30))]))
+                 for _ in range(n_walks)]
+    walks = [np.asarray(w, np.uint32) for w in walks]
+    off = np.zeros(n_walks + 1, np.uint64)
+    off[1:] = np.cumsum([w.shape[0] for w in walks])
+    ids = np.concatenate(walks)
+    got = sia.greedy(id_space, off, ids, k)
+    ref = cpu.greedy_csr(id_space, off, ids, k)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
 def test_greedy_empty_and_exhaustive(sia):
     sel, gains = sia.greedy(5, np.zeros(1, np.uint64), np.zeros(0, np.uint32), 5)
     assert sel.tolist() == [0, 1, 2, 3, 4] and gains.tolist() == [0] * 5
