@@ -1,0 +1,138 @@
+"""GPU parity at full workload sizes.
+
+* cl1m (Chung-Lu, n=10^6, m=1.6*10^7, 1000 sources, N=10^7): the whole path,
+  edges and nodes, compared with the oracle run on all N attempts.
+* rmat24 (R-MAT scale 24, 2.6*10^8 edges, 10^4 sources, N=10^8 -- the bench
+  workload, in the same launch configuration): the sampler's kept walks for
+  sampled attempt ids (kept and not kept) against the oracle walking those
+  attempts one by one; counters against invariants; the greedy on a prefix
+  of the kept walks against the oracle; and properties of the full solve
+  that hold at any size.
+"""
+import numpy as np
+import pytest
+
+
+def say(*a):
+    print("[fullsize]", *a, flush=True)
+
+from oracle import cpu
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sia():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1702_05854_amd import sia as _sia
+    _sia.lib()
+    return _sia
+
+
+@pytest.fixture(scope="module")
+def cl1m(sia):
+    from paper_1702_05854_amd import workloads
+    say("generating cl1m")
+    wl = workloads.load("cl1m")
+    say("ingest")
+    g = sia.Graph(wl.col_off.cuda(), wl.row_idx.cuda(), wl.w.cuda())
+    og = cpu.Graph(*wl.host())
+    yield wl, g, og
+    g.close()
+
+
+@pytest.mark.parametrize("mode", ["edges", "nodes"])
+def test_cl1m_solve_matches_oracle(sia, cl1m, mode):
+    wl, g, og = cl1m
+    om = cpu.MODE_EDGES if mode == "edges" else cpu.MODE_NODES
+    got = sia.solve(g, wl.sources, mode, wl.k, wl.n_attempts, 0, wl.seed)
+    say("oracle solve", mode)
+    ref = cpu.solve(og, wl.sources, om, wl.k, wl.n_attempts, 0, wl.seed)
+    st = got["stats"]
+    assert (st["hits"], st["dead_ends"], st["cycles"], st["steps"]) == (
+        ref["walks"].hits, ref["walks"].dead_ends, ref["walks"].cycles, ref["walks"].steps)
+    assert st["walk_ids"] == ref["walks"].ids.shape[0]
+    assert np.array_equal(got["selected"], ref["selected"])
+    assert np.array_equal(got["gains"], ref["gains"])
+    assert st["suspension_est"] == ref["suspension"]
+    assert st["suspension_nodes_est"] == ref["suspension_nodes"]
+
+
+def test_cl1m_walks_match_oracle(sia, cl1m):
+    wl, g, og = cl1m
+    got = sia.sample(g, wl.sources, "edges", 1_000_003, 5_000_000, wl.seed)
+    ref = og.sample(wl.sources, cpu.MODE_EDGES, 1_000_003, 5_000_000, wl.seed)
+    assert np.array_equal(got.attempt, ref.attempt)
+    assert np.array_equal(got.off, ref.off)
+    assert np.array_equal(got.ids, ref.ids)
+
+
+@pytest.fixture(scope="module")
+def rmat24(sia):
+    from paper_1702_05854_amd import workloads
+    say("generating rmat24")
+    wl = workloads.load("rmat24", device="cuda")
+    g = sia.Graph(wl.col_off, wl.row_idx, wl.w)
+    host = wl.host()
+    say("oracle thresholds")
+    og = cpu.Graph(*host)
+    yield wl, g, og, host
+    g.close()
+
+
+def test_rmat24_sampled_walks_match_oracle(sia, rmat24):
+    wl, g, og, (col_off, row_idx, w) = rmat24
+    N = wl.n_attempts
+    say("gpu sample")
+    got = sia.sample(g, wl.sources, "edges", N, 0, wl.seed)
+    say("walks on host")
+    st = got.stats
+    assert st["hits"] + st["dead_ends"] + st["cycles"] == N
+    assert got.n_walks == st["hits"] and got.ids.shape[0] == st["walk_ids"]
+    assert st["evaluations"] >= st["steps"]
+    rng = np.random.default_rng(24)
+    kept = got.attempt[rng.choice(got.n_walks, 1000, replace=False)]
+    anyid = rng.choice(N, 2000, replace=False).astype(np.uint64)
+    probe = np.unique(np.concatenate([kept, anyid, np.array([0, N - 1], np.uint64)]))
+    say("oracle on", probe.shape[0], "attempts")
+    ref = og.sample_list(wl.sources, cpu.MODE_EDGES, probe, wl.seed)
+    # the oracle's kept walks among the probed attempts are exactly the GPU's
+    pos = np.minimum(np.searchsorted(got.attempt, probe), got.n_walks - 1)
+    gpu_kept = probe[got.attempt[pos] == probe]
+    assert np.array_equal(ref.attempt, gpu_kept)
+    for i, a in enumerate(ref.attempt):
+        j = int(np.searchsorted(got.attempt, a))
+        assert np.array_equal(got.walk(j), ref.walk(i)), int(a)
+    # walks chain backwards: the tail of edge j_i is the head (column) of j_{i+1}
+    for i in range(min(got.n_walks, 2000)):
+        e = got.walk(i).astype(np.int64)
+        heads = np.searchsorted(col_off, e, side="right") - 1
+        assert np.all(row_idx[e[:-1]] == heads[1:]), i
+    # greedy on a prefix of the kept walks: identical to the oracle's
+    nw = 20_000
+    off = got.off[: nw + 1].copy()
+    ids = got.ids[: int(off[-1])]
+    a = sia.greedy(g.m, off, ids, 200)
+    say("oracle greedy")
+    b = cpu.greedy_csr(g.m, off, ids, 200)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_rmat24_solve_properties(sia, rmat24):
+    wl, g, og, host = rmat24
+    res = sia.solve(g, wl.sources, "edges", wl.k, wl.n_attempts, 0, wl.seed)
+    sel, gains, st = res["selected"], res["gains"], res["stats"]
+    assert len(set(sel.tolist())) == wl.k
+    assert np.all(np.diff(gains.astype(np.int64)) <= 0)      # submodular: gains never grow
+    assert st["covered"] == int(gains.sum()) <= st["hits"]
+    walks = sia.sample(g, wl.sources, "edges", wl.n_attempts, 0, wl.seed)
+    cnt = np.bincount(walks.ids, minlength=g.m)
+    assert int(gains[0]) == int(cnt.max())
+    assert int(sel[0]) == int(np.flatnonzero(cnt == cnt.max())[0])  # lowest id on ties
+    # coverage of the selected set, recomputed from the walks
+    chosen = np.zeros(g.m, bool)
+    chosen[sel] = True
+    hit = np.add.reduceat(chosen[walks.ids].astype(np.int64), walks.off[:-1].astype(np.int64)) > 0
+    assert int(hit.sum()) == st["covered"]
