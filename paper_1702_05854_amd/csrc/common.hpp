@@ -37,8 +37,9 @@ struct Error {
 // ------------------------------------------------------------ device layout
 // One 16-byte record per node: where its in-edges start, how many, the last
 // cumulative threshold (so the dead-end test needs no extra load), and the
-// source tag: equal to the running query's tag exactly when the node is one
-// of its sources (so membership comes with the record the walk loads anyway).
+// source tag: bit b is set exactly when the node is a source of the query
+// holding slot bit b (so membership comes with the record the walk loads
+// anyway).  Bit 31 belongs to single-query calls, bits 0..30 to batches.
 struct NodeRec {
     uint32_t off;
     uint32_t deg;
@@ -82,7 +83,6 @@ struct Workspace {
 struct sia_graph {
     int64_t n = 0, m = 0;
     int device = 0;
-    uint32_t tag = 0;   // tag of the last query that marked its sources
     sia::DevBuf nodes;  // NodeRec[n]
     sia::DevBuf edges;  // EdgeRec[m]
     sia::Workspace ws;
@@ -103,21 +103,63 @@ void check_query(int64_t n, int64_t m, int mode, const int32_t *sources, int64_t
                  int64_t k, uint64_t n_attempts, uint64_t attempt_offset);
 SourceTables build_source_tables(int64_t n, const int32_t *sources, int64_t n_sources);
 
-// Stats slots written by the sampler.
+// Per-query counters written by the sampler.
 enum StatSlot {
     ST_WALKS = 0, ST_IDS = 1, ST_HITS = 2, ST_DEAD = 3, ST_CYCLE = 4, ST_STEPS = 5,
-    ST_EVALS = 6, ST_OVERFLOW = 7, ST_NEXT = 8, ST_FAULTS = 9, ST_COUNT = 16
+    ST_EVALS = 6, ST_OVERFLOW = 7, ST_FAULTS = 8, ST_COUNT = 16
 };
+
+constexpr uint32_t kSoloBit = 31;   // source-tag bit of single-query calls
+constexpr uint32_t kMaxSlots = 31;  // source-tag bits 0..30 for batches
+
+// Device-side state of one query while it samples (read by the sampler).
+struct SlotDev {
+    uint64_t seed;
+    uint64_t attempt_base;   // attempt id of the query's local attempt 0
+    uint64_t n_ns;           // non-sources
+    const uint32_t *src_t;   // t_i = s_i - i over the sorted sources
+    const uint32_t *bucket;  // bucket[b] = #{i : t_i < b << bucket_shift}
+    uint32_t n_src;
+    uint32_t bucket_shift;
+    uint32_t tag_mask;       // source-tag bit of this query
+    uint32_t mode;           // SIA_EDGES / SIA_NODES
+    uint64_t *walk_attempt;  // kept walks: attempt id, offset, length
+    uint64_t *walk_off;
+    uint32_t *walk_len;
+    uint32_t *ids;
+    uint32_t *cnt;           // coverage counts (nullptr: not counted)
+    uint64_t walk_cap;
+    uint64_t id_cap;
+    uint64_t *counters;      // StatSlot entries
+};
+
+// One entry of a sampling wave: attempts [local_start, local_start + count)
+// of the query in slot `slot` (index into the wave's SlotDev array).
+struct WaveItem {
+    uint32_t slot;
+    uint64_t local_start;
+    uint64_t count;
+};
+
+// Sampling of several queries in one persistent launch.  d_slots: device
+// array of SlotDev; items: host array (copied to d_table, which must hold
+// wave_table_bytes(n_items)).  Asynchronous on stream s.
+size_t wave_table_bytes(uint32_t n_items);
+void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
+                 const WaveItem *items, uint32_t n_items, void *d_table, hipStream_t s);
+// Set or clear the tag bit `mask` of the given sources (device array).
+void tag_sources(const sia_graph *g, const int32_t *d_src, uint32_t n_src, uint32_t mask, bool set,
+                 hipStream_t s);
 
 struct SampleResult {
     uint64_t walks = 0, ids = 0, hits = 0, dead = 0, cycles = 0, steps = 0, evals = 0;
     float ms = 0.f;
 };
 
-// Upload sources, tag them in the node records, run the sampler (rerunning
-// with larger buffers if the output did not fit).  Results stay in g->ws.
-// With count_ids, ws.cnt[id_space] receives the coverage count of every id
-// (number of kept walks holding it).
+// A single query (slot bit 31): upload sources, tag them, run one wave
+// (rerunning with larger buffers if the output did not fit), untag.
+// Results stay in g->ws.  With count_ids, ws.cnt[id_space] receives the
+// coverage count of every id.
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
                          uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing,
                          bool count_ids);

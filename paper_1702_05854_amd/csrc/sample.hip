@@ -18,16 +18,21 @@
 //    is needed either; coverage counts are incremented as the ids are
 //    written.
 //
+// One launch samples a wave: attempt ranges of up to 31 queries ("slots",
+// each with its own sources, seed, mode and output buffers) laid end to end.
 // One lane per attempt; persistent waves refill idle lanes from a global
-// attempt counter in chunks; kept walks are appended with one pair of
-// atomics per wave.  Every iteration a lane computes one Philox block (its
-// start draw, or the draw of the node it evaluates) and, when evaluating,
-// gathers the 16-byte node record (which also carries the source tag) and
-// one or two 8-byte edge records (threshold + tail).
+// counter in chunks and find the slot of each attempt in a small table kept
+// in LDS; kept walks are appended with one pair of atomics per slot per
+// wave.  Every iteration a lane computes one Philox block (its start draw,
+// or the draw of the node it evaluates) and, when evaluating, gathers the
+// 16-byte node record (whose tag bits say which slots have the node as a
+// source) and one or two 8-byte edge records (threshold + tail).  A single
+// query is a wave of one slot, so every call goes through this kernel.
 #include "common.hpp"
 #include "philox.hpp"
 
 #include <algorithm>
+#include <cstddef>
 
 namespace sia {
 
@@ -45,28 +50,20 @@ enum Phase : uint32_t {
     PH_EMIT = 5     // kept walk: re-walk and write its ids
 };
 
-struct SampleArgs {
+struct WaveArgs {
     const NodeRec *nodes;
     const EdgeRec *edges;
-    const uint32_t *src_t;    // t_i = s_i - i over sorted sources
-    const uint32_t *bucket;   // bucket[b] = #{i : t_i < b << bucket_shift}
-    uint32_t n_src;
-    uint32_t bucket_shift;
-    uint32_t tag;             // source tag of this query in NodeRec::tag
-    uint64_t n_ns;
-    uint64_t seed;
-    uint64_t attempt_offset;
-    uint64_t n_attempts;
-    uint64_t guard_evals;     // no walk may need more evaluations than this
-    uint64_t *stats;
-    uint64_t *walk_attempt;
-    uint64_t *walk_off;
-    uint32_t *walk_len;
-    uint32_t *ids;
-    uint32_t *cnt;            // coverage counts (nullptr: not counted)
-    uint64_t walk_cap;
-    uint64_t id_cap;
+    const SlotDev *slots;
+    uint32_t n_slots;
+    uint32_t n_items;
+    const uint64_t *item_prefix;   // [n_items + 1] wave-global attempt index of each item
+    const uint32_t *item_slot;     // [n_items]
+    const uint64_t *item_local;    // [n_items] local attempt index of the item's first attempt
+    uint64_t *next;                // wave-global chunk counter
+    uint64_t guard_evals;          // no walk may need more evaluations than this
 };
+
+constexpr uint32_t kMaxItems = 32;
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 {
@@ -140,20 +137,34 @@ __device__ __forceinline__ bool select_edge(const EdgeRec *__restrict__ edges, c
     return true;
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
+__global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
 {
+    __shared__ SlotDev sl[kMaxSlots + 1];
+    __shared__ uint64_t ip[kMaxItems + 1];
+    __shared__ uint64_t il[kMaxItems];
+    __shared__ uint32_t is[kMaxItems];
+    // per-slot counters of this workgroup: hits, dead ends, cycles, steps, evaluations, faults
+    __shared__ unsigned long long acc[kMaxSlots + 1][6];
     const int lane = threadIdx.x & (kWave - 1);
+    for (uint32_t i = threadIdx.x; i < A.n_slots; i += blockDim.x) sl[i] = A.slots[i];
+    for (uint32_t i = threadIdx.x; i <= A.n_items; i += blockDim.x) ip[i] = A.item_prefix[i];
+    for (uint32_t i = threadIdx.x; i < A.n_items; i += blockDim.x) {
+        il[i] = A.item_local[i];
+        is[i] = A.item_slot[i];
+    }
+    for (uint32_t i = threadIdx.x; i < A.n_slots * 6; i += blockDim.x) acc[i / 6][i % 6] = 0;
+    __syncthreads();
+    const uint64_t total = ip[A.n_items];
+
     // wave-uniform work state
     uint64_t chunk_next = 0, chunk_end = 0;
     bool exhausted = false;
     // lane state
     bool active = false;
-    uint64_t a = 0, out_pos = 0;
+    uint64_t a = 0, out_pos = 0, seed = 0;
+    uint32_t slot = 0, mode = SIA_EDGES, tag_mask = 0;
     uint32_t phase = PH_START, x1 = 0, cur = 0, tort = 0, power = 1, lam = 0, t = 0, lambda = 0,
-             cnt = 0, pa = 0, pb = 0;
-    uint32_t hits = 0, dead = 0, cycles = 0, faults = 0;
-    uint64_t steps = 0, evals = 0;
+             cnt = 0, pa = 0, pb = 0, evals = 0;
 
     for (;;) {
         // ---- refill idle lanes with new attempts (converged section)
@@ -161,23 +172,32 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
         while (idle != 0 && !exhausted) {
             if (chunk_next >= chunk_end) {
                 uint64_t base = 0;
-                if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long *>(&A.stats[ST_NEXT]),
+                if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long *>(A.next),
                                                 static_cast<unsigned long long>(kChunk));
                 base = shfl_u64(base, 0);
-                if (base >= A.n_attempts) {
+                if (base >= total) {
                     exhausted = true;
                     break;
                 }
                 chunk_next = base;
-                chunk_end = min(base + kChunk, A.n_attempts);
+                chunk_end = min(base + kChunk, total);
             }
             const uint32_t need = static_cast<uint32_t>(__popcll(idle));
             const uint64_t avail = chunk_end - chunk_next;
             const uint32_t take = static_cast<uint32_t>(min(static_cast<uint64_t>(need), avail));
             const uint32_t rank = lanes_below(idle);
             if (!active && rank < take) {
-                a = A.attempt_offset + chunk_next + rank;
+                const uint64_t gidx = chunk_next + rank;
+                uint32_t it = 0;
+                while (it + 1 < A.n_items && ip[it + 1] <= gidx) ++it;
+                slot = is[it];
+                const SlotDev &S = sl[slot];
+                a = S.attempt_base + il[it] + (gidx - ip[it]);
+                seed = S.seed;
+                mode = S.mode;
+                tag_mask = S.tag_mask;
                 phase = PH_START;
+                evals = 0;
                 active = true;
             }
             chunk_next += take;
@@ -215,11 +235,12 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
             } else {
                 y = pb;
             }
-            word = phase == PH_START ? philox_word0(0, 1, A.seed, a) : philox_word0(y, 0, A.seed, a);
+            word = phase == PH_START ? philox_word0(0, 1, seed, a) : philox_word0(y, 0, seed, a);
             if (phase == PH_START) {
-                const uint64_t idx = __umul64hi(word, A.n_ns);
-                uint32_t c = A.bucket[idx >> A.bucket_shift];
-                while (c < A.n_src && A.src_t[c] <= idx) ++c;
+                const SlotDev &S = sl[slot];
+                const uint64_t idx = __umul64hi(word, S.n_ns);
+                uint32_t c = S.bucket[idx >> S.bucket_shift];
+                while (c < S.n_src && S.src_t[c] <= idx) ++c;
                 x1 = static_cast<uint32_t>(idx + c);
                 cur = x1;
                 tort = x1;
@@ -230,54 +251,62 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
             } else {
                 R = A.nodes[y];
                 do_eval = true;
-                if (phase == PH_DETECT && t > 0 && R.tag == A.tag) {
+                if (phase == PH_DETECT && t > 0 && (R.tag & tag_mask)) {
                     hit_now = true;
                     do_eval = false;
                 } else if (phase == PH_DETECT && t > A.guard_evals) {  // unreachable for a correct walk
-                    ++faults;
+                    atomicAdd(&acc[slot][5], 1ull);
                     active = false;
                     do_eval = false;
                 }
             }
         }
 
-        // ---- stage 2: reserve output for kept walks (converged section)
-        const uint64_t hm = __ballot(hit_now);
-        if (hm) {
-            const uint32_t len = hit_now ? (MODE == SIA_EDGES ? t : t + 1u) : 0u;
+        // ---- stage 2: reserve output for kept walks, one pair of atomics per slot (converged)
+        uint64_t hm = __ballot(hit_now);
+        while (hm) {
+            const int leader = __ffsll(static_cast<long long>(hm)) - 1;
+            const uint32_t s_lead = __shfl(slot, leader, kWave);
+            const bool mine = hit_now && slot == s_lead;
+            const uint64_t mm = __ballot(mine);
+            const uint32_t len = mine ? (mode == SIA_EDGES ? t : t + 1u) : 0u;
             const uint32_t incl = wave_incl_scan_u32(len, lane);
-            const uint32_t total = __shfl(incl, kWave - 1, kWave);
+            const uint32_t total_len = __shfl(incl, kWave - 1, kWave);
             uint64_t wbase = 0, ibase = 0;
-            if (lane == 0) {
-                wbase = atomicAdd(reinterpret_cast<unsigned long long *>(&A.stats[ST_WALKS]),
-                                  static_cast<unsigned long long>(__popcll(hm)));
-                ibase = atomicAdd(reinterpret_cast<unsigned long long *>(&A.stats[ST_IDS]),
-                                  static_cast<unsigned long long>(total));
+            if (lane == leader) {
+                uint64_t *ctr = sl[s_lead].counters;
+                wbase = atomicAdd(reinterpret_cast<unsigned long long *>(&ctr[ST_WALKS]),
+                                  static_cast<unsigned long long>(__popcll(mm)));
+                ibase = atomicAdd(reinterpret_cast<unsigned long long *>(&ctr[ST_IDS]),
+                                  static_cast<unsigned long long>(total_len));
             }
-            wbase = shfl_u64(wbase, 0);
-            ibase = shfl_u64(ibase, 0);
-            if (hit_now) {
-                ++hits;
-                steps += t;
-                const uint64_t widx = wbase + lanes_below(hm);
+            wbase = shfl_u64(wbase, leader);
+            ibase = shfl_u64(ibase, leader);
+            if (mine) {
+                const SlotDev &S = sl[slot];
+                atomicAdd(&acc[slot][0], 1ull);
+                atomicAdd(&acc[slot][3], static_cast<unsigned long long>(t));
+                const uint64_t widx = wbase + lanes_below(mm);
                 const uint64_t ioff = ibase + incl - len;
-                if (widx < A.walk_cap && ioff + len <= A.id_cap) {
-                    A.walk_attempt[widx] = a;
-                    A.walk_off[widx] = ioff;
-                    A.walk_len[widx] = len;
+                if (widx < S.walk_cap && ioff + len <= S.id_cap) {
+                    S.walk_attempt[widx] = a;
+                    S.walk_off[widx] = ioff;
+                    S.walk_len[widx] = len;
                     out_pos = ioff;
-                    if (MODE == SIA_NODES) {
-                        A.ids[out_pos++] = x1;
-                        if (A.cnt) atomicAdd(&A.cnt[x1], 1u);
+                    if (mode == SIA_NODES) {
+                        S.ids[out_pos++] = x1;
+                        if (S.cnt) atomicAdd(&S.cnt[x1], 1u);
                     }
                     phase = PH_EMIT;
                     cur = x1;
                     cnt = t;
                 } else {
-                    A.stats[ST_OVERFLOW] = 1;
+                    S.counters[ST_OVERFLOW] = 1;
+                    atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
                     active = false;
                 }
             }
+            hm &= ~mm;
         }
 
         // ---- stage 3: one live-edge evaluation per evaluating lane
@@ -285,25 +314,26 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
             uint32_t j = 0, u = 0;
             const bool live = select_edge(A.edges, R, static_cast<uint32_t>(word >> 32), j, u);
             ++evals;
+            bool done = false;
             if (phase == PH_DETECT) {
                 ++t;
                 if (!live) {
-                    ++dead;
-                    steps += t;
-                    active = false;
+                    atomicAdd(&acc[slot][1], 1ull);
+                    atomicAdd(&acc[slot][3], static_cast<unsigned long long>(t));
+                    done = true;
                 } else {
                     cur = u;
                 }
             } else if (!live) {  // re-walks retrace live edges only
-                ++faults;
-                active = false;
+                atomicAdd(&acc[slot][5], 1ull);
+                done = true;
             } else if (phase == PH_MU_POS) {
                 pb = u;
                 if (--cnt == 0) {
                     if (pa == pb) {  // the start lies on the cycle: mu = 0
-                        ++cycles;
-                        steps += lambda;
-                        active = false;
+                        atomicAdd(&acc[slot][2], 1ull);
+                        atomicAdd(&acc[slot][3], static_cast<unsigned long long>(lambda));
+                        done = true;
                     } else {
                         phase = PH_MU_A;
                     }
@@ -315,69 +345,116 @@ __global__ __launch_bounds__(256) void k_sample(const SampleArgs A)
                 pb = u;
                 ++cnt;
                 if (pa == pb) {  // first repeat after mu + lambda draws
-                    ++cycles;
-                    steps += static_cast<uint64_t>(cnt) + lambda;
-                    active = false;
+                    atomicAdd(&acc[slot][2], 1ull);
+                    atomicAdd(&acc[slot][3], static_cast<unsigned long long>(cnt) + lambda);
+                    done = true;
                 } else if (cnt > t) {
-                    ++faults;
-                    active = false;
+                    atomicAdd(&acc[slot][5], 1ull);
+                    done = true;
                 } else {
                     phase = PH_MU_A;
                 }
             } else {  // PH_EMIT
-                const uint32_t id = (MODE == SIA_EDGES) ? j : u;
-                A.ids[out_pos++] = id;
-                if (A.cnt) atomicAdd(&A.cnt[id], 1u);
+                const SlotDev &S = sl[slot];
+                const uint32_t id = (mode == SIA_EDGES) ? j : u;
+                S.ids[out_pos++] = id;
+                if (S.cnt) atomicAdd(&S.cnt[id], 1u);
                 cur = u;
-                if (--cnt == 0) active = false;
+                if (--cnt == 0) done = true;
+            }
+            if (done) {
+                atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
+                active = false;
             }
         }
     }
 
-    // ---- fold the lane counters into the global ones (one atomic per wave)
-    const uint64_t s_hits = wave_sum_u64(hits), s_dead = wave_sum_u64(dead),
-                   s_cyc = wave_sum_u64(cycles), s_steps = wave_sum_u64(steps),
-                   s_evals = wave_sum_u64(evals), s_faults = wave_sum_u64(faults);
-    if (lane == 0) {
-        auto add = [&](int slot, uint64_t v) {
-            if (v) atomicAdd(reinterpret_cast<unsigned long long *>(&A.stats[slot]),
-                             static_cast<unsigned long long>(v));
-        };
-        add(ST_HITS, s_hits);
-        add(ST_DEAD, s_dead);
-        add(ST_CYCLE, s_cyc);
-        add(ST_STEPS, s_steps);
-        add(ST_EVALS, s_evals);
-        add(ST_FAULTS, s_faults);
+    // ---- fold this workgroup's per-slot counters into the global ones
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < A.n_slots * 6; i += blockDim.x) {
+        const unsigned long long v = acc[i / 6][i % 6];
+        if (!v) continue;
+        const int map[6] = {ST_HITS, ST_DEAD, ST_CYCLE, ST_STEPS, ST_EVALS, ST_FAULTS};
+        atomicAdd(reinterpret_cast<unsigned long long *>(&sl[i / 6].counters[map[i % 6]]), v);
     }
 }
 
-__global__ void k_tag_sources(const int32_t *src, uint32_t n_src, NodeRec *nodes, uint32_t tag)
+__global__ void k_tag_sources(const int32_t *src, uint32_t n_src, NodeRec *nodes, uint32_t mask,
+                              int set)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_src) nodes[src[i]].tag = tag;
+    if (i < n_src) {
+        if (set) atomicOr(&nodes[src[i]].tag, mask);
+        else atomicAnd(&nodes[src[i]].tag, ~mask);
+    }
 }
 
-__global__ void k_clear_tags(NodeRec *nodes, uint64_t n)
-{
-    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (; i < n; i += stride) nodes[i].tag = 0;
-}
-
-template <int MODE>
 int persistent_blocks()
 {
     static int blocks = 0;
     if (!blocks) {
         int per_cu = 0;
-        SIA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sample<MODE>, 256, 0));
+        SIA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sample, 256, 0));
         blocks = std::max(1, per_cu) * device_cu_count();
     }
     return blocks;
 }
 
 }  // namespace
+
+size_t wave_table_bytes(uint32_t n_items)
+{
+    return 64 + sizeof(uint64_t) * (kMaxItems + 1) + sizeof(uint64_t) * kMaxItems +
+           sizeof(uint32_t) * kMaxItems;
+}
+
+void tag_sources(const sia_graph *g, const int32_t *d_src, uint32_t n_src, uint32_t mask, bool set,
+                 hipStream_t s)
+{
+    if (!n_src) return;
+    hipLaunchKernelGGL(k_tag_sources, dim3((n_src + 255) / 256), dim3(256), 0, s, d_src, n_src,
+                       const_cast<NodeRec *>(g->nodes.as<NodeRec>()), mask, set ? 1 : 0);
+    SIA_HIP(hipGetLastError());
+}
+
+void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
+                 const WaveItem *items, uint32_t n_items, void *d_table, hipStream_t s)
+{
+    SIA_REQUIRE(n_slots >= 1 && n_slots <= kMaxSlots + 1 && n_items >= 1 && n_items <= kMaxItems,
+                SIA_EINVAL, "bad wave shape");
+    // table layout: next counter (64 B), prefix[kMaxItems+1], local[kMaxItems], slot[kMaxItems]
+    struct {
+        uint64_t next[8];
+        uint64_t prefix[kMaxItems + 1];
+        uint64_t local[kMaxItems];
+        uint32_t slot[kMaxItems];
+    } h{};
+    uint64_t run = 0;
+    for (uint32_t i = 0; i < n_items; ++i) {
+        SIA_REQUIRE(items[i].slot < n_slots, SIA_EINVAL, "wave item names a missing slot");
+        h.prefix[i] = run;
+        h.local[i] = items[i].local_start;
+        h.slot[i] = items[i].slot;
+        run += items[i].count;
+    }
+    h.prefix[n_items] = run;
+    static_assert(sizeof(h) <= 64 + 8 * (kMaxItems + 1) + 8 * kMaxItems + 4 * kMaxItems + 64, "");
+    SIA_HIP(hipMemcpyAsync(d_table, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    char *base = static_cast<char *>(d_table);
+    WaveArgs A;
+    A.nodes = g->nodes.as<NodeRec>();
+    A.edges = g->edges.as<EdgeRec>();
+    A.slots = d_slots;
+    A.n_slots = n_slots;
+    A.n_items = n_items;
+    A.next = reinterpret_cast<uint64_t *>(base);
+    A.item_prefix = reinterpret_cast<const uint64_t *>(base + offsetof(decltype(h), prefix));
+    A.item_local = reinterpret_cast<const uint64_t *>(base + offsetof(decltype(h), local));
+    A.item_slot = reinterpret_cast<const uint32_t *>(base + offsetof(decltype(h), slot));
+    A.guard_evals = 3 * static_cast<uint64_t>(g->n) + 8;
+    hipLaunchKernelGGL(k_sample, dim3(persistent_blocks()), dim3(256), 0, s, A);
+    SIA_HIP(hipGetLastError());
+}
 
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
                          uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing,
@@ -386,28 +463,24 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
     Workspace &ws = g->ws;
     const uint32_t n_src = static_cast<uint32_t>(st.sorted.size());
     const uint64_t id_space = mode == SIA_EDGES ? static_cast<uint64_t>(g->m) : static_cast<uint64_t>(g->n);
+    const uint32_t mask = 1u << kSoloBit;
 
     ws.src_sorted.ensure(sizeof(int32_t) * n_src);
     ws.src_t.ensure(sizeof(uint32_t) * n_src);
     ws.bucket.ensure(sizeof(uint32_t) * st.bucket.size());
-    ws.counters.ensure(sizeof(uint64_t) * ST_COUNT);
+    ws.counters.ensure(sizeof(uint64_t) * ST_COUNT + sizeof(SlotDev) + wave_table_bytes(1) + 256);
     SIA_HIP(hipMemcpyAsync(ws.src_sorted.ptr, st.sorted.data(), sizeof(int32_t) * n_src,
                            hipMemcpyHostToDevice, s));
     SIA_HIP(hipMemcpyAsync(ws.src_t.ptr, st.t.data(), sizeof(uint32_t) * n_src,
                            hipMemcpyHostToDevice, s));
     SIA_HIP(hipMemcpyAsync(ws.bucket.ptr, st.bucket.data(), sizeof(uint32_t) * st.bucket.size(),
                            hipMemcpyHostToDevice, s));
-    // a fresh tag per query marks exactly its sources
-    if (++g->tag == 0) {
-        hipLaunchKernelGGL(k_clear_tags, dim3(device_cu_count() * 8), dim3(256), 0, s,
-                           g->nodes.as<NodeRec>(), static_cast<uint64_t>(g->n));
-        SIA_HIP(hipGetLastError());
-        g->tag = 1;
-    }
-    hipLaunchKernelGGL(k_tag_sources, dim3((n_src + 255) / 256), dim3(256), 0, s,
-                       ws.src_sorted.as<int32_t>(), n_src, g->nodes.as<NodeRec>(), g->tag);
-    SIA_HIP(hipGetLastError());
+    tag_sources(g, ws.src_sorted.as<int32_t>(), n_src, mask, true, s);
     if (count_ids) ws.cnt.ensure(sizeof(uint32_t) * std::max<uint64_t>(id_space, 1));
+    char *cbase = ws.counters.as<char>();
+    uint64_t *d_counters = reinterpret_cast<uint64_t *>(cbase);
+    SlotDev *d_slot = reinterpret_cast<SlotDev *>(cbase + sizeof(uint64_t) * ST_COUNT);
+    void *d_table = cbase + ((sizeof(uint64_t) * ST_COUNT + sizeof(SlotDev) + 255) / 256) * 256;
 
     if (!ws.walk_cap) {
         ws.walk_cap = std::min<uint64_t>(n_attempts, std::max<uint64_t>(1u << 20, n_attempts / 16));
@@ -415,35 +488,35 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
     }
 
     SampleResult res;
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    bool ok = false;
+    for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
         ws.walk_attempt.ensure(sizeof(uint64_t) * ws.walk_cap);
         ws.walk_off.ensure(sizeof(uint64_t) * ws.walk_cap);
         ws.walk_len.ensure(sizeof(uint32_t) * ws.walk_cap);
         ws.ids.ensure(sizeof(uint32_t) * ws.id_cap);
-        SIA_HIP(hipMemsetAsync(ws.counters.ptr, 0, sizeof(uint64_t) * ST_COUNT, s));
+        SIA_HIP(hipMemsetAsync(d_counters, 0, sizeof(uint64_t) * ST_COUNT, s));
         if (count_ids) SIA_HIP(hipMemsetAsync(ws.cnt.ptr, 0, sizeof(uint32_t) * id_space, s));
 
-        SampleArgs A;
-        A.nodes = g->nodes.as<NodeRec>();
-        A.edges = g->edges.as<EdgeRec>();
-        A.src_t = ws.src_t.as<uint32_t>();
-        A.bucket = ws.bucket.as<uint32_t>();
-        A.n_src = n_src;
-        A.bucket_shift = st.shift;
-        A.tag = g->tag;
-        A.n_ns = st.n_ns;
-        A.seed = seed;
-        A.attempt_offset = attempt_offset;
-        A.n_attempts = n_attempts;
-        A.guard_evals = 3 * static_cast<uint64_t>(g->n) + 8;
-        A.stats = ws.counters.as<uint64_t>();
-        A.walk_attempt = ws.walk_attempt.as<uint64_t>();
-        A.walk_off = ws.walk_off.as<uint64_t>();
-        A.walk_len = ws.walk_len.as<uint32_t>();
-        A.ids = ws.ids.as<uint32_t>();
-        A.cnt = count_ids ? ws.cnt.as<uint32_t>() : nullptr;
-        A.walk_cap = ws.walk_cap;
-        A.id_cap = ws.id_cap;
+        SlotDev S{};
+        S.seed = seed;
+        S.attempt_base = attempt_offset;
+        S.n_ns = st.n_ns;
+        S.src_t = ws.src_t.as<uint32_t>();
+        S.bucket = ws.bucket.as<uint32_t>();
+        S.n_src = n_src;
+        S.bucket_shift = st.shift;
+        S.tag_mask = mask;
+        S.mode = static_cast<uint32_t>(mode);
+        S.walk_attempt = ws.walk_attempt.as<uint64_t>();
+        S.walk_off = ws.walk_off.as<uint64_t>();
+        S.walk_len = ws.walk_len.as<uint32_t>();
+        S.ids = ws.ids.as<uint32_t>();
+        S.cnt = count_ids ? ws.cnt.as<uint32_t>() : nullptr;
+        S.walk_cap = ws.walk_cap;
+        S.id_cap = ws.id_cap;
+        S.counters = d_counters;
+        SIA_HIP(hipMemcpyAsync(d_slot, &S, sizeof(S), hipMemcpyHostToDevice, s));
+        const WaveItem item{0u, 0u, n_attempts};
 
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timing) {
@@ -451,24 +524,21 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
             SIA_HIP(hipEventCreate(&e1));
             SIA_HIP(hipEventRecord(e0, s));
         }
-        if (mode == SIA_EDGES)
-            hipLaunchKernelGGL(k_sample<SIA_EDGES>, dim3(persistent_blocks<SIA_EDGES>()), dim3(256),
-                               0, s, A);
-        else
-            hipLaunchKernelGGL(k_sample<SIA_NODES>, dim3(persistent_blocks<SIA_NODES>()), dim3(256),
-                               0, s, A);
-        SIA_HIP(hipGetLastError());
+        launch_wave(g, d_slot, 1, &item, 1, d_table, s);
         if (timing) SIA_HIP(hipEventRecord(e1, s));
 
         uint64_t h[ST_COUNT];
-        SIA_HIP(hipMemcpyAsync(h, ws.counters.ptr, sizeof(h), hipMemcpyDeviceToHost, s));
+        SIA_HIP(hipMemcpyAsync(h, d_counters, sizeof(h), hipMemcpyDeviceToHost, s));
         SIA_HIP(hipStreamSynchronize(s));
         if (timing) {
             SIA_HIP(hipEventElapsedTime(&res.ms, e0, e1));
             SIA_HIP(hipEventDestroy(e0));
             SIA_HIP(hipEventDestroy(e1));
         }
-        SIA_REQUIRE(h[ST_FAULTS] == 0, SIA_EDEVICE, "sampler consistency check failed");
+        if (h[ST_FAULTS]) {
+            tag_sources(g, ws.src_sorted.as<int32_t>(), n_src, mask, false, s);
+            throw Error{SIA_EDEVICE, "sampler consistency check failed"};
+        }
         res.walks = h[ST_WALKS];
         res.ids = h[ST_IDS];
         res.hits = h[ST_HITS];
@@ -476,12 +546,15 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
         res.cycles = h[ST_CYCLE];
         res.steps = h[ST_STEPS];
         res.evals = h[ST_EVALS];
-        if (!h[ST_OVERFLOW]) return res;
-        // The counters say exactly how much room the walks need: rerun once.
-        ws.walk_cap = std::max(ws.walk_cap, h[ST_WALKS]);
-        ws.id_cap = std::max(ws.id_cap, h[ST_IDS] + 1);
+        ok = !h[ST_OVERFLOW];
+        if (!ok) {  // the counters say exactly how much room the walks need: rerun once
+            ws.walk_cap = std::max(ws.walk_cap, h[ST_WALKS]);
+            ws.id_cap = std::max(ws.id_cap, h[ST_IDS] + 1);
+        }
     }
-    throw Error{SIA_EDEVICE, "sampler output did not fit after resizing"};
+    tag_sources(g, ws.src_sorted.as<int32_t>(), n_src, mask, false, s);
+    SIA_REQUIRE(ok, SIA_EDEVICE, "sampler output did not fit after resizing");
+    return res;
 }
 
 }  // namespace sia
