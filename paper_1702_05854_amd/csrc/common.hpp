@@ -73,8 +73,8 @@ struct Workspace {
     DevBuf walk_attempt, walk_off, walk_len, ids;  // sampler output
     DevBuf counters;                               // sampler / greedy scalars
     DevBuf src_sorted, src_t, bucket, bitmap;      // per-query source tables
-    DevBuf cnt, cur, inv, covered;                 // coverage + inverted index
-    DevBuf lvl1, lvl2, flag1, flag2, dirty1, dirty2, sel, gain, scan_tmp;
+    DevBuf cnt;                                    // coverage counts
+    DevBuf greedy, jobs;                           // greedy scratch + job table
     uint64_t walk_cap = 0, id_cap = 0;
 };
 
@@ -167,10 +167,35 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
 struct GreedyResult {
     float ms_count = 0.f, ms_greedy = 0.f;
 };
-// Inverted index + k greedy rounds over the walks held in ws (walk_off /
-// walk_len / ids, n_walks walks, n_ids ids).  counts_ready: ws.cnt already
-// holds the coverage counts; otherwise they are counted here.  Writes k
-// selected ids and gains to host arrays.
+
+// One greedy job: the kept walks of one query (device arrays) and where its
+// answer goes.  scratch holds greedy_scratch_bytes(id_space, n_walks, n_ids,
+// k) bytes of device memory owned by the caller.
+struct GreedyInput {
+    const uint64_t *walk_off = nullptr;
+    const uint32_t *walk_len = nullptr;
+    const uint32_t *ids = nullptr;
+    uint64_t id_space = 0, n_walks = 0, n_ids = 0;
+    int64_t k = 0;
+    uint32_t *cnt = nullptr;    // id_space coverage counts (device)
+    bool counts_ready = false;  // cnt already holds the counts; else counted here
+    void *scratch = nullptr;
+    int64_t *selected = nullptr;  // k entries each; host memory
+    uint64_t *gains = nullptr;
+    uint32_t rounds_seen = 0;     // progress bookkeeping
+};
+size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids, int64_t k);
+size_t greedy_job_table_bytes(uint32_t n_jobs);
+
+// Inverted index + k greedy rounds for every job, concurrently (blockIdx.y /
+// one workgroup per job).  d_job_table: greedy_job_table_bytes(jobs.size())
+// bytes of device memory.  Synchronises s; writes each job's selected ids and
+// gains to its host arrays.  Timing (if requested) covers all jobs.
+void run_greedy_jobs(std::vector<GreedyInput> &jobs, void *d_job_table, hipStream_t s, bool timing,
+                     GreedyResult *res);
+
+// A single job over the walks held in ws (walk_off / walk_len / ids, n_walks
+// walks, n_ids ids).  counts_ready: ws.cnt already holds the coverage counts.
 GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
                         int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s,
                         bool timing, bool counts_ready);

@@ -1,5 +1,5 @@
 // Coverage counts and greedy max-coverage (Algorithm 4 for edges, Algorithm 7
-// for nodes) over the kept walks.
+// for nodes) over the kept walks of one or more queries ("jobs").
 //
 //   cnt[id] = number of not-yet-covered walks holding id (Cov of one id),
 //             exact at all times; 0xFFFFFFFF once id is selected;
@@ -12,13 +12,19 @@
 // Lazy greedy.  Covering walks only lowers counts, so a key computed once is
 // an upper bound forever.  A pool holds the ids whose keys may be the
 // largest, and tau bounds the key of every id outside the pool.  One
-// workgroup then runs rounds back to back: recompute the pool's keys from the
-// exact counts, and if the best exceeds tau it is the true argmax of the
-// round -- record it, mark its walks covered and decrement the counts of
+// workgroup per job runs rounds back to back: recompute the pool's keys from
+// the exact counts, and while the best exceeds tau it is the true argmax of
+// the round -- record it, mark its walks covered and decrement the counts of
 // their ids.  When the best no longer exceeds tau, grid-wide kernels rebuild
-// the pool from the current counts (a histogram of counts chooses the
-// threshold; ties at the threshold are resolved by ascending id).  The
-// result is exactly the greedy of Algorithm 4 / 7.
+// the pool from the current counts: a histogram of counts, read on the
+// device, chooses the threshold, and ties at the threshold are taken by
+// ascending id (ordered compaction).  The result is exactly the greedy of
+// Algorithm 4 / 7.
+//
+// Every kernel takes the job table; blockIdx.y (blockIdx.x for the
+// one-workgroup kernels) selects the job, so the greedies of a batch of
+// queries advance in the same launches, and a job that is finished returns
+// at once.
 #include "common.hpp"
 
 #include <algorithm>
@@ -32,23 +38,68 @@ constexpr int kWave = 64;
 constexpr uint32_t kSelected = 0xFFFFFFFFu;
 constexpr uint32_t kScanTile = 4096;  // 256 threads x 16
 
-struct GreedyState {
-    uint32_t pool_n;    // ids in the pool
-    uint32_t next_id;   // first tied id left out of the pool (tie case)
-    uint32_t rounds;    // rounds completed so far
-    uint32_t error;
-};
-
 // Count histogram: counts 0..4095 exactly; above, 512 bins per octave.
 constexpr uint32_t kExact = 4096;
 constexpr uint32_t kPerOctave = 512;
 constexpr uint32_t kBins = kExact + 20 * kPerOctave;  // octaves 2^12 .. 2^31
+constexpr uint32_t kPoolTarget = 4096;
+constexpr uint32_t kPoolMax = 16384;
+constexpr int kLazyThreads = 1024;
+constexpr int kPlanThreads = 1024;
+
+enum PlanKind : uint32_t { PLAN_COLLECT = 0, PLAN_TIES = 1 };
+
+// Per-job state, written by the plan / collect / lazy kernels.
+struct GreedyState {
+    uint32_t rounds;    // rounds completed so far
+    uint32_t error;     // 2: more tied high counts than the pool holds
+    uint32_t plan;      // PlanKind of the current pool
+    uint32_t c_min;     // pool holds every unselected id with cnt >= c_min (0: none)
+    uint32_t pool_n;    // ids collected that way
+    uint32_t c_tie;     // PLAN_TIES: the tied count
+    uint32_t n_tie;     // PLAN_TIES: tied ids taken, lowest ids first
+    uint32_t leftover;  // PLAN_TIES: tied ids were left out
+    uint32_t next_id;   // PLAN_TIES: lowest tied id left out
+    uint32_t pad;
+    uint64_t tau;       // bound on keys outside the pool (without left-out ties)
+};
+
+struct GreedyJob {
+    uint32_t *cnt;
+    uint32_t *cur;      // id_space + 1
+    uint32_t *inv;      // n_ids
+    uint32_t *covered;  // n_walks
+    const uint64_t *walk_off;
+    const uint32_t *walk_len;
+    const uint32_t *ids;
+    uint64_t S;         // id space
+    uint64_t n_walks;
+    uint64_t n_ids;
+    int64_t k;
+    uint32_t need_count;
+    uint32_t pad;
+    int64_t *sel;       // k
+    uint64_t *gain;     // k
+    uint32_t *hist;     // kBins
+    uint32_t *pool;     // kPoolMax
+    uint32_t *tiles;    // ceil(S / kScanTile)
+    GreedyState *st;
+};
 
 __device__ __forceinline__ uint32_t count_bin(uint32_t c)
 {
     if (c < kExact) return c;
     const uint32_t L = 32u - __clz(c);  // bit length, 13..32
     return kExact + (L - 13u) * kPerOctave + ((c >> (L - 10u)) & (kPerOctave - 1u));
+}
+
+// lowest count of bin b
+__device__ __forceinline__ uint64_t bin_lo(uint32_t b)
+{
+    if (b < kExact) return b;
+    const uint32_t o = (b - kExact) / kPerOctave, r = (b - kExact) % kPerOctave;
+    const uint32_t L = o + 13;  // bit length
+    return (static_cast<uint64_t>(kPerOctave + r)) << (L - 10);
 }
 
 __device__ __forceinline__ uint64_t key_of(uint32_t c, uint32_t id)
@@ -68,14 +119,14 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
     return v;
 }
 
-__global__ void k_count(const uint32_t *ids, uint64_t n_ids, uint32_t *cnt)
+__device__ __forceinline__ bool job_done(const GreedyJob &J)
 {
-    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (; i < n_ids; i += stride) atomicAdd(&cnt[ids[i]], 1u);
+    return J.st->error != 0 || static_cast<int64_t>(J.st->rounds) >= J.k;
 }
 
-// ---- inclusive scan of cnt[0..S) into out[0..S) (uint32; totals < 2^32)
+__device__ __forceinline__ uint64_t n_tiles_of(uint64_t S) { return (S + kScanTile - 1) / kScanTile; }
+
+// block-wide exclusive scan of one value per thread (256 threads)
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *sh, uint32_t &total)
 {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -97,166 +148,298 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *sh
     return before + x - v;
 }
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *in, uint64_t count,
-                                                     uint32_t *tile_sums)
-{
-    __shared__ uint32_t sh[4];
-    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
-    uint32_t s = 0;
-    for (int i = 0; i < 16; ++i)
-        if (base + i < count) s += in[base + i];
-    uint32_t total;
-    block_excl_scan_256(s, sh, total);
-    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(256) void k_scan_tiles(uint32_t *tile_sums, uint64_t n_tiles)
+// exclusive scan of tiles[0 .. n) in place, one 256-thread workgroup
+__device__ void scan_tiles_256(uint32_t *tiles, uint64_t n)
 {
     __shared__ uint32_t sh[4];
     uint32_t carry = 0;
-    for (uint64_t base = 0; base < n_tiles; base += 256) {
+    for (uint64_t base = 0; base < n; base += 256) {
         const uint64_t i = base + threadIdx.x;
-        const uint32_t v = i < n_tiles ? tile_sums[i] : 0u;
+        const uint32_t v = i < n ? tiles[i] : 0u;
         uint32_t total;
         const uint32_t ex = block_excl_scan_256(v, sh, total);
-        if (i < n_tiles) tile_sums[i] = carry + ex;
+        if (i < n) tiles[i] = carry + ex;
         carry += total;
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_down(const uint32_t *in, uint64_t count,
-                                                   const uint32_t *tile_offs, uint32_t *out)
+// ---------------------------------------------------------------- set-up
+// Zero the per-job state, histogram, covered flags and (when the job counts
+// here) the counts.  A kernel rather than memsets, so a captured graph holds
+// no memset nodes.
+__global__ void k_init(const GreedyJob *jobs)
+{
+    const GreedyJob J = jobs[blockIdx.y];
+    const uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = t; i < J.n_walks; i += stride) J.covered[i] = 0;
+    if (J.need_count)
+        for (uint64_t i = t; i < J.S; i += stride) J.cnt[i] = 0;
+    for (uint64_t i = t; i < kBins; i += stride) J.hist[i] = 0;
+    if (t == 0) *J.st = GreedyState{};
+}
+
+__global__ void k_count(const GreedyJob *jobs)
+{
+    const GreedyJob J = jobs[blockIdx.y];
+    if (!J.need_count) return;
+    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (; i < J.n_ids; i += stride) atomicAdd(&J.cnt[J.ids[i]], 1u);
+}
+
+// ---------------------------------------------------------------- inverted index
+// cur = inclusive prefix sum of cnt (tiles of 4096 ids), cur[S] = n_ids.
+__global__ __launch_bounds__(256) void k_scan_reduce(const GreedyJob *jobs)
 {
     __shared__ uint32_t sh[4];
+    const GreedyJob J = jobs[blockIdx.y];
+    if (blockIdx.x >= n_tiles_of(J.S)) return;  // uniform per block
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
+    uint32_t s = 0;
+    for (int i = 0; i < 16; ++i)
+        if (base + i < J.S) s += J.cnt[base + i];
+    uint32_t total;
+    block_excl_scan_256(s, sh, total);
+    if (threadIdx.x == 0) J.tiles[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const GreedyJob *jobs)
+{
+    const GreedyJob J = jobs[blockIdx.y];
+    scan_tiles_256(J.tiles, n_tiles_of(J.S));
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const GreedyJob *jobs)
+{
+    __shared__ uint32_t sh[4];
+    const GreedyJob J = jobs[blockIdx.y];
+    if (blockIdx.x >= n_tiles_of(J.S)) return;
     const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
     uint32_t v[16];
     uint32_t s = 0;
     for (int i = 0; i < 16; ++i) {
-        v[i] = base + i < count ? in[base + i] : 0u;
+        v[i] = base + i < J.S ? J.cnt[base + i] : 0u;
         s += v[i];
     }
     uint32_t total;
-    uint32_t run = tile_offs[blockIdx.x] + block_excl_scan_256(s, sh, total);
+    uint32_t run = J.tiles[blockIdx.x] + block_excl_scan_256(s, sh, total);
     for (int i = 0; i < 16; ++i) {
         run += v[i];
-        if (base + i < count) out[base + i] = run;
+        if (base + i < J.S) J.cur[base + i] = run;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) J.cur[J.S] = static_cast<uint32_t>(J.n_ids);
 }
 
-// ---- inverted index: cur[id] counts down from the inclusive prefix sum to
-// the start of id's list; walk w is listed under each of its ids.  One wave
-// per walk.
-__global__ __launch_bounds__(256) void k_fill(const uint64_t *walk_off, const uint32_t *walk_len,
-                                              uint64_t n_walks, const uint32_t *ids, uint32_t *cur,
-                                              uint32_t *inv)
+// cur[id] counts down from the inclusive prefix sum to the start of id's
+// list; walk w is listed under each of its ids.  One wave per walk.
+__global__ __launch_bounds__(256) void k_fill(const GreedyJob *jobs)
 {
+    const GreedyJob J = jobs[blockIdx.y];
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
     for (uint64_t w = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
-         w < n_walks; w += waves) {
-        const uint64_t o = walk_off[w];
-        const uint32_t L = walk_len[w];
+         w < J.n_walks; w += waves) {
+        const uint64_t o = J.walk_off[w];
+        const uint32_t L = J.walk_len[w];
         for (uint32_t e = lane; e < L; e += kWave) {
-            const uint32_t p = atomicSub(&cur[ids[o + e]], 1u) - 1u;
-            inv[p] = static_cast<uint32_t>(w);
+            const uint32_t p = atomicSub(&J.cur[J.ids[o + e]], 1u) - 1u;
+            J.inv[p] = static_cast<uint32_t>(w);
         }
     }
 }
 
-// ---- pool rebuild
-__global__ __launch_bounds__(1024) void k_hist(const uint32_t *cnt, uint64_t S, uint32_t *hist)
+// ---------------------------------------------------------------- pool rebuild
+__global__ __launch_bounds__(1024) void k_hist(const GreedyJob *jobs)
 {
     __shared__ uint32_t h[kBins];
+    const GreedyJob J = jobs[blockIdx.y];
+    if (job_done(J)) return;  // uniform per block
     for (uint32_t i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
     uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (; i < S; i += stride) {
-        const uint32_t c = cnt[i];
+    for (; i < J.S; i += stride) {
+        const uint32_t c = J.cnt[i];
         if (c != kSelected) atomicAdd(&h[count_bin(c)], 1u);
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < kBins; b += blockDim.x)
-        if (h[b]) atomicAdd(&hist[b], h[b]);
+        if (h[b]) atomicAdd(&J.hist[b], h[b]);
 }
 
-// Pool += every unselected id with cnt >= c_min (c_min >= 1).
-__global__ void k_collect(const uint32_t *cnt, uint64_t S, uint32_t c_min, uint32_t *pool,
-                          GreedyState *st)
+// Choose the next pool from the histogram (and clear it for the next
+// rebuild).  b* = the highest bin with at least kPoolTarget unselected ids at
+// or above it (bin 0 if there are fewer).  If those ids fit the pool and b* >
+// 0, the pool is every id with cnt >= the lowest count of b*.  Otherwise b*
+// is an exact count c (else: error) and the pool is every id above c plus the
+// lowest-id ones at c, up to kPoolTarget.  One workgroup per job.
+__global__ __launch_bounds__(kPlanThreads) void k_plan(const GreedyJob *jobs)
 {
-    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (; i < S; i += stride) {
-        const uint32_t c = cnt[i];
-        if (c != kSelected && c >= c_min) pool[atomicAdd(&st->pool_n, 1u)] = static_cast<uint32_t>(i);
+    constexpr uint32_t kPer = (kBins + kPlanThreads - 1) / kPlanThreads;
+    constexpr int kWaves = kPlanThreads / kWave;
+    __shared__ uint32_t h[kBins];
+    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t found, bstar, ab_sh;
+    const GreedyJob J = jobs[blockIdx.x];
+    if (job_done(J)) return;  // uniform per block
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (uint32_t b = threadIdx.x; b < kBins; b += kPlanThreads) {
+        h[b] = J.hist[b];
+        J.hist[b] = 0;
+    }
+    if (threadIdx.x == 0) found = 0;
+    __syncthreads();
+    // thread t owns bins [t*kPer, t*kPer + kPer)
+    const uint32_t b0 = threadIdx.x * kPer;
+    uint32_t mine = 0;
+    for (uint32_t i = 0; i < kPer; ++i)
+        if (b0 + i < kBins) mine += h[b0 + i];
+    uint32_t x = mine;  // inclusive suffix sum within the wave
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_down(x, d, kWave);
+        if (lane + d < kWave) x += o;
+    }
+    if (lane == 0) wsum[wid] = x;
+    __syncthreads();
+    uint32_t above = x - mine;  // ids in bins >= b0 + kPer
+    for (int w = wid + 1; w < kWaves; ++w) above += wsum[w];
+    // the suffix sum crosses kPoolTarget at exactly one bin (if at all)
+    for (int i = static_cast<int>(kPer) - 1; i >= 0; --i) {
+        const uint32_t b = b0 + i;
+        if (b >= kBins) continue;
+        if (above < kPoolTarget && above + h[b] >= kPoolTarget) {
+            found = 1;
+            bstar = b;
+            ab_sh = above;
+        }
+        above += h[b];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    uint32_t b = 0, ab = above - h[0];  // thread 0: above == every unselected id
+    if (found) {
+        b = bstar;
+        ab = ab_sh;
+    }
+    const uint64_t ge = static_cast<uint64_t>(ab) + h[b];
+    GreedyState *st = J.st;
+    st->pool_n = 0;
+    st->next_id = 0;
+    if (ge <= kPoolMax && b > 0) {
+        const uint64_t c_lo = bin_lo(b);
+        st->plan = PLAN_COLLECT;
+        st->c_min = static_cast<uint32_t>(c_lo);
+        st->n_tie = 0;
+        st->leftover = 0;
+        st->tau = (c_lo << 32) | 0xFFFFFFFFull;  // bound for every count <= c_lo - 1
+    } else if (b < kExact) {
+        const uint32_t c = b;
+        const uint32_t R = static_cast<uint32_t>(std::min<uint64_t>(kPoolTarget, ge) - ab);
+        st->plan = PLAN_TIES;
+        st->c_min = ab ? c + 1 : 0;
+        st->c_tie = c;
+        st->n_tie = R;
+        st->leftover = ge > static_cast<uint64_t>(ab) + R;
+        st->tau = c ? (static_cast<uint64_t>(c) << 32) | 0xFFFFFFFFull : 0ull;
+    } else {
+        st->error = 2;
     }
 }
 
-// Ties: per tile of 4096 ids, how many have cnt == c.
-__global__ __launch_bounds__(256) void k_tie_count(const uint32_t *cnt, uint64_t S, uint32_t c,
-                                                   uint32_t *tile_counts)
+// Pool += every unselected id with cnt >= c_min.
+__global__ void k_collect(const GreedyJob *jobs)
 {
-    __shared__ uint32_t sh[4];
-    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
-    uint32_t k = 0;
-    for (int i = 0; i < 16; ++i)
-        if (base + i < S && cnt[base + i] == c) ++k;
-    uint32_t total;
-    block_excl_scan_256(k, sh, total);
-    if (threadIdx.x == 0) tile_counts[blockIdx.x] = total;
+    const GreedyJob J = jobs[blockIdx.y];
+    if (job_done(J)) return;
+    const uint32_t c_min = J.st->c_min;
+    if (c_min == 0) return;
+    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (; i < J.S; i += stride) {
+        const uint32_t c = J.cnt[i];
+        if (c != kSelected && c >= c_min) J.pool[atomicAdd(&J.st->pool_n, 1u)] = static_cast<uint32_t>(i);
+    }
 }
 
-// Ties: the first R ids (ascending) with cnt == c go to pool[pool_base ..];
-// the (R+1)-th one is recorded in st->next_id.
-__global__ __launch_bounds__(256) void k_tie_emit(const uint32_t *cnt, uint64_t S, uint32_t c,
-                                                  const uint32_t *tile_offs, uint32_t R,
-                                                  uint32_t pool_base, uint32_t *pool, GreedyState *st)
+// Ties: per tile of 4096 ids, how many have cnt == c_tie.
+__global__ __launch_bounds__(256) void k_tie_count(const GreedyJob *jobs)
 {
     __shared__ uint32_t sh[4];
-    if (tile_offs[blockIdx.x] > R) return;  // uniform per block
+    const GreedyJob J = jobs[blockIdx.y];
+    if (blockIdx.x >= n_tiles_of(J.S) || job_done(J) || J.st->plan != PLAN_TIES) return;
+    const uint32_t c = J.st->c_tie;
     const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
     uint32_t k = 0;
     for (int i = 0; i < 16; ++i)
-        if (base + i < S && cnt[base + i] == c) ++k;
+        if (base + i < J.S && J.cnt[base + i] == c) ++k;
     uint32_t total;
-    uint32_t q = tile_offs[blockIdx.x] + block_excl_scan_256(k, sh, total);
+    block_excl_scan_256(k, sh, total);
+    if (threadIdx.x == 0) J.tiles[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_tie_scan(const GreedyJob *jobs)
+{
+    const GreedyJob J = jobs[blockIdx.y];
+    if (job_done(J) || J.st->plan != PLAN_TIES) return;  // uniform per block
+    scan_tiles_256(J.tiles, n_tiles_of(J.S));
+}
+
+// Ties: the first n_tie ids (ascending) with cnt == c_tie go to the pool after
+// the collected ones; the next tied id is recorded in next_id.
+__global__ __launch_bounds__(256) void k_tie_emit(const GreedyJob *jobs)
+{
+    __shared__ uint32_t sh[4];
+    const GreedyJob J = jobs[blockIdx.y];
+    if (blockIdx.x >= n_tiles_of(J.S) || job_done(J) || J.st->plan != PLAN_TIES) return;
+    const uint32_t R = J.st->n_tie, c = J.st->c_tie;
+    if (J.tiles[blockIdx.x] > R) return;  // uniform per block
+    const uint32_t pool_base = J.st->pool_n;  // complete: written by an earlier kernel
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
+    uint32_t k = 0;
+    for (int i = 0; i < 16; ++i)
+        if (base + i < J.S && J.cnt[base + i] == c) ++k;
+    uint32_t total;
+    uint32_t q = J.tiles[blockIdx.x] + block_excl_scan_256(k, sh, total);
     for (int i = 0; i < 16; ++i) {
-        if (base + i < S && cnt[base + i] == c) {
-            if (q < R) pool[pool_base + q] = static_cast<uint32_t>(base + i);
-            else if (q == R) st->next_id = static_cast<uint32_t>(base + i);
+        if (base + i < J.S && J.cnt[base + i] == c) {
+            if (q < R) J.pool[pool_base + q] = static_cast<uint32_t>(base + i);
+            else if (q == R) J.st->next_id = static_cast<uint32_t>(base + i);
             ++q;
         }
     }
 }
 
-// ---- lazy rounds: one workgroup, rounds [st->rounds, k) while certified
-constexpr int kLazyThreads = 1024;
-
+// ---------------------------------------------------------------- lazy rounds
 __device__ __forceinline__ uint32_t load_count(const uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kLazyThreads) void k_lazy(uint32_t *cnt, const uint32_t *pool,
-                                                       uint64_t tau, int64_t k, int64_t *sel,
-                                                       uint64_t *gain, const uint32_t *cur,
-                                                       const uint32_t *inv, const uint64_t *walk_off,
-                                                       const uint32_t *walk_len, const uint32_t *ids,
-                                                       uint32_t *covered, GreedyState *st)
+// One workgroup per job: rounds [rounds, k) while the pool certifies the pick.
+__global__ __launch_bounds__(kLazyThreads) void k_lazy(const GreedyJob *jobs)
 {
     __shared__ uint64_t sh[kLazyThreads / kWave];
     __shared__ uint32_t queue[kLazyThreads];
     __shared__ uint32_t qn;
+    const GreedyJob J = jobs[blockIdx.x];
+    if (job_done(J)) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     constexpr int kWaves = kLazyThreads / kWave;
-    const uint32_t P = st->pool_n;
+    GreedyState *st = J.st;
+    const bool ties = st->plan == PLAN_TIES;
+    const uint32_t P = st->pool_n + (ties ? st->n_tie : 0u);
+    const uint64_t tau = ties && st->leftover
+                             ? ((static_cast<uint64_t>(st->c_tie) + 1) << 32) | (0xFFFFFFFFu - st->next_id)
+                             : st->tau;
     int64_t r = st->rounds;
-    for (; r < k; ++r) {
+    for (; r < J.k; ++r) {
         // exact keys of the pool; the largest is this round's pick if it beats tau
         uint64_t best = 0;
         for (uint32_t i = threadIdx.x; i < P; i += kLazyThreads) {
-            const uint32_t id = pool[i];
-            const uint64_t key = key_of(load_count(&cnt[id]), id);
+            const uint32_t id = J.pool[i];
+            const uint64_t key = key_of(load_count(&J.cnt[id]), id);
             best = key > best ? key : best;
         }
         best = wave_max_u64(best);
@@ -269,27 +452,27 @@ __global__ __launch_bounds__(kLazyThreads) void k_lazy(uint32_t *cnt, const uint
         const uint32_t id = 0xFFFFFFFFu - static_cast<uint32_t>(best);
         const uint32_t g = static_cast<uint32_t>(best >> 32) - 1u;
         if (threadIdx.x == 0) {
-            sel[r] = id;
-            gain[r] = g;
-            atomicExch(&cnt[id], kSelected);
+            J.sel[r] = id;
+            J.gain[r] = g;
+            atomicExch(&J.cnt[id], kSelected);
         }
         if (g > 0) {
-            const uint32_t lo = cur[id], hi = cur[id + 1];
+            const uint32_t lo = J.cur[id], hi = J.cur[id + 1];
             for (uint32_t b0 = lo; b0 < hi; b0 += kLazyThreads) {
                 const uint32_t p = b0 + threadIdx.x;
                 if (p < hi) {
-                    const uint32_t w = inv[p];
-                    if (atomicExch(&covered[w], 1u) == 0u) queue[atomicAdd(&qn, 1u)] = w;
+                    const uint32_t w = J.inv[p];
+                    if (atomicExch(&J.covered[w], 1u) == 0u) queue[atomicAdd(&qn, 1u)] = w;
                 }
                 __syncthreads();
                 const uint32_t n = qn;
                 for (uint32_t qi = wid; qi < n; qi += kWaves) {
                     const uint32_t w = queue[qi];
-                    const uint64_t o = walk_off[w];
-                    const uint32_t L = walk_len[w];
+                    const uint64_t o = J.walk_off[w];
+                    const uint32_t L = J.walk_len[w];
                     for (uint32_t e = lane; e < L; e += kWave) {
-                        const uint32_t x = ids[o + e];
-                        if (x != id) atomicSub(&cnt[x], 1u);
+                        const uint32_t x = J.ids[o + e];
+                        if (x != id) atomicSub(&J.cnt[x], 1u);
                     }
                 }
                 __syncthreads();
@@ -309,148 +492,167 @@ unsigned grid_for(uint64_t items, unsigned block, unsigned cap)
     return static_cast<unsigned>(std::min<uint64_t>(g, cap));
 }
 
-}  // namespace
+uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
 
-namespace {
-
-uint64_t bin_lo(uint32_t b)
+// Carve a job's buffers from its scratch block (layout of greedy_scratch_bytes).
+GreedyJob carve(const GreedyInput &g)
 {
-    if (b < kExact) return b;
-    const uint32_t o = (b - kExact) / kPerOctave, r = (b - kExact) % kPerOctave;
-    const uint32_t L = o + 13;  // bit length
-    return (static_cast<uint64_t>(kPerOctave + r)) << (L - 10);
+    char *p = static_cast<char *>(g.scratch);
+    const uint64_t S = g.id_space;
+    GreedyJob J{};
+    auto take = [&p](uint64_t bytes) {
+        char *q = p;
+        p += al256(bytes);
+        return q;
+    };
+    J.cur = reinterpret_cast<uint32_t *>(take(4 * (S + 1)));
+    J.inv = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_ids, 1)));
+    J.covered = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
+    J.sel = reinterpret_cast<int64_t *>(take(8 * g.k));
+    J.gain = reinterpret_cast<uint64_t *>(take(8 * g.k));
+    J.hist = reinterpret_cast<uint32_t *>(take(4 * kBins));
+    J.pool = reinterpret_cast<uint32_t *>(take(4 * kPoolMax));
+    J.tiles = reinterpret_cast<uint32_t *>(take(4 * ((S + kScanTile - 1) / kScanTile)));
+    J.st = reinterpret_cast<GreedyState *>(take(sizeof(GreedyState)));
+    J.cnt = g.cnt;
+    J.walk_off = g.walk_off;
+    J.walk_len = g.walk_len;
+    J.ids = g.ids;
+    J.S = S;
+    J.n_walks = g.n_walks;
+    J.n_ids = g.n_ids;
+    J.k = g.k;
+    J.need_count = g.counts_ready ? 0u : 1u;
+    return J;
 }
 
-constexpr uint64_t kPoolTarget = 4096;
-constexpr uint64_t kPoolMax = 16384;
-
 }  // namespace
 
-GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
-                        int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s, bool timing,
-                        bool counts_ready)
+// ---------------------------------------------------------------- host side
+size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids, int64_t k)
 {
-    SIA_REQUIRE(n_ids < 0xFFFFFFFFull && n_walks < 0xFFFFFFFFull, SIA_EINVAL,
-                "too many walk ids for 32-bit inverted index offsets");
-    const uint64_t S = static_cast<uint64_t>(id_space);
-    const uint64_t n_tiles = (S + kScanTile - 1) / kScanTile;
-    const int cus = device_cu_count();
+    const uint64_t S = id_space;
+    return al256(4 * (S + 1)) + al256(4 * std::max<uint64_t>(n_ids, 1)) +
+           al256(4 * std::max<uint64_t>(n_walks, 1)) + 2 * al256(8 * static_cast<uint64_t>(k)) +
+           al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile)) +
+           al256(sizeof(GreedyState));
+}
 
-    ws.cnt.ensure(sizeof(uint32_t) * S);
-    ws.cur.ensure(sizeof(uint32_t) * (S + 1));
-    ws.inv.ensure(sizeof(uint32_t) * std::max<uint64_t>(n_ids, 1));
-    ws.covered.ensure(sizeof(uint32_t) * std::max<uint64_t>(n_walks, 1));
-    ws.lvl1.ensure(sizeof(uint32_t) * (kBins + kPoolMax));   // histogram + pool
-    ws.sel.ensure(sizeof(int64_t) * k);
-    ws.gain.ensure(sizeof(uint64_t) * k);
-    ws.scan_tmp.ensure(sizeof(uint32_t) * n_tiles + sizeof(GreedyState) + 64);
-    uint32_t *tiles = ws.scan_tmp.as<uint32_t>();
-    GreedyState *st = reinterpret_cast<GreedyState *>(
-        ws.scan_tmp.as<char>() + ((sizeof(uint32_t) * n_tiles + 63) / 64) * 64);
-    uint32_t *hist = ws.lvl1.as<uint32_t>();
-    uint32_t *pool = hist + kBins;
-    uint32_t *cnt = ws.cnt.as<uint32_t>(), *cur = ws.cur.as<uint32_t>();
-    const uint32_t *ids = ws.ids.as<uint32_t>();
+size_t greedy_job_table_bytes(uint32_t n_jobs) { return sizeof(GreedyJob) * n_jobs; }
+
+void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_t s, bool timing,
+                     GreedyResult *res)
+{
+    const uint32_t Q = static_cast<uint32_t>(in.size());
+    if (!Q) return;
+    uint64_t max_S = 0, max_walks = 0, max_ids = 0;
+    std::vector<GreedyJob> jobs(Q);
+    for (uint32_t q = 0; q < Q; ++q) {
+        GreedyInput &g = in[q];
+        SIA_REQUIRE(g.n_ids < 0xFFFFFFFFull && g.n_walks < 0xFFFFFFFFull, SIA_EINVAL,
+                    "too many walk ids for 32-bit inverted index offsets");
+        SIA_REQUIRE(g.k >= 1 && static_cast<uint64_t>(g.k) <= g.id_space, SIA_EINVAL,
+                    "k must be in [1, id space]");
+        SIA_REQUIRE(g.cnt && g.scratch && g.selected && g.gains, SIA_EINVAL, "greedy job buffers");
+        jobs[q] = carve(g);
+        g.rounds_seen = 0;
+        max_S = std::max(max_S, g.id_space);
+        max_walks = std::max(max_walks, g.n_walks);
+        max_ids = std::max(max_ids, g.n_ids);
+    }
+    const unsigned cus = static_cast<unsigned>(device_cu_count());
+    const unsigned tiles = static_cast<unsigned>((max_S + kScanTile - 1) / kScanTile);
+    GreedyJob *d_jobs = static_cast<GreedyJob *>(d_job_table);
 
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (timing) {
         for (auto &e : ev) SIA_HIP(hipEventCreate(&e));
         SIA_HIP(hipEventRecord(ev[0], s));
     }
-    // counts (unless the sampler already produced them)
-    if (!counts_ready) SIA_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * S, s));
-    if (n_ids && !counts_ready) {
-        hipLaunchKernelGGL(k_count, dim3(grid_for(n_ids, 256, cus * 64)), dim3(256), 0, s, ids,
-                           n_ids, cnt);
-        SIA_HIP(hipGetLastError());
-    }
-    // inverted index
-    hipLaunchKernelGGL(k_scan_reduce, dim3(n_tiles), dim3(256), 0, s, cnt, S, tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(256), 0, s, tiles, n_tiles);
-    hipLaunchKernelGGL(k_scan_down, dim3(n_tiles), dim3(256), 0, s, cnt, S, tiles, cur);
+    SIA_HIP(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(GreedyJob) * Q, hipMemcpyHostToDevice, s));
+    const uint64_t init_items = std::max<uint64_t>({max_walks, max_S, kBins});
+    hipLaunchKernelGGL(k_init, dim3(grid_for(init_items, 256, cus * 8), Q), dim3(256), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_count, dim3(grid_for(max_ids, 256, cus * 16), Q), dim3(256), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1, Q), dim3(256), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_scan_down, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(max_walks * kWave, 256, cus * 32), Q), dim3(256), 0, s,
+                       d_jobs);
     SIA_HIP(hipGetLastError());
-    SIA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(cur + S), static_cast<int>(n_ids), 1, s));
-    if (n_walks) {
-        hipLaunchKernelGGL(k_fill, dim3(grid_for(n_walks * kWave, 256, cus * 32)), dim3(256), 0, s,
-                           ws.walk_off.as<uint64_t>(), ws.walk_len.as<uint32_t>(), n_walks, ids,
-                           cur, ws.inv.as<uint32_t>());
-        SIA_HIP(hipGetLastError());
-    }
-    SIA_HIP(hipMemsetAsync(ws.covered.ptr, 0, sizeof(uint32_t) * std::max<uint64_t>(n_walks, 1), s));
-    SIA_HIP(hipMemsetAsync(st, 0, sizeof(GreedyState), s));
     if (timing) SIA_HIP(hipEventRecord(ev[1], s));
 
-    std::vector<uint32_t> h(kBins);
-    GreedyState hs{};
-    int64_t done = 0;
-    while (done < k) {
-        // ---- rebuild the pool from the current counts
-        SIA_HIP(hipMemsetAsync(hist, 0, sizeof(uint32_t) * kBins, s));
-        hipLaunchKernelGGL(k_hist, dim3(cus), dim3(1024), 0, s, cnt, S, hist);
-        SIA_HIP(hipGetLastError());
-        SIA_HIP(hipMemcpyAsync(h.data(), hist, sizeof(uint32_t) * kBins, hipMemcpyDeviceToHost, s));
-        SIA_HIP(hipStreamSynchronize(s));
-        // highest bin b* with at least kPoolTarget ids at or above it (or bin 0)
-        uint64_t above = 0;
-        int64_t bstar = kBins - 1;
-        for (; bstar > 0; --bstar) {
-            if (above + h[bstar] >= kPoolTarget) break;
-            above += h[bstar];
-        }
-        const uint64_t ge = above + h[bstar];
-        uint64_t tau;
-        uint32_t pool_n;
-        SIA_HIP(hipMemsetAsync(st, 0, offsetof(GreedyState, rounds), s));  // pool_n, next_id
-        if (ge <= kPoolMax && bstar > 0) {
-            const uint64_t c_lo = bin_lo(static_cast<uint32_t>(bstar));
-            hipLaunchKernelGGL(k_collect, dim3(cus * 8), dim3(256), 0, s, cnt, S,
-                               static_cast<uint32_t>(c_lo), pool, st);
-            tau = (c_lo << 32) | 0xFFFFFFFFull;  // bound for every count <= c_lo - 1
-            pool_n = static_cast<uint32_t>(ge);
-        } else {
-            // ties at an exact count c: all ids above c, then the lowest-id ones at c
-            SIA_REQUIRE(bstar < static_cast<int64_t>(kExact), SIA_EDEVICE,
-                        "greedy pool: more tied high counts than the pool holds");
-            const uint32_t c = static_cast<uint32_t>(bstar);
-            const uint32_t R = static_cast<uint32_t>(std::min<uint64_t>(kPoolTarget, ge) - above);
-            if (above) {
-                hipLaunchKernelGGL(k_collect, dim3(cus * 8), dim3(256), 0, s, cnt, S, c + 1, pool, st);
-            }
-            hipLaunchKernelGGL(k_tie_count, dim3(n_tiles), dim3(256), 0, s, cnt, S, c, tiles);
-            hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(256), 0, s, tiles, n_tiles);
-            hipLaunchKernelGGL(k_tie_emit, dim3(n_tiles), dim3(256), 0, s, cnt, S, c, tiles, R,
-                               static_cast<uint32_t>(above), pool, st);
+    // pool rebuilds + certified rounds; groups of generations between host checks
+    const unsigned hist_blocks =
+        std::min(grid_for(max_S, 1024, cus), std::max(1u, cus / std::min<unsigned>(Q, 8)));
+    const unsigned collect_blocks = grid_for(max_S, 256, cus * 4);
+    std::vector<GreedyState> hs(Q);
+    for (int group = 1;; group = std::min(group * 2, 8)) {
+        for (int gen = 0; gen < group; ++gen) {
+            hipLaunchKernelGGL(k_hist, dim3(hist_blocks, Q), dim3(1024), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_plan, dim3(Q), dim3(kPlanThreads), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_collect, dim3(collect_blocks, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_tie_count, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_tie_scan, dim3(1, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_tie_emit, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_lazy, dim3(Q), dim3(kLazyThreads), 0, s, d_jobs);
             SIA_HIP(hipGetLastError());
-            SIA_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-            SIA_HIP(hipStreamSynchronize(s));
-            pool_n = static_cast<uint32_t>(above + R);
-            tau = ge > above + R ? ((static_cast<uint64_t>(c) + 1) << 32) | (0xFFFFFFFFu - hs.next_id)
-                                 : (c ? (static_cast<uint64_t>(c) << 32) | 0xFFFFFFFFull : 0ull);
-            SIA_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(&st->pool_n),
-                                      static_cast<int>(pool_n), 1, s));
         }
-        SIA_HIP(hipGetLastError());
-        // ---- certified rounds, back to back
-        hipLaunchKernelGGL(k_lazy, dim3(1), dim3(kLazyThreads), 0, s, cnt, pool, tau, k,
-                           ws.sel.as<int64_t>(), ws.gain.as<uint64_t>(), cur,
-                           ws.inv.as<uint32_t>(), ws.walk_off.as<uint64_t>(),
-                           ws.walk_len.as<uint32_t>(), ids, ws.covered.as<uint32_t>(), st);
-        SIA_HIP(hipGetLastError());
-        SIA_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+        for (uint32_t q = 0; q < Q; ++q)
+            SIA_HIP(hipMemcpyAsync(&hs[q], jobs[q].st, sizeof(GreedyState), hipMemcpyDeviceToHost, s));
         SIA_HIP(hipStreamSynchronize(s));
-        SIA_REQUIRE(static_cast<int64_t>(hs.rounds) > done, SIA_EDEVICE, "greedy made no progress");
-        done = hs.rounds;
+        bool all = true;
+        for (uint32_t q = 0; q < Q; ++q) {
+            SIA_REQUIRE(hs[q].error == 0, SIA_EDEVICE,
+                        "greedy pool: more tied high counts than the pool holds");
+            const bool finished = static_cast<int64_t>(hs[q].rounds) >= in[q].k;
+            // every rebuild certifies at least one pick, so an unfinished job
+            // always advances
+            SIA_REQUIRE(finished || hs[q].rounds > in[q].rounds_seen, SIA_EDEVICE,
+                        "greedy made no progress");
+            in[q].rounds_seen = hs[q].rounds;
+            all = all && finished;
+        }
+        if (all) break;
     }
     if (timing) SIA_HIP(hipEventRecord(ev[2], s));
-    SIA_HIP(hipMemcpyAsync(selected, ws.sel.ptr, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
-    SIA_HIP(hipMemcpyAsync(gains, ws.gain.ptr, sizeof(uint64_t) * k, hipMemcpyDeviceToHost, s));
+    for (uint32_t q = 0; q < Q; ++q) {
+        SIA_HIP(hipMemcpyAsync(in[q].selected, jobs[q].sel, sizeof(int64_t) * in[q].k,
+                               hipMemcpyDeviceToHost, s));
+        SIA_HIP(hipMemcpyAsync(in[q].gains, jobs[q].gain, sizeof(uint64_t) * in[q].k,
+                               hipMemcpyDeviceToHost, s));
+    }
     SIA_HIP(hipStreamSynchronize(s));
-    GreedyResult res;
     if (timing) {
-        SIA_HIP(hipEventElapsedTime(&res.ms_count, ev[0], ev[1]));
-        SIA_HIP(hipEventElapsedTime(&res.ms_greedy, ev[1], ev[2]));
+        SIA_HIP(hipEventElapsedTime(&res->ms_count, ev[0], ev[1]));
+        SIA_HIP(hipEventElapsedTime(&res->ms_greedy, ev[1], ev[2]));
         for (auto &e : ev) SIA_HIP(hipEventDestroy(e));
     }
+}
+
+GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
+                        int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s, bool timing,
+                        bool counts_ready)
+{
+    const uint64_t S = static_cast<uint64_t>(id_space);
+    ws.greedy.ensure(greedy_scratch_bytes(S, n_walks, n_ids, k));
+    ws.jobs.ensure(greedy_job_table_bytes(1));
+    ws.cnt.ensure(sizeof(uint32_t) * std::max<uint64_t>(S, 1));
+    std::vector<GreedyInput> in(1);
+    GreedyInput &g = in[0];
+    g.walk_off = ws.walk_off.as<uint64_t>();
+    g.walk_len = ws.walk_len.as<uint32_t>();
+    g.ids = ws.ids.as<uint32_t>();
+    g.id_space = S;
+    g.n_walks = n_walks;
+    g.n_ids = n_ids;
+    g.k = k;
+    g.cnt = ws.cnt.as<uint32_t>();
+    g.counts_ready = counts_ready;
+    g.scratch = ws.greedy.ptr;
+    g.selected = selected;
+    g.gains = gains;
+    GreedyResult res;
+    run_greedy_jobs(in, ws.jobs.ptr, s, timing, &res);
     return res;
 }
 
