@@ -84,6 +84,116 @@ def cpu_baseline(wl, mode, k, budget_s):
             "hsaw_per_s": res["walks"].hits / dt, "steps_per_s": res["walks"].steps / dt}
 
 
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def serve_bench(args):
+    """Batched / served queries vs the plain path (one query per call, FIFO).
+
+    Closed loop: every query of the mix is submitted at t=0; queries/s =
+    count / makespan.  Open loop: Poisson arrivals at fractions of the
+    batched closed-loop rate; the batch is fed in real time and per-query
+    latency (done - arrival) is recorded.  The plain path serves one query at
+    a time, so its open-loop latencies follow from its measured service times
+    by the FIFO recurrence finish_i = max(arrival_i, finish_{i-1}) + service_i
+    on the same arrival trace."""
+    import numpy as np
+    import torch
+    from paper_1702_05854_amd import sia, workloads
+
+    torch.cuda.set_device(0)
+    name = args.workload if args.workload != "rmat24" else "rmat22"
+    print(f"[serve] generating {name}", file=sys.stderr, flush=True)
+    wl = workloads.load(name, device="cuda")
+    g = sia.Graph(wl.col_off, wl.row_idx, wl.w)
+    torch.cuda.synchronize()
+    qs = workloads.query_mix(wl.n, args.queries, seed=5)
+    total_att = sum(q["n_attempts"] for q in qs)
+    print(f"[serve] n={wl.n} m={wl.m}: {len(qs)} queries, {total_att} attempts", file=sys.stderr,
+          flush=True)
+
+    def submit_all(b, qlist):
+        return [b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"]) for q in qlist]
+
+    with sia.Batch(g, walk_budget_bytes=args.walk_budget << 20, use_graph=1) as b:
+        probe = qs[int(np.argmax([q["n_attempts"] for q in qs]))]
+        cfg = b.tune(probe["sources"], probe["mode"], min(probe["n_attempts"], 4_000_000),
+                     seed=probe["seed"], target_ms=args.wave_ms)
+        print(f"[serve] tuned {cfg}", file=sys.stderr, flush=True)
+        # warm-up: a few queries through every path
+        for t in submit_all(b, qs[:8]):
+            b.wait(t)
+        t0 = time.perf_counter()
+        tickets = submit_all(b, qs)
+        batched = []
+        for i, t in enumerate(tickets):
+            batched.append(b.wait(t))
+            if (i + 1) % 64 == 0:
+                print(f"[serve] batched {i + 1}/{len(qs)} done", file=sys.stderr, flush=True)
+        makespan = time.perf_counter() - t0
+        bstats = b.stats()
+        closed_lat = [r["info"]["t_done"] - r["info"]["t_submit"] for r in batched]
+        rate_b = len(qs) / makespan
+        print(f"[serve] batched closed loop: {rate_b:.1f} q/s ({makespan:.2f} s)", file=sys.stderr,
+              flush=True)
+
+        # plain: one query per call, in order; the answers must agree
+        service = []
+        for i, q in enumerate(qs):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = sia.solve(g, q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"])
+            service.append(time.perf_counter() - t1)
+            assert (r["selected"] == batched[i]["selected"]).all(), f"query {i}: batched != plain"
+            assert (r["gains"] == batched[i]["gains"]).all(), f"query {i}: batched != plain"
+            if (i + 1) % 64 == 0:
+                print(f"[serve] plain {i + 1}/{len(qs)} done", file=sys.stderr, flush=True)
+        rate_p = len(qs) / sum(service)
+        print(f"[serve] plain: {rate_p:.1f} q/s", file=sys.stderr, flush=True)
+
+        open_loop = []
+        rng = np.random.default_rng(6)
+        for frac in args.loads:
+            lam = frac * rate_b
+            arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(qs)))
+            ts, lat = [], []
+            base = time.perf_counter()
+            for i, q in enumerate(qs):
+                delay = arrivals[i] - (time.perf_counter() - base)
+                if delay > 0:
+                    time.sleep(delay)
+                ts.append(b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"]))
+            for t in ts:
+                r = b.wait(t)
+                lat.append(r["info"]["t_done"] - r["info"]["t_submit"])
+            fin, plain_lat = 0.0, []
+            for i in range(len(qs)):
+                fin = max(arrivals[i], fin) + service[i]
+                plain_lat.append(fin - arrivals[i])
+            open_loop.append({"load": frac, "arrivals_per_s": lam,
+                              "batched_p50_s": percentile(lat, 50), "batched_p99_s": percentile(lat, 99),
+                              "plain_p50_s": percentile(plain_lat, 50),
+                              "plain_p99_s": percentile(plain_lat, 99)})
+            print(f"[serve] open loop {frac}: {open_loop[-1]}", file=sys.stderr, flush=True)
+    g.close()
+    out = {
+        "metric": "queries/s (mixed interdiction queries, batched and served)",
+        "value": rate_b, "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": makespan * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{name}: R-MAT s{wl.desc.get('scale')} ef{wl.desc.get('ef')}, "
+                               f"{len(qs)} mixed queries", "n": wl.n, "m": wl.m,
+                   "queries": len(qs), "attempts_total": total_att},
+        "plain_queries_per_s": rate_p, "speedup_vs_plain": rate_b / rate_p,
+        "closed_loop_p50_s": percentile(closed_lat, 50), "closed_loop_p99_s": percentile(closed_lat, 99),
+        "attempts_per_s_batched": total_att / makespan,
+        "open_loop": open_loop, "batch_stats": bstats,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,11 +206,20 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="batched/served queries vs plain on the mixed-query workload (rmat22)")
+    ap.add_argument("--queries", type=int, default=512)
+    ap.add_argument("--walk-budget", type=int, default=16384, help="MiB of walk buffers (--serve)")
+    ap.add_argument("--wave-ms", type=float, default=25.0, help="target sampling launch (--serve)")
+    ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(this build runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
 
     import torch
     from paper_1702_05854_amd import sia, workloads

@@ -44,9 +44,9 @@ typedef enum {
     SIA_EWEIGHTS = -2,   /* a weight outside [0,1]/NaN, or an in-weight sum above 1 */
     SIA_ENOMEM = -3,     /* device or host allocation failed */
     SIA_EDEVICE = -4,    /* HIP runtime error */
-    SIA_ENOTREADY = -5,  /* reserved: result not ready */
-    SIA_ECANCELLED = -6, /* reserved: request cancelled */
-    SIA_EBUSY = -7       /* reserved: no free slot */
+    SIA_ENOTREADY = -5,  /* batch: the query has not finished yet */
+    SIA_ECANCELLED = -6, /* batch: the query was cancelled */
+    SIA_EBUSY = -7       /* batch: resource held (tag bits, or tuning while busy) */
 } sia_status;
 
 typedef enum {
@@ -196,6 +196,140 @@ sia_status sia_solve(const sia_graph *g, int mode, const int32_t *sources,
                      int64_t n_sources, int64_t k, uint64_t n_attempts,
                      uint64_t attempt_offset, uint64_t seed, int64_t *selected,
                      uint64_t *gains, sia_stats *stats, int timing, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batched and served queries.  Not part of the paper's method (which runs
+ * one query per launch); the answers are identical to sia_solve's for the
+ * same query.
+ *
+ * A batch owns up to 31 query slots on one graph.  Queries are submitted at
+ * any time and admitted in arrival order as a slot and walk-buffer memory
+ * become free.  Every sampling launch takes a share of the attempts of every
+ * admitted query (one persistent launch, queries told apart by a per-slot
+ * source tag bit in the node records); a query whose attempts are all
+ * sampled moves to the greedy, which runs the greedies of all such queries
+ * in shared launches on a second stream while the next sampling launch
+ * proceeds.  Two host threads drive the device; the calls below only queue
+ * work and read results, and are safe from any thread.
+ *
+ * Walk buffers: each slot keeps its kept walks (20 bytes per walk + 4 per
+ * id) in device memory counted against walk_budget_bytes.  A launch gives a
+ * query at most the share its buffer has room for (estimated from the rates
+ * seen so far); a share whose walks outgrow the buffer is discarded and
+ * sampled again with a buffer of the exact size, so results never depend on
+ * the budget.  The greedy's index (about 12 bytes per id of the id space per
+ * running greedy) is outside the budget.
+ * ---------------------------------------------------------------------- */
+typedef struct sia_batch sia_batch; /* opaque */
+
+/* One query: the arguments of sia_solve. */
+typedef struct {
+    int32_t mode;            /* SIA_EDGES or SIA_NODES */
+    int32_t reserved;        /* must be 0 */
+    const int32_t *sources;  /* host; copied by sia_batch_submit */
+    int64_t n_sources;
+    int64_t k;               /* >= 1 */
+    uint64_t n_attempts;
+    uint64_t attempt_offset;
+    uint64_t seed;
+} sia_query;
+
+/* Launch shape of a batch (0 in any field = the default). */
+typedef struct {
+    int32_t sampler_blocks_per_cu; /* persistent sampler workgroups per CU
+                                      (default: as many as fit) */
+    uint32_t refill_chunk;         /* attempts a sampler wave takes per refill
+                                      (default 256) */
+    uint64_t wave_attempts;        /* attempts per sampling launch, shared by
+                                      the admitted queries (default 2^23) */
+    uint64_t min_share;            /* smallest share of a launch one query
+                                      gets (default 2^16) */
+    int32_t use_graph;             /* nonzero: each sampling launch is a replay
+                                      of one captured hipGraph (table and
+                                      counter uploads, kernel, read-back) */
+    int32_t reserved;
+} sia_batch_config;
+
+/* Timeline of one query, in seconds since sia_batch_create (host steady
+ * clock). */
+typedef struct {
+    double t_submit;
+    double t_admit;    /* took a slot */
+    double t_sampled;  /* last share sampled */
+    double t_done;     /* greedy finished */
+    uint32_t waves;    /* sampling launches it took part in */
+    uint32_t reruns;   /* shares sampled again after outgrowing the buffer */
+} sia_ticket_info;
+
+/* Counters of a batch. */
+typedef struct {
+    uint64_t submitted, completed, failed, cancelled;
+    uint64_t waves;           /* sampling launches */
+    uint64_t graph_replays;   /* of those, replays of the captured graph */
+    uint64_t greedy_launches; /* shared greedy runs */
+    uint64_t greedy_jobs;     /* queries they served */
+    uint64_t reruns;
+    uint64_t evictions;       /* queries restarted to free walk memory */
+    uint64_t walk_bytes;      /* walk-buffer memory held now */
+    uint64_t walk_bytes_peak;
+    uint64_t walk_budget;
+    uint32_t slots, busy_slots, pending, reserved;
+    sia_batch_config config;  /* the shape in use */
+} sia_batch_stats;
+
+/*
+ * Create a batch on graph g (whose device must be current or is made
+ * current for the batch's threads).
+ *   walk_budget_bytes  device memory for walk buffers (>= 1 MiB)
+ *   max_slots          1..31 concurrent queries; takes that many source-tag
+ *                      bits of the graph (SIA_EBUSY if other batches hold
+ *                      them).  sia_solve on the same graph stays available.
+ *   config             NULL for defaults
+ * The graph must outlive the batch.
+ */
+sia_status sia_batch_create(const sia_graph *g, uint64_t walk_budget_bytes, int32_t max_slots,
+                            const sia_batch_config *config, sia_batch **out);
+
+/* Stop the batch (queries not finished are dropped), join its threads and
+ * free its memory.  NULL is a no-op. */
+sia_status sia_batch_destroy(sia_batch *b);
+
+/* Queue a query; *ticket identifies it.  The query is checked as in
+ * sia_check_query (SIA_EINVAL, nothing queued). */
+sia_status sia_batch_submit(sia_batch *b, const sia_query *q, uint64_t *ticket);
+
+/*
+ * Result of a ticket.  SIA_ENOTREADY while it runs.  Once finished the
+ * outputs are filled (selected / gains: host arrays of the query's k
+ * entries; stats, info may be NULL), the ticket is released and the
+ * query's status is returned: SIA_OK, SIA_ECANCELLED, or the error that
+ * ended it (message via sia_last_error).  Unknown ticket: SIA_EINVAL.
+ */
+sia_status sia_batch_poll(sia_batch *b, uint64_t ticket, int64_t *selected, uint64_t *gains,
+                          sia_stats *stats, sia_ticket_info *info);
+
+/* As sia_batch_poll, blocking up to timeout_ms (< 0: no limit). */
+sia_status sia_batch_wait(sia_batch *b, uint64_t ticket, int64_t timeout_ms, int64_t *selected,
+                          uint64_t *gains, sia_stats *stats, sia_ticket_info *info);
+
+/* Cancel a ticket: a queued query leaves at once, a sampling one at the end
+ * of the current launch, a query in the greedy when the greedy ends.  Its
+ * poll then returns SIA_ECANCELLED.  Finished or unknown tickets:
+ * SIA_EINVAL. */
+sia_status sia_batch_cancel(sia_batch *b, uint64_t ticket);
+
+/* Counters and the launch shape in use. */
+sia_status sia_batch_stats_get(sia_batch *b, sia_batch_stats *out);
+
+/*
+ * Autotune the sampling launch shape on a probe query: sample its attempts
+ * once per candidate (workgroups per CU x refill chunk), keep the fastest,
+ * and size wave_attempts for launches of about target_ms.  The batch must be
+ * idle (no unfinished ticket), else SIA_EBUSY.  *chosen (may be NULL)
+ * receives the new shape.
+ */
+sia_status sia_batch_tune(sia_batch *b, const sia_query *probe, double target_ms,
+                          sia_batch_config *chosen);
 
 #ifdef __cplusplus
 }

@@ -13,45 +13,29 @@ namespace sia {
 namespace {
 thread_local std::string g_last_error;
 
-// Run f(); convert failures into a status and a thread-local message.
-template <class F>
-sia_status guarded(F &&f)
-{
-    try {
-        g_last_error.clear();
-        f();
-        return SIA_OK;
-    } catch (const Error &e) {
-        g_last_error = e.msg;
-        return e.status;
-    } catch (const std::bad_alloc &) {
-        g_last_error = "host allocation failed";
-        return SIA_ENOMEM;
-    } catch (const std::exception &e) {
-        g_last_error = e.what();
-        return SIA_EDEVICE;
-    }
-}
-
-// Make g's device current for the duration of a call.
-struct DeviceScope {
-    int prev = -1;
-    explicit DeviceScope(int dev)
-    {
-        SIA_HIP(hipGetDevice(&prev));
-        if (prev != dev) SIA_HIP(hipSetDevice(dev));
-    }
-    ~DeviceScope()
-    {
-        int cur = -1;
-        if (hipGetDevice(&cur) == hipSuccess && prev >= 0 && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
 constexpr uint32_t kMaxBuckets = 1u << 16;
 }  // namespace
 
 void set_error(const std::string &msg) { g_last_error = msg; }
+
+void finish_stats(sia_stats &S, const SourceTables &st, int mode, uint64_t n_attempts,
+                  const int64_t *selected, const uint64_t *gains, int64_t k)
+{
+    uint64_t covered = 0;
+    int64_t src_selected = 0;
+    for (int64_t i = 0; i < k; ++i) {
+        covered += gains[i];
+        if (mode == SIA_NODES &&
+            std::binary_search(st.sorted.begin(), st.sorted.end(), static_cast<int32_t>(selected[i])))
+            ++src_selected;
+    }
+    S.attempts = n_attempts;
+    S.covered = covered;
+    const double n_ns = static_cast<double>(st.n_ns), N = static_cast<double>(n_attempts);
+    S.spread_est = static_cast<double>(st.sorted.size()) + n_ns * static_cast<double>(S.hits) / N;
+    S.suspension_est = n_ns * static_cast<double>(covered) / N;
+    S.suspension_nodes_est = S.suspension_est + static_cast<double>(src_selected);
+}
 void clear_error() { g_last_error.clear(); }
 
 void DevBuf::ensure(size_t want)
@@ -341,26 +325,13 @@ sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int6
         }
         if (stats) {
             sia_stats S{};
-            S.attempts = n_attempts;
             S.hits = r.hits;
             S.dead_ends = r.dead;
             S.cycles = r.cycles;
             S.steps = r.steps;
             S.evaluations = r.evals;
             S.walk_ids = r.ids;
-            uint64_t covered = 0;
-            int64_t src_selected = 0;
-            for (int64_t i = 0; i < k; ++i) {
-                covered += gains[i];
-                if (mode == SIA_NODES &&
-                    std::binary_search(st.sorted.begin(), st.sorted.end(), static_cast<int32_t>(selected[i])))
-                    ++src_selected;
-            }
-            S.covered = covered;
-            const double n_ns = static_cast<double>(st.n_ns), N = static_cast<double>(n_attempts);
-            S.spread_est = static_cast<double>(n_sources) + n_ns * static_cast<double>(r.hits) / N;
-            S.suspension_est = n_ns * static_cast<double>(covered) / N;
-            S.suspension_nodes_est = S.suspension_est + static_cast<double>(src_selected);
+            finish_stats(S, st, mode, n_attempts, selected, gains, k);
             S.ms_sample = r.ms;
             S.ms_count = gr.ms_count;
             S.ms_greedy = gr.ms_greedy;

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -33,6 +35,43 @@ struct Error {
     do {                                                                                \
         if (!(cond)) throw ::sia::Error{(status), (msg)};                               \
     } while (0)
+
+// Run f(); turn failures into a status and the calling thread's message.
+template <class F>
+sia_status guarded(F &&f)
+{
+    try {
+        clear_error();
+        f();
+        return SIA_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return SIA_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return SIA_EDEVICE;
+    }
+}
+
+// Make a device current for the duration of a call.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev)
+    {
+        SIA_HIP(hipGetDevice(&prev));
+        if (prev != dev) SIA_HIP(hipSetDevice(dev));
+    }
+    ~DeviceScope()
+    {
+        int cur = -1;
+        if (hipGetDevice(&cur) == hipSuccess && prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+    }
+    DeviceScope(const DeviceScope &) = delete;
+    DeviceScope &operator=(const DeviceScope &) = delete;
+};
 
 // ------------------------------------------------------------ device layout
 // One 16-byte record per node: where its in-edges start, how many, the last
@@ -87,6 +126,8 @@ struct sia_graph {
     sia::DevBuf edges;  // EdgeRec[m]
     sia::Workspace ws;
     std::mutex mu;      // one query at a time per graph handle
+    std::mutex tag_mu;  // guards tag_bits
+    uint32_t tag_bits = 0;  // source-tag bits 0..30 held by batches
 };
 
 namespace sia {
@@ -102,6 +143,10 @@ struct SourceTables {
 void check_query(int64_t n, int64_t m, int mode, const int32_t *sources, int64_t n_sources,
                  int64_t k, uint64_t n_attempts, uint64_t attempt_offset);
 SourceTables build_source_tables(int64_t n, const int32_t *sources, int64_t n_sources);
+// Fill attempts, covered and the estimates of a finished query into S (whose
+// counters are already set).
+void finish_stats(sia_stats &S, const SourceTables &st, int mode, uint64_t n_attempts,
+                  const int64_t *selected, const uint64_t *gains, int64_t k);
 
 // Per-query counters written by the sampler.
 enum StatSlot {
@@ -141,12 +186,33 @@ struct WaveItem {
     uint64_t count;
 };
 
-// Sampling of several queries in one persistent launch.  d_slots: device
-// array of SlotDev; items: host array (copied to d_table, which must hold
-// wave_table_bytes(n_items)).  Asynchronous on stream s.
-size_t wave_table_bytes(uint32_t n_items);
+// The work table a sampling launch reads from device memory: the wave's
+// items laid end to end and the chunk counter the persistent lanes draw
+// from.  Host code fills it (fill_wave_table) and copies it to the device
+// before each launch, so a captured launch can be replayed with new contents.
+constexpr uint32_t kMaxItems = 32;
+struct WaveTable {
+    uint64_t next[8];                // next[0]: wave-global chunk counter (own 64-B line)
+    uint64_t prefix[kMaxItems + 1];  // wave-global index of each item's first attempt
+    uint64_t local[kMaxItems];       // local attempt index of each item's first attempt
+    uint32_t slot[kMaxItems];
+    uint32_t n_items;
+    uint32_t pad;
+};
+void fill_wave_table(WaveTable &t, const WaveItem *items, uint32_t n_items, uint32_t n_slots);
+
+// Launch shape of the sampler: persistent workgroups per CU (0: as many as
+// fit) and attempts a wave takes from the chunk counter per refill.
+struct SamplerConfig {
+    int blocks_per_cu = 0;
+    uint32_t chunk = 256;
+};
+int sampler_max_blocks_per_cu();
+
+// Sample the wave described by d_table (device) over the n_slots SlotDev
+// entries at d_slots (device).  Asynchronous on stream s.
 void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
-                 const WaveItem *items, uint32_t n_items, void *d_table, hipStream_t s);
+                 const WaveTable *d_table, const SamplerConfig &cfg, hipStream_t s);
 // Set or clear the tag bit `mask` of the given sources (device array).
 void tag_sources(const sia_graph *g, const int32_t *d_src, uint32_t n_src, uint32_t mask, bool set,
                  hipStream_t s);

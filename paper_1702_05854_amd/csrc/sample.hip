@@ -39,7 +39,6 @@ namespace sia {
 namespace {
 
 constexpr int kWave = 64;
-constexpr uint64_t kChunk = 256;
 
 enum Phase : uint32_t {
     PH_START = 0,   // compute the start node
@@ -55,15 +54,10 @@ struct WaveArgs {
     const EdgeRec *edges;
     const SlotDev *slots;
     uint32_t n_slots;
-    uint32_t n_items;
-    const uint64_t *item_prefix;   // [n_items + 1] wave-global attempt index of each item
-    const uint32_t *item_slot;     // [n_items]
-    const uint64_t *item_local;    // [n_items] local attempt index of the item's first attempt
-    uint64_t *next;                // wave-global chunk counter
+    uint32_t chunk;                // attempts taken per refill
+    const WaveTable *table;
     uint64_t guard_evals;          // no walk may need more evaluations than this
 };
-
-constexpr uint32_t kMaxItems = 32;
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
 {
@@ -146,15 +140,17 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
     // per-slot counters of this workgroup: hits, dead ends, cycles, steps, evaluations, faults
     __shared__ unsigned long long acc[kMaxSlots + 1][6];
     const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t n_items = A.table->n_items;
     for (uint32_t i = threadIdx.x; i < A.n_slots; i += blockDim.x) sl[i] = A.slots[i];
-    for (uint32_t i = threadIdx.x; i <= A.n_items; i += blockDim.x) ip[i] = A.item_prefix[i];
-    for (uint32_t i = threadIdx.x; i < A.n_items; i += blockDim.x) {
-        il[i] = A.item_local[i];
-        is[i] = A.item_slot[i];
+    for (uint32_t i = threadIdx.x; i <= n_items; i += blockDim.x) ip[i] = A.table->prefix[i];
+    for (uint32_t i = threadIdx.x; i < n_items; i += blockDim.x) {
+        il[i] = A.table->local[i];
+        is[i] = A.table->slot[i];
     }
     for (uint32_t i = threadIdx.x; i < A.n_slots * 6; i += blockDim.x) acc[i / 6][i % 6] = 0;
     __syncthreads();
-    const uint64_t total = ip[A.n_items];
+    const uint64_t total = ip[n_items];
+    uint64_t *next = const_cast<uint64_t *>(&A.table->next[0]);
 
     // wave-uniform work state
     uint64_t chunk_next = 0, chunk_end = 0;
@@ -172,15 +168,15 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
         while (idle != 0 && !exhausted) {
             if (chunk_next >= chunk_end) {
                 uint64_t base = 0;
-                if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long *>(A.next),
-                                                static_cast<unsigned long long>(kChunk));
+                if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long *>(next),
+                                                static_cast<unsigned long long>(A.chunk));
                 base = shfl_u64(base, 0);
                 if (base >= total) {
                     exhausted = true;
                     break;
                 }
                 chunk_next = base;
-                chunk_end = min(base + kChunk, total);
+                chunk_end = min(base + A.chunk, total);
             }
             const uint32_t need = static_cast<uint32_t>(__popcll(idle));
             const uint64_t avail = chunk_end - chunk_next;
@@ -189,7 +185,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
             if (!active && rank < take) {
                 const uint64_t gidx = chunk_next + rank;
                 uint32_t it = 0;
-                while (it + 1 < A.n_items && ip[it + 1] <= gidx) ++it;
+                while (it + 1 < n_items && ip[it + 1] <= gidx) ++it;
                 slot = is[it];
                 const SlotDev &S = sl[slot];
                 a = S.attempt_base + il[it] + (gidx - ip[it]);
@@ -389,23 +385,36 @@ __global__ void k_tag_sources(const int32_t *src, uint32_t n_src, NodeRec *nodes
     }
 }
 
-int persistent_blocks()
+int max_blocks_per_cu()
 {
-    static int blocks = 0;
-    if (!blocks) {
-        int per_cu = 0;
-        SIA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sample, 256, 0));
-        blocks = std::max(1, per_cu) * device_cu_count();
+    static int per_cu = 0;
+    if (!per_cu) {
+        int v = 0;
+        SIA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_sample, 256, 0));
+        per_cu = std::max(1, v);
     }
-    return blocks;
+    return per_cu;
 }
 
 }  // namespace
 
-size_t wave_table_bytes(uint32_t n_items)
+int sampler_max_blocks_per_cu() { return max_blocks_per_cu(); }
+
+void fill_wave_table(WaveTable &t, const WaveItem *items, uint32_t n_items, uint32_t n_slots)
 {
-    return 64 + sizeof(uint64_t) * (kMaxItems + 1) + sizeof(uint64_t) * kMaxItems +
-           sizeof(uint32_t) * kMaxItems;
+    SIA_REQUIRE(n_slots >= 1 && n_slots <= kMaxSlots + 1 && n_items >= 1 && n_items <= kMaxItems,
+                SIA_EINVAL, "bad wave shape");
+    t = WaveTable{};
+    uint64_t run = 0;
+    for (uint32_t i = 0; i < n_items; ++i) {
+        SIA_REQUIRE(items[i].slot < n_slots, SIA_EINVAL, "wave item names a missing slot");
+        t.prefix[i] = run;
+        t.local[i] = items[i].local_start;
+        t.slot[i] = items[i].slot;
+        run += items[i].count;
+    }
+    t.prefix[n_items] = run;
+    t.n_items = n_items;
 }
 
 void tag_sources(const sia_graph *g, const int32_t *d_src, uint32_t n_src, uint32_t mask, bool set,
@@ -418,41 +427,21 @@ void tag_sources(const sia_graph *g, const int32_t *d_src, uint32_t n_src, uint3
 }
 
 void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
-                 const WaveItem *items, uint32_t n_items, void *d_table, hipStream_t s)
+                 const WaveTable *d_table, const SamplerConfig &cfg, hipStream_t s)
 {
-    SIA_REQUIRE(n_slots >= 1 && n_slots <= kMaxSlots + 1 && n_items >= 1 && n_items <= kMaxItems,
-                SIA_EINVAL, "bad wave shape");
-    // table layout: next counter (64 B), prefix[kMaxItems+1], local[kMaxItems], slot[kMaxItems]
-    struct {
-        uint64_t next[8];
-        uint64_t prefix[kMaxItems + 1];
-        uint64_t local[kMaxItems];
-        uint32_t slot[kMaxItems];
-    } h{};
-    uint64_t run = 0;
-    for (uint32_t i = 0; i < n_items; ++i) {
-        SIA_REQUIRE(items[i].slot < n_slots, SIA_EINVAL, "wave item names a missing slot");
-        h.prefix[i] = run;
-        h.local[i] = items[i].local_start;
-        h.slot[i] = items[i].slot;
-        run += items[i].count;
-    }
-    h.prefix[n_items] = run;
-    static_assert(sizeof(h) <= 64 + 8 * (kMaxItems + 1) + 8 * kMaxItems + 4 * kMaxItems + 64, "");
-    SIA_HIP(hipMemcpyAsync(d_table, &h, sizeof(h), hipMemcpyHostToDevice, s));
-    char *base = static_cast<char *>(d_table);
+    SIA_REQUIRE(n_slots >= 1 && n_slots <= kMaxSlots + 1, SIA_EINVAL, "bad wave shape");
+    SIA_REQUIRE(cfg.chunk >= 1 && cfg.chunk <= (1u << 20), SIA_EINVAL, "bad refill chunk");
+    const int per_cu = cfg.blocks_per_cu > 0 ? std::min(cfg.blocks_per_cu, max_blocks_per_cu())
+                                             : max_blocks_per_cu();
     WaveArgs A;
     A.nodes = g->nodes.as<NodeRec>();
     A.edges = g->edges.as<EdgeRec>();
     A.slots = d_slots;
     A.n_slots = n_slots;
-    A.n_items = n_items;
-    A.next = reinterpret_cast<uint64_t *>(base);
-    A.item_prefix = reinterpret_cast<const uint64_t *>(base + offsetof(decltype(h), prefix));
-    A.item_local = reinterpret_cast<const uint64_t *>(base + offsetof(decltype(h), local));
-    A.item_slot = reinterpret_cast<const uint32_t *>(base + offsetof(decltype(h), slot));
+    A.chunk = cfg.chunk;
+    A.table = d_table;
     A.guard_evals = 3 * static_cast<uint64_t>(g->n) + 8;
-    hipLaunchKernelGGL(k_sample, dim3(persistent_blocks()), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_sample, dim3(per_cu * device_cu_count()), dim3(256), 0, s, A);
     SIA_HIP(hipGetLastError());
 }
 
@@ -468,7 +457,7 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
     ws.src_sorted.ensure(sizeof(int32_t) * n_src);
     ws.src_t.ensure(sizeof(uint32_t) * n_src);
     ws.bucket.ensure(sizeof(uint32_t) * st.bucket.size());
-    ws.counters.ensure(sizeof(uint64_t) * ST_COUNT + sizeof(SlotDev) + wave_table_bytes(1) + 256);
+    ws.counters.ensure(sizeof(uint64_t) * ST_COUNT + sizeof(SlotDev) + sizeof(WaveTable) + 256);
     SIA_HIP(hipMemcpyAsync(ws.src_sorted.ptr, st.sorted.data(), sizeof(int32_t) * n_src,
                            hipMemcpyHostToDevice, s));
     SIA_HIP(hipMemcpyAsync(ws.src_t.ptr, st.t.data(), sizeof(uint32_t) * n_src,
@@ -480,7 +469,8 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
     char *cbase = ws.counters.as<char>();
     uint64_t *d_counters = reinterpret_cast<uint64_t *>(cbase);
     SlotDev *d_slot = reinterpret_cast<SlotDev *>(cbase + sizeof(uint64_t) * ST_COUNT);
-    void *d_table = cbase + ((sizeof(uint64_t) * ST_COUNT + sizeof(SlotDev) + 255) / 256) * 256;
+    WaveTable *d_table = reinterpret_cast<WaveTable *>(
+        cbase + ((sizeof(uint64_t) * ST_COUNT + sizeof(SlotDev) + 255) / 256) * 256);
 
     if (!ws.walk_cap) {
         ws.walk_cap = std::min<uint64_t>(n_attempts, std::max<uint64_t>(1u << 20, n_attempts / 16));
@@ -517,6 +507,9 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
         S.counters = d_counters;
         SIA_HIP(hipMemcpyAsync(d_slot, &S, sizeof(S), hipMemcpyHostToDevice, s));
         const WaveItem item{0u, 0u, n_attempts};
+        WaveTable table;
+        fill_wave_table(table, &item, 1, 1);
+        SIA_HIP(hipMemcpyAsync(d_table, &table, sizeof(table), hipMemcpyHostToDevice, s));
 
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (timing) {
@@ -524,7 +517,7 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
             SIA_HIP(hipEventCreate(&e1));
             SIA_HIP(hipEventRecord(e0, s));
         }
-        launch_wave(g, d_slot, 1, &item, 1, d_table, s);
+        launch_wave(g, d_slot, 1, d_table, SamplerConfig{}, s);
         if (timing) SIA_HIP(hipEventRecord(e1, s));
 
         uint64_t h[ST_COUNT];

@@ -42,11 +42,51 @@ class Stats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Query(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("reserved", C.c_int32), ("sources", C.c_void_p),
+                ("n_sources", C.c_int64), ("k", C.c_int64), ("n_attempts", C.c_uint64),
+                ("attempt_offset", C.c_uint64), ("seed", C.c_uint64)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("sampler_blocks_per_cu", C.c_int32), ("refill_chunk", C.c_uint32),
+                ("wave_attempts", C.c_uint64), ("min_share", C.c_uint64),
+                ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class TicketInfo(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_sampled", C.c_double),
+                ("t_done", C.c_double), ("waves", C.c_uint32), ("reruns", C.c_uint32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class BatchStats(C.Structure):
+    _fields_ = [(name, C.c_uint64) for name in (
+        "submitted", "completed", "failed", "cancelled", "waves", "graph_replays",
+        "greedy_launches", "greedy_jobs", "reruns", "evictions", "walk_bytes", "walk_bytes_peak",
+        "walk_budget")] + [("slots", C.c_uint32), ("busy_slots", C.c_uint32),
+                           ("pending", C.c_uint32), ("reserved", C.c_uint32),
+                           ("config", BatchConfig)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        d["config"] = self.config.as_dict()
+        return d
+
+
 class _Walks(C.Structure):
     _fields_ = [("n_walks", C.c_uint64), ("n_ids", C.c_uint64),
                 ("attempt", C.POINTER(C.c_uint64)), ("off", C.POINTER(C.c_uint64)),
                 ("ids", C.POINTER(C.c_uint32)), ("stats", Stats)]
 
+
+BATCH_SYMBOLS = ("sia_batch_create", "sia_batch_destroy", "sia_batch_submit", "sia_batch_poll",
+                 "sia_batch_wait", "sia_batch_cancel", "sia_batch_stats_get", "sia_batch_tune")
 
 _lib = None
 
@@ -73,9 +113,17 @@ def lib():
         L.sia_walks_free.restype = None
         L.sia_greedy.argtypes = [i64, p, p, u64, i64, p, p, p]
         L.sia_solve.argtypes = [p, i32, p, i64, i64, u64, u64, u64, p, p, C.POINTER(Stats), i32, p]
+        L.sia_batch_create.argtypes = [p, u64, C.c_int32, C.POINTER(BatchConfig), C.POINTER(p)]
+        L.sia_batch_destroy.argtypes = [p]
+        L.sia_batch_submit.argtypes = [p, C.POINTER(Query), C.POINTER(u64)]
+        L.sia_batch_poll.argtypes = [p, u64, p, p, C.POINTER(Stats), C.POINTER(TicketInfo)]
+        L.sia_batch_wait.argtypes = [p, u64, i64, p, p, C.POINTER(Stats), C.POINTER(TicketInfo)]
+        L.sia_batch_cancel.argtypes = [p, u64]
+        L.sia_batch_stats_get.argtypes = [p, C.POINTER(BatchStats)]
+        L.sia_batch_tune.argtypes = [p, C.POINTER(Query), C.c_double, C.POINTER(BatchConfig)]
         for name in ("sia_check_query", "sia_graph_create", "sia_graph_destroy", "sia_graph_info",
                      "sia_graph_thresholds", "sia_quantize", "sia_sample", "sia_greedy",
-                     "sia_solve"):
+                     "sia_solve") + BATCH_SYMBOLS:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -212,6 +260,86 @@ def solve(graph: Graph, sources, mode, k, n_attempts, attempt_offset=0, seed=201
                            attempt_offset, seed, _hptr(sel), _hptr(gains), C.byref(st),
                            1 if timing else 0, _stream(stream)))
     return dict(selected=sel, gains=gains, stats=st.as_dict())
+
+
+def _query(sources, mode, k, n_attempts, attempt_offset, seed):
+    src = _host(sources, np.int32)
+    q = Query(MODES[mode], 0, src.ctypes.data, src.shape[0], k, n_attempts, attempt_offset, seed)
+    return q, src  # src keeps the array alive while q is used
+
+
+class Batch:
+    """Queries served together on one graph (see sia_batch_* in include/sia.h).
+
+    ``submit`` queues a query and returns its ticket; ``poll`` returns None
+    while it runs, ``wait`` blocks.  A finished ticket yields
+    ``dict(selected, gains, stats, info)``; a failed or cancelled one raises
+    SiaError with its status."""
+
+    def __init__(self, graph: Graph, walk_budget_bytes=8 << 30, max_slots=31, **config):
+        self._h = C.c_void_p()
+        cfg = BatchConfig(**config)
+        _check(lib().sia_batch_create(graph.handle, walk_budget_bytes, max_slots, C.byref(cfg),
+                                      C.byref(self._h)))
+        self.graph = graph  # the graph must outlive the batch
+        self._k = {}
+
+    def submit(self, sources, mode, k, n_attempts, attempt_offset=0, seed=2017):
+        q, src = _query(sources, mode, k, n_attempts, attempt_offset, seed)
+        t = C.c_uint64()
+        _check(lib().sia_batch_submit(self._h, C.byref(q), C.byref(t)))
+        self._k[t.value] = k
+        return t.value
+
+    def _take(self, fn, ticket, *extra):
+        k = self._k.get(ticket, 1)  # an unknown ticket is rejected by the library
+        sel = np.zeros(k, dtype=np.int64)
+        gains = np.zeros(k, dtype=np.uint64)
+        st, info = Stats(), TicketInfo()
+        rc = fn(self._h, ticket, *extra, _hptr(sel), _hptr(gains), C.byref(st), C.byref(info))
+        if rc == -5:  # SIA_ENOTREADY
+            return None
+        if rc != -1:  # the ticket was released (finished, failed or cancelled)
+            self._k.pop(ticket, None)
+        _check(rc)
+        return dict(selected=sel, gains=gains, stats=st.as_dict(), info=info.as_dict())
+
+    def poll(self, ticket):
+        return self._take(lib().sia_batch_poll, ticket)
+
+    def wait(self, ticket, timeout_ms=-1):
+        return self._take(lib().sia_batch_wait, ticket, timeout_ms)
+
+    def cancel(self, ticket):
+        _check(lib().sia_batch_cancel(self._h, ticket))
+
+    def stats(self):
+        s = BatchStats()
+        _check(lib().sia_batch_stats_get(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def tune(self, sources, mode, n_attempts, attempt_offset=0, seed=2017, target_ms=25.0):
+        q, src = _query(sources, mode, 0, n_attempts, attempt_offset, seed)
+        cfg = BatchConfig()
+        _check(lib().sia_batch_tune(self._h, C.byref(q), target_ms, C.byref(cfg)))
+        return cfg.as_dict()
+
+    def close(self):
+        if self._h:
+            _check(lib().sia_batch_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def quantize(w_dev, q_dev, stream=None):

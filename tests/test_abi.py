@@ -84,3 +84,42 @@ def test_greedy_rejects_bad_arguments(L):
         sia.greedy(5, off, ids, 2, stream=0)                       # id 9 outside [0, 5)
     with pytest.raises(sia.SiaError):
         sia.greedy(10, off, ids, 11, stream=0)                     # k > id_space
+
+
+def test_batch_entry_points_reject_null_handles(L):
+    out = C.c_void_p()
+    assert L.sia_batch_create(None, 1 << 30, 4, None, C.byref(out)) == -1
+    assert not out.value
+    q = sia.Query()
+    t = C.c_uint64()
+    assert L.sia_batch_submit(None, C.byref(q), C.byref(t)) == -1
+    assert L.sia_batch_poll(None, 1, None, None, None, None) == -1
+    assert L.sia_batch_wait(None, 1, 0, None, None, None, None) == -1
+    assert L.sia_batch_cancel(None, 1) == -1
+    assert L.sia_batch_stats_get(None, None) == -1
+    assert L.sia_batch_tune(None, None, 1.0, None) == -1
+    assert "NULL" in L.sia_last_error().decode()
+    assert L.sia_batch_destroy(None) == 0
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C sizes and offsets."""
+    import subprocess
+    structs = {"sia_stats": sia.Stats, "sia_query": sia.Query, "sia_batch_config": sia.BatchConfig,
+               "sia_ticket_info": sia.TicketInfo, "sia_batch_stats": sia.BatchStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    c_layout = {tuple(l.split()[:2]): int(l.split()[2]) for l in got if l}
+    for cname, py in structs.items():
+        assert c_layout[(cname, "size")] == C.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert c_layout[(cname, field)] == getattr(py, field).offset, (cname, field)
