@@ -117,7 +117,9 @@ def serve_bench(args):
     def submit_all(b, qlist):
         return [b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"]) for q in qlist]
 
-    with sia.Batch(g, walk_budget_bytes=args.walk_budget << 20, use_graph=1) as b:
+    with sia.Batch(g, walk_budget_bytes=args.walk_budget << 20, use_graph=1,
+                   greedy_mode=args.greedy_mode, greedy_cus=args.greedy_cus,
+                   greedy_batch=args.greedy_batch) as b:
         probe = qs[int(np.argmax([q["n_attempts"] for q in qs]))]
         cfg = b.tune(probe["sources"], probe["mode"], min(probe["n_attempts"], 4_000_000),
                      seed=probe["seed"], target_ms=args.wave_ms)
@@ -141,7 +143,7 @@ def serve_bench(args):
 
         # plain: one query per call, in order; the answers must agree
         service = []
-        for i, q in enumerate(qs):
+        for i, q in enumerate(qs if not args.skip_plain else []):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             r = sia.solve(g, q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"])
@@ -150,8 +152,9 @@ def serve_bench(args):
             assert (r["gains"] == batched[i]["gains"]).all(), f"query {i}: batched != plain"
             if (i + 1) % 64 == 0:
                 print(f"[serve] plain {i + 1}/{len(qs)} done", file=sys.stderr, flush=True)
-        rate_p = len(qs) / sum(service)
-        print(f"[serve] plain: {rate_p:.1f} q/s", file=sys.stderr, flush=True)
+        rate_p = len(qs) / sum(service) if service else None
+        if rate_p:
+            print(f"[serve] plain: {rate_p:.1f} q/s", file=sys.stderr, flush=True)
 
         open_loop = []
         rng = np.random.default_rng(6)
@@ -169,7 +172,7 @@ def serve_bench(args):
                 r = b.wait(t)
                 lat.append(r["info"]["t_done"] - r["info"]["t_submit"])
             fin, plain_lat = 0.0, []
-            for i in range(len(qs)):
+            for i in range(len(service)):
                 fin = max(arrivals[i], fin) + service[i]
                 plain_lat.append(fin - arrivals[i])
             open_loop.append({"load": frac, "arrivals_per_s": lam,
@@ -186,7 +189,7 @@ def serve_bench(args):
         "config": {"workload": f"{name}: R-MAT s{wl.desc.get('scale')} ef{wl.desc.get('ef')}, "
                                f"{len(qs)} mixed queries", "n": wl.n, "m": wl.m,
                    "queries": len(qs), "attempts_total": total_att},
-        "plain_queries_per_s": rate_p, "speedup_vs_plain": rate_b / rate_p,
+        "plain_queries_per_s": rate_p, "speedup_vs_plain": rate_b / rate_p if rate_p else None,
         "closed_loop_p50_s": percentile(closed_lat, 50), "closed_loop_p99_s": percentile(closed_lat, 99),
         "attempts_per_s_batched": total_att / makespan,
         "open_loop": open_loop, "batch_stats": bstats,
@@ -212,6 +215,11 @@ def main():
     ap.add_argument("--walk-budget", type=int, default=16384, help="MiB of walk buffers (--serve)")
     ap.add_argument("--wave-ms", type=float, default=25.0, help="target sampling launch (--serve)")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0])
+    ap.add_argument("--greedy-mode", type=int, default=0,
+                    help="0: greedy between sampling launches, 1: on a second stream (--serve)")
+    ap.add_argument("--greedy-cus", type=int, default=0, help="CUs reserved for the greedy (--serve)")
+    ap.add_argument("--greedy-batch", type=int, default=0, help="queries per greedy launch (--serve)")
+    ap.add_argument("--skip-plain", action="store_true", help="batched side only (--serve, profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "

@@ -208,9 +208,10 @@ sia_status sia_solve(const sia_graph *g, int mode, const int32_t *sources,
  * admitted query (one persistent launch, queries told apart by a per-slot
  * source tag bit in the node records); a query whose attempts are all
  * sampled moves to the greedy, which runs the greedies of all such queries
- * in shared launches on a second stream while the next sampling launch
- * proceeds.  Two host threads drive the device; the calls below only queue
- * work and read results, and are safe from any thread.
+ * in shared launches, either between sampling launches (default) or on a
+ * second stream beside them.  Host threads of the batch drive the device;
+ * the calls below only queue work and read results, and are safe from any
+ * thread.
  *
  * Walk buffers: each slot keeps its kept walks (20 bytes per walk + 4 per
  * id) in device memory counted against walk_budget_bytes.  A launch gives a
@@ -247,7 +248,20 @@ typedef struct {
     int32_t use_graph;             /* nonzero: each sampling launch is a replay
                                       of one captured hipGraph (table and
                                       counter uploads, kernel, read-back) */
-    int32_t reserved;
+    int32_t greedy_mode;           /* 0: time-sliced -- the greedy of finished
+                                      queries runs between sampling launches
+                                      in batches of greedy_batch (sooner when
+                                      sampling would wait for it); 1:
+                                      concurrent -- a second thread runs each
+                                      finished query's greedy at once on its
+                                      own stream, beside the sampling */
+    int32_t greedy_cus;            /* greedy_mode 1 only: CUs given to the
+                                      greedy stream alone (CU-masked streams;
+                                      the sampler gets the rest); 0: both
+                                      streams use every CU */
+    uint32_t greedy_batch;         /* greedy_mode 0: finished queries per
+                                      greedy launch (default 8) */
+    uint32_t reserved;
 } sia_batch_config;
 
 /* Timeline of one query, in seconds since sia_batch_create (host steady
@@ -274,6 +288,9 @@ typedef struct {
     uint64_t walk_bytes_peak;
     uint64_t walk_budget;
     uint32_t slots, busy_slots, pending, reserved;
+    double sample_busy_s;     /* host wall time inside sampling launches */
+    double greedy_busy_s;     /* host wall time inside greedy launches */
+    double greedy_index_s;    /* of which: device time of counts + index */
     sia_batch_config config;  /* the shape in use */
 } sia_batch_stats;
 

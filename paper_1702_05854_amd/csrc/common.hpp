@@ -206,6 +206,7 @@ void fill_wave_table(WaveTable &t, const WaveItem *items, uint32_t n_items, uint
 struct SamplerConfig {
     int blocks_per_cu = 0;
     uint32_t chunk = 256;
+    int cus = 0;  // CUs the launch stream may use (0: all of the device)
 };
 int sampler_max_blocks_per_cu();
 
@@ -251,7 +252,7 @@ struct GreedyInput {
     uint32_t rounds_seen = 0;     // progress bookkeeping
 };
 size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids, int64_t k);
-size_t greedy_job_table_bytes(uint32_t n_jobs);
+size_t greedy_job_table_bytes(uint32_t n_jobs);  // job records + their states
 
 // Inverted index + k greedy rounds for every job, concurrently (blockIdx.y /
 // one workgroup per job).  d_job_table: greedy_job_table_bytes(jobs.size())

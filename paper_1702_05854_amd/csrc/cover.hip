@@ -44,8 +44,6 @@ constexpr uint32_t kPerOctave = 512;
 constexpr uint32_t kBins = kExact + 20 * kPerOctave;  // octaves 2^12 .. 2^31
 constexpr uint32_t kPoolTarget = 4096;
 constexpr uint32_t kPoolMax = 16384;
-constexpr int kLazyThreads = 1024;
-constexpr int kPlanThreads = 1024;
 
 enum PlanKind : uint32_t { PLAN_COLLECT = 0, PLAN_TIES = 1 };
 
@@ -126,9 +124,11 @@ __device__ __forceinline__ bool job_done(const GreedyJob &J)
 
 __device__ __forceinline__ uint64_t n_tiles_of(uint64_t S) { return (S + kScanTile - 1) / kScanTile; }
 
-// block-wide exclusive scan of one value per thread (256 threads)
-__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *sh, uint32_t &total)
+// block-wide exclusive scan of one value per thread (T threads; sh holds T/64)
+template <int T>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total)
 {
+    constexpr int W = T / kWave;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     uint32_t x = v;
 #pragma unroll
@@ -140,12 +140,17 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *sh
     __syncthreads();
     uint32_t before = 0;
     total = 0;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < W; ++k) {
         if (k < wid) before += sh[k];
         total += sh[k];
     }
     __syncthreads();
     return before + x - v;
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    return block_excl_scan<256>(v, sh, total);
 }
 
 // exclusive scan of tiles[0 .. n) in place, one 256-thread workgroup
@@ -250,7 +255,8 @@ __global__ __launch_bounds__(256) void k_fill(const GreedyJob *jobs)
 }
 
 // ---------------------------------------------------------------- pool rebuild
-__global__ __launch_bounds__(1024) void k_hist(const GreedyJob *jobs)
+template <int T>
+__global__ __launch_bounds__(T) void k_hist(const GreedyJob *jobs)
 {
     __shared__ uint32_t h[kBins];
     const GreedyJob J = jobs[blockIdx.y];
@@ -274,17 +280,18 @@ __global__ __launch_bounds__(1024) void k_hist(const GreedyJob *jobs)
 // 0, the pool is every id with cnt >= the lowest count of b*.  Otherwise b*
 // is an exact count c (else: error) and the pool is every id above c plus the
 // lowest-id ones at c, up to kPoolTarget.  One workgroup per job.
-__global__ __launch_bounds__(kPlanThreads) void k_plan(const GreedyJob *jobs)
+template <int T>
+__global__ __launch_bounds__(T) void k_plan(const GreedyJob *jobs)
 {
-    constexpr uint32_t kPer = (kBins + kPlanThreads - 1) / kPlanThreads;
-    constexpr int kWaves = kPlanThreads / kWave;
+    constexpr uint32_t kPer = (kBins + T - 1) / T;
+    constexpr int kWaves = T / kWave;
     __shared__ uint32_t h[kBins];
     __shared__ uint32_t wsum[kWaves];
     __shared__ uint32_t found, bstar, ab_sh;
     const GreedyJob J = jobs[blockIdx.x];
     if (job_done(J)) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    for (uint32_t b = threadIdx.x; b < kBins; b += kPlanThreads) {
+    for (uint32_t b = threadIdx.x; b < kBins; b += T) {
         h[b] = J.hist[b];
         J.hist[b] = 0;
     }
@@ -417,27 +424,39 @@ __device__ __forceinline__ uint32_t load_count(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One workgroup per job: rounds [rounds, k) while the pool certifies the pick.
-__global__ __launch_bounds__(kLazyThreads) void k_lazy(const GreedyJob *jobs)
+// One workgroup of T threads per job: rounds [rounds, k) while the pool
+// certifies the pick.
+//
+// Zero gains.  When the best key of the pool has gain 0, every unselected id
+// of the pool has count 0.  If the pool is exactly the lowest-id ids that had
+// count 0 when it was built (tie plan at count 0, nothing collected above),
+// then every id outside it has count 0 and a higher id, so the remaining
+// rounds take the pool's unselected ids in ascending order: they are written
+// in one pass.  Otherwise the round is taken one by one as usual and the
+// launch ends after it, so the next rebuild forms such a pool.
+template <int T>
+__global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
 {
-    __shared__ uint64_t sh[kLazyThreads / kWave];
-    __shared__ uint32_t queue[kLazyThreads];
+    constexpr int kWaves = T / kWave;
+    __shared__ uint64_t sh[kWaves];
+    __shared__ uint32_t sh32[kWaves];
+    __shared__ uint32_t queue[T];
     __shared__ uint32_t qn;
     const GreedyJob J = jobs[blockIdx.x];
     if (job_done(J)) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    constexpr int kWaves = kLazyThreads / kWave;
     GreedyState *st = J.st;
     const bool ties = st->plan == PLAN_TIES;
     const uint32_t P = st->pool_n + (ties ? st->n_tie : 0u);
     const uint64_t tau = ties && st->leftover
                              ? ((static_cast<uint64_t>(st->c_tie) + 1) << 32) | (0xFFFFFFFFu - st->next_id)
                              : st->tau;
+    const bool ordered_zeros = ties && st->c_tie == 0 && st->pool_n == 0;
     int64_t r = st->rounds;
     for (; r < J.k; ++r) {
         // exact keys of the pool; the largest is this round's pick if it beats tau
         uint64_t best = 0;
-        for (uint32_t i = threadIdx.x; i < P; i += kLazyThreads) {
+        for (uint32_t i = threadIdx.x; i < P; i += T) {
             const uint32_t id = J.pool[i];
             const uint64_t key = key_of(load_count(&J.cnt[id]), id);
             best = key > best ? key : best;
@@ -451,37 +470,63 @@ __global__ __launch_bounds__(kLazyThreads) void k_lazy(const GreedyJob *jobs)
         if (best <= tau) break;  // uniform: every thread saw the same values
         const uint32_t id = 0xFFFFFFFFu - static_cast<uint32_t>(best);
         const uint32_t g = static_cast<uint32_t>(best >> 32) - 1u;
+        if (g == 0 && ordered_zeros) {
+            const uint64_t need = static_cast<uint64_t>(J.k - r);
+            uint64_t taken = 0;
+            for (uint32_t b0 = 0; b0 < P && taken < need; b0 += T) {
+                const uint32_t i = b0 + threadIdx.x;
+                uint32_t x = 0;
+                bool open = false;
+                if (i < P) {
+                    x = J.pool[i];
+                    open = load_count(&J.cnt[x]) != kSelected;
+                }
+                uint32_t total;
+                const uint64_t rank = taken + block_excl_scan<T>(open ? 1u : 0u, sh32, total);
+                if (open && rank < need) {
+                    J.sel[r + rank] = x;
+                    J.gain[r + rank] = 0;
+                    atomicExch(&J.cnt[x], kSelected);
+                }
+                taken += total;
+            }
+            r += static_cast<int64_t>(taken < need ? taken : need);
+            break;
+        }
         if (threadIdx.x == 0) {
             J.sel[r] = id;
             J.gain[r] = g;
             atomicExch(&J.cnt[id], kSelected);
         }
-        if (g > 0) {
-            const uint32_t lo = J.cur[id], hi = J.cur[id + 1];
-            for (uint32_t b0 = lo; b0 < hi; b0 += kLazyThreads) {
-                const uint32_t p = b0 + threadIdx.x;
-                if (p < hi) {
-                    const uint32_t w = J.inv[p];
-                    if (atomicExch(&J.covered[w], 1u) == 0u) queue[atomicAdd(&qn, 1u)] = w;
-                }
-                __syncthreads();
-                const uint32_t n = qn;
-                for (uint32_t qi = wid; qi < n; qi += kWaves) {
-                    const uint32_t w = queue[qi];
-                    const uint64_t o = J.walk_off[w];
-                    const uint32_t L = J.walk_len[w];
-                    for (uint32_t e = lane; e < L; e += kWave) {
-                        const uint32_t x = J.ids[o + e];
-                        if (x != id) atomicSub(&J.cnt[x], 1u);
-                    }
-                }
-                __syncthreads();
-                if (threadIdx.x == 0) qn = 0;
-                __syncthreads();
+        if (g == 0) {  // rebuild into an ordered pool of zeros
+            ++r;
+            break;
+        }
+        const uint32_t lo = J.cur[id], hi = J.cur[id + 1];
+        for (uint32_t b0 = lo; b0 < hi; b0 += T) {
+            const uint32_t p = b0 + threadIdx.x;
+            if (p < hi) {
+                const uint32_t w = J.inv[p];
+                if (atomicExch(&J.covered[w], 1u) == 0u) queue[atomicAdd(&qn, 1u)] = w;
             }
+            __syncthreads();
+            const uint32_t n = qn;
+            for (uint32_t qi = wid; qi < n; qi += kWaves) {
+                const uint32_t w = queue[qi];
+                const uint64_t o = J.walk_off[w];
+                const uint32_t L = J.walk_len[w];
+                for (uint32_t e = lane; e < L; e += kWave) {
+                    const uint32_t x = J.ids[o + e];
+                    if (x != id) atomicSub(&J.cnt[x], 1u);
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) qn = 0;
+            __syncthreads();
         }
         __syncthreads();
     }
+    __syncthreads();
     if (threadIdx.x == 0) st->rounds = static_cast<uint32_t>(r);
 }
 
@@ -513,7 +558,6 @@ GreedyJob carve(const GreedyInput &g)
     J.hist = reinterpret_cast<uint32_t *>(take(4 * kBins));
     J.pool = reinterpret_cast<uint32_t *>(take(4 * kPoolMax));
     J.tiles = reinterpret_cast<uint32_t *>(take(4 * ((S + kScanTile - 1) / kScanTile)));
-    J.st = reinterpret_cast<GreedyState *>(take(sizeof(GreedyState)));
     J.cnt = g.cnt;
     J.walk_off = g.walk_off;
     J.walk_len = g.walk_len;
@@ -534,11 +578,15 @@ size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids,
     const uint64_t S = id_space;
     return al256(4 * (S + 1)) + al256(4 * std::max<uint64_t>(n_ids, 1)) +
            al256(4 * std::max<uint64_t>(n_walks, 1)) + 2 * al256(8 * static_cast<uint64_t>(k)) +
-           al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile)) +
-           al256(sizeof(GreedyState));
+           al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile));
 }
 
-size_t greedy_job_table_bytes(uint32_t n_jobs) { return sizeof(GreedyJob) * n_jobs; }
+// job table: n_jobs GreedyJob records, then their n_jobs states (one copy
+// reads every state back)
+size_t greedy_job_table_bytes(uint32_t n_jobs)
+{
+    return al256(sizeof(GreedyJob) * n_jobs) + sizeof(GreedyState) * n_jobs;
+}
 
 void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_t s, bool timing,
                      GreedyResult *res)
@@ -563,6 +611,9 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     const unsigned cus = static_cast<unsigned>(device_cu_count());
     const unsigned tiles = static_cast<unsigned>((max_S + kScanTile - 1) / kScanTile);
     GreedyJob *d_jobs = static_cast<GreedyJob *>(d_job_table);
+    GreedyState *d_states = reinterpret_cast<GreedyState *>(static_cast<char *>(d_job_table) +
+                                                            al256(sizeof(GreedyJob) * Q));
+    for (uint32_t q = 0; q < Q; ++q) jobs[q].st = d_states + q;
 
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (timing) {
@@ -582,23 +633,23 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     if (timing) SIA_HIP(hipEventRecord(ev[1], s));
 
     // pool rebuilds + certified rounds; groups of generations between host checks
+    constexpr unsigned T = 1024;
     const unsigned hist_blocks =
-        std::min(grid_for(max_S, 1024, cus), std::max(1u, cus / std::min<unsigned>(Q, 8)));
+        std::min(grid_for(max_S, T, cus), std::max(1u, cus / std::min<unsigned>(Q, 8)));
     const unsigned collect_blocks = grid_for(max_S, 256, cus * 4);
     std::vector<GreedyState> hs(Q);
     for (int group = 1;; group = std::min(group * 2, 8)) {
         for (int gen = 0; gen < group; ++gen) {
-            hipLaunchKernelGGL(k_hist, dim3(hist_blocks, Q), dim3(1024), 0, s, d_jobs);
-            hipLaunchKernelGGL(k_plan, dim3(Q), dim3(kPlanThreads), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_hist<T>, dim3(hist_blocks, Q), dim3(T), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_plan<T>, dim3(Q), dim3(T), 0, s, d_jobs);
             hipLaunchKernelGGL(k_collect, dim3(collect_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_tie_count, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_tie_scan, dim3(1, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_tie_emit, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
-            hipLaunchKernelGGL(k_lazy, dim3(Q), dim3(kLazyThreads), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_lazy<T>, dim3(Q), dim3(T), 0, s, d_jobs);
             SIA_HIP(hipGetLastError());
         }
-        for (uint32_t q = 0; q < Q; ++q)
-            SIA_HIP(hipMemcpyAsync(&hs[q], jobs[q].st, sizeof(GreedyState), hipMemcpyDeviceToHost, s));
+        SIA_HIP(hipMemcpyAsync(hs.data(), d_states, sizeof(GreedyState) * Q, hipMemcpyDeviceToHost, s));
         SIA_HIP(hipStreamSynchronize(s));
         bool all = true;
         for (uint32_t q = 0; q < Q; ++q) {

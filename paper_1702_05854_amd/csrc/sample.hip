@@ -441,7 +441,8 @@ void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
     A.chunk = cfg.chunk;
     A.table = d_table;
     A.guard_evals = 3 * static_cast<uint64_t>(g->n) + 8;
-    hipLaunchKernelGGL(k_sample, dim3(per_cu * device_cu_count()), dim3(256), 0, s, A);
+    const int cus = cfg.cus > 0 ? std::min(cfg.cus, device_cu_count()) : device_cu_count();
+    hipLaunchKernelGGL(k_sample, dim3(per_cu * cus), dim3(256), 0, s, A);
     SIA_HIP(hipGetLastError());
 }
 

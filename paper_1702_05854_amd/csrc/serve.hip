@@ -77,6 +77,7 @@ struct Slot {
 constexpr uint64_t kBytesPerWalk = 8 + 8 + 4;  // attempt, offset, length
 constexpr uint64_t kWalkSlack = 1024, kIdSlack = 16384;
 constexpr double kHeadroom = 1.3;
+constexpr double kGreedyMaxWait = 0.1;  // s a finished query waits at most for a greedy batch
 
 uint64_t walk_bytes_of(uint64_t walks, uint64_t ids) { return walks * kBytesPerWalk + ids * 4; }
 
@@ -120,6 +121,7 @@ struct sia_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     SamplerConfig exec_cfg{};
+    int sampler_cus = 0;  // CUs of the sampling stream (0: all)
 
     std::mutex mu;
     std::condition_variable cv_sampler, cv_greedy, cv_done;
@@ -147,6 +149,7 @@ struct sia_batch {
         SamplerConfig sc;
         sc.blocks_per_cu = cfg.sampler_blocks_per_cu;
         sc.chunk = cfg.refill_chunk;
+        sc.cus = sampler_cus;
         return sc;
     }
 
@@ -420,6 +423,7 @@ struct sia_batch {
                 cv_sampler.wait(lk, [&] {
                     if (stop) return true;
                     if (tuning) return false;
+                    if (!concurrent() && !ready.empty()) return true;
                     if (stalled && mem_epoch == seen_epoch) return false;
                     return sampling_locked() || (!pending.empty() && free_slot_locked());
                 });
@@ -464,6 +468,9 @@ struct sia_batch {
                 }
                 plan(active, in_wave, chunk);
                 if (in_wave.empty()) {
+                    // time-sliced: finished queries hold memory and slots; their
+                    // greedy (on this thread) is what frees them
+                    if (!concurrent() && run_greedy_if(true)) continue;
                     if (!active.empty()) resolve_stall(active, stalled);
                     continue;
                 }
@@ -477,15 +484,45 @@ struct sia_batch {
                     h_ctr_in[i * ST_COUNT + ST_IDS] = t.wm_ids;
                 }
                 fill_wave_table(*h_table, items.data(), static_cast<uint32_t>(items.size()), n_slots);
+                const auto w0 = Clock::now();
                 const bool replay = run_wave();
+                const double dt = std::chrono::duration<double>(Clock::now() - w0).count();
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    ctr.sample_busy_s += dt;
+                }
                 spins = 0;
                 commit(in_wave, chunk, replay);
+                if (!concurrent()) run_greedy_if(false);
             } catch (const Error &e) {
                 fail_sampling(e.status, e.msg);
             } catch (const std::exception &e) {
                 fail_sampling(SIA_EDEVICE, e.what());
             }
         }
+    }
+
+    bool concurrent() const { return cfg.greedy_mode != 0; }
+
+    // Time-sliced mode: run the greedy of the finished queries between
+    // sampling launches once enough of them wait (greedy_batch), or when
+    // sampling cannot proceed without it: nothing left to sample, a queued
+    // query waits for a slot they hold, the oldest has waited long, or
+    // (force) the launch planner found no share to run.
+    bool run_greedy_if(bool force)
+    {
+        std::vector<TicketP> batch;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (ready.empty()) return false;
+            const bool due = force || ready.size() >= cfg.greedy_batch || !sampling_locked() ||
+                             (!pending.empty() && !free_slot_locked()) ||
+                             now() - ready.front()->info.t_sampled > kGreedyMaxWait;
+            if (!due) return false;
+            batch = take_ready_locked();
+        }
+        if (!batch.empty()) run_greedy_batch(batch);
+        return true;
     }
 
     // Choose each active query's share and make its buffer room for it.
@@ -653,6 +690,8 @@ struct sia_batch {
     }
 
     // ------------------------------------------------------------ greedy thread
+    // Concurrent mode: the greedy thread runs every finished query's greedy
+    // on its own stream as soon as it is ready.
     void greedy_loop()
     {
         (void)hipSetDevice(g->device);
@@ -660,80 +699,98 @@ struct sia_batch {
             std::vector<TicketP> batch;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_greedy.wait(lk, [&] { return stop || !ready.empty(); });
+                cv_greedy.wait(lk, [&] { return stop || (concurrent() && !ready.empty()); });
                 if (stop) return;
-                while (!ready.empty()) {
-                    TicketP t = ready.front();
-                    ready.pop_front();
-                    if (t->cancel) {
-                        finish_locked(t, SIA_ECANCELLED, "cancelled");
-                        continue;
-                    }
-                    t->state = TState::Greedy;
-                    batch.push_back(t);
-                }
-                greedy_running = batch.size();
+                batch = take_ready_locked();
             }
-            if (batch.empty()) continue;
-            sia_status st = SIA_OK;
-            std::string msg;
-            try {
-                std::vector<GreedyInput> in(batch.size());
-                for (size_t q = 0; q < batch.size(); ++q) {
-                    Ticket &t = *batch[q];
-                    Slot &sl = slots[t.slot];
-                    const uint64_t S = t.mode == SIA_EDGES ? static_cast<uint64_t>(g->m) : static_cast<uint64_t>(g->n);
-                    sl.cnt.ensure(4 * S);
-                    sl.greedy.ensure(greedy_scratch_bytes(S, t.wm_walks, t.wm_ids, t.k));
-                    t.selected.assign(static_cast<size_t>(t.k), 0);
-                    t.gains.assign(static_cast<size_t>(t.k), 0);
-                    GreedyInput &gi = in[q];
-                    gi.walk_off = sl.walk_off.as<uint64_t>();
-                    gi.walk_len = sl.walk_len.as<uint32_t>();
-                    gi.ids = sl.ids.as<uint32_t>();
-                    gi.id_space = S;
-                    gi.n_walks = t.wm_walks;
-                    gi.n_ids = t.wm_ids;
-                    gi.k = t.k;
-                    gi.cnt = sl.cnt.as<uint32_t>();
-                    gi.counts_ready = false;
-                    gi.scratch = sl.greedy.ptr;
-                    gi.selected = t.selected.data();
-                    gi.gains = t.gains.data();
-                }
-                GreedyResult res;
-                run_greedy_jobs(in, d_jobs.ptr, s_greedy, false, &res);
-            } catch (const Error &e) {
-                st = e.status;
-                msg = e.msg;
-            } catch (const std::exception &e) {
-                st = SIA_EDEVICE;
-                msg = e.what();
+            if (!batch.empty()) run_greedy_batch(batch);
+        }
+    }
+
+    // Move the ready queries into the greedy (cancelled ones finish here).
+    std::vector<TicketP> take_ready_locked()
+    {
+        std::vector<TicketP> batch;
+        while (!ready.empty()) {
+            TicketP t = ready.front();
+            ready.pop_front();
+            if (t->cancel) {
+                finish_locked(t, SIA_ECANCELLED, "cancelled");
+                continue;
             }
+            t->state = TState::Greedy;
+            batch.push_back(t);
+        }
+        greedy_running = batch.size();
+        return batch;
+    }
+
+    // Index + greedy of a batch of queries in shared launches; finishes them.
+    void run_greedy_batch(const std::vector<TicketP> &batch)
+    {
+        sia_status st = SIA_OK;
+        std::string msg;
+        try {
+            std::vector<GreedyInput> in(batch.size());
+            for (size_t q = 0; q < batch.size(); ++q) {
+                Ticket &t = *batch[q];
+                Slot &sl = slots[t.slot];
+                const uint64_t S = t.mode == SIA_EDGES ? static_cast<uint64_t>(g->m) : static_cast<uint64_t>(g->n);
+                sl.cnt.ensure(4 * S);
+                sl.greedy.ensure(greedy_scratch_bytes(S, t.wm_walks, t.wm_ids, t.k));
+                t.selected.assign(static_cast<size_t>(t.k), 0);
+                t.gains.assign(static_cast<size_t>(t.k), 0);
+                GreedyInput &gi = in[q];
+                gi.walk_off = sl.walk_off.as<uint64_t>();
+                gi.walk_len = sl.walk_len.as<uint32_t>();
+                gi.ids = sl.ids.as<uint32_t>();
+                gi.id_space = S;
+                gi.n_walks = t.wm_walks;
+                gi.n_ids = t.wm_ids;
+                gi.k = t.k;
+                gi.cnt = sl.cnt.as<uint32_t>();
+                gi.counts_ready = false;
+                gi.scratch = sl.greedy.ptr;
+                gi.selected = t.selected.data();
+                gi.gains = t.gains.data();
+            }
+            GreedyResult res;
+            const auto g0 = Clock::now();
+            run_greedy_jobs(in, d_jobs.ptr, s_greedy, true, &res);
+            const double dt = std::chrono::duration<double>(Clock::now() - g0).count();
             std::lock_guard<std::mutex> lk(mu);
-            ++ctr.greedy_launches;
-            ctr.greedy_jobs += batch.size();
-            greedy_running = 0;
-            for (const TicketP &tp : batch) {
-                Ticket &t = *tp;
-                if (st == SIA_OK) {
-                    sia_stats S{};
-                    S.hits = t.hits;
-                    S.dead_ends = t.dead;
-                    S.cycles = t.cycles;
-                    S.steps = t.steps;
-                    S.evaluations = t.evals;
-                    S.walk_ids = t.wm_ids;
-                    finish_stats(S, t.st, t.mode, t.n_attempts, t.selected.data(), t.gains.data(), t.k);
-                    t.stats = S;
-                }
-                finish_locked(tp, st != SIA_OK ? st : (t.cancel ? SIA_ECANCELLED : SIA_OK),
-                              st != SIA_OK ? msg : (t.cancel ? "cancelled" : ""));
+            ctr.greedy_busy_s += dt;
+            ctr.greedy_index_s += res.ms_count * 1e-3;
+        } catch (const Error &e) {
+            st = e.status;
+            msg = e.msg;
+        } catch (const std::exception &e) {
+            st = SIA_EDEVICE;
+            msg = e.what();
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        ++ctr.greedy_launches;
+        ctr.greedy_jobs += batch.size();
+        greedy_running = 0;
+        for (const TicketP &tp : batch) {
+            Ticket &t = *tp;
+            if (st == SIA_OK) {
+                sia_stats S{};
+                S.hits = t.hits;
+                S.dead_ends = t.dead;
+                S.cycles = t.cycles;
+                S.steps = t.steps;
+                S.evaluations = t.evals;
+                S.walk_ids = t.wm_ids;
+                finish_stats(S, t.st, t.mode, t.n_attempts, t.selected.data(), t.gains.data(), t.k);
+                t.stats = S;
             }
-            if (st == SIA_EDEVICE) {
-                fatal = st;
-                fatal_msg = msg;
-            }
+            finish_locked(tp, st != SIA_OK ? st : (t.cancel ? SIA_ECANCELLED : SIA_OK),
+                          st != SIA_OK ? msg : (t.cancel ? "cancelled" : ""));
+        }
+        if (st == SIA_EDEVICE) {
+            fatal = st;
+            fatal_msg = msg;
         }
     }
 
@@ -844,6 +901,7 @@ sia_batch_config defaults(const sia_batch_config *c)
     if (!d.refill_chunk) d.refill_chunk = 256;
     if (!d.wave_attempts) d.wave_attempts = uint64_t(1) << 23;
     if (!d.min_share) d.min_share = uint64_t(1) << 16;
+    if (!d.greedy_batch) d.greedy_batch = 8;
     return d;
 }
 
@@ -945,8 +1003,26 @@ sia_status sia_batch_create(const sia_graph *cg, uint64_t walk_budget_bytes, int
                 if (b) destroy_batch(b.release());
             }
         } undo{b};
-        SIA_HIP(hipStreamCreateWithFlags(&raw->s_sample, hipStreamNonBlocking));
-        SIA_HIP(hipStreamCreateWithFlags(&raw->s_greedy, hipStreamNonBlocking));
+        const int cus = device_cu_count();
+        SIA_REQUIRE(raw->cfg.greedy_cus >= 0 && raw->cfg.greedy_cus < cus, SIA_EINVAL,
+                    "greedy_cus must be in [0, number of CUs)");
+        SIA_REQUIRE(raw->cfg.greedy_mode == 0 || raw->cfg.greedy_mode == 1, SIA_EINVAL,
+                    "greedy_mode must be 0 or 1");
+        SIA_REQUIRE(raw->cfg.greedy_cus == 0 || raw->cfg.greedy_mode == 1, SIA_EINVAL,
+                    "greedy_cus needs greedy_mode 1");
+        if (raw->cfg.greedy_cus > 0) {
+            // disjoint CU sets: the sampler keeps the first CUs, the greedy the last
+            const uint32_t words = static_cast<uint32_t>((cus + 31) / 32);
+            std::vector<uint32_t> ms(words, 0), mg(words, 0);
+            const int split = cus - raw->cfg.greedy_cus;
+            for (int c = 0; c < cus; ++c) (c < split ? ms : mg)[c / 32] |= 1u << (c % 32);
+            SIA_HIP(hipExtStreamCreateWithCUMask(&raw->s_sample, words, ms.data()));
+            SIA_HIP(hipExtStreamCreateWithCUMask(&raw->s_greedy, words, mg.data()));
+            raw->sampler_cus = split;
+        } else {
+            SIA_HIP(hipStreamCreateWithFlags(&raw->s_sample, hipStreamNonBlocking));
+            SIA_HIP(hipStreamCreateWithFlags(&raw->s_greedy, hipStreamNonBlocking));
+        }
         SIA_HIP(hipHostMalloc(reinterpret_cast<void **>(&raw->h_table), sizeof(WaveTable), hipHostMallocDefault));
         SIA_HIP(hipHostMalloc(reinterpret_cast<void **>(&raw->h_slots), sizeof(SlotDev) * raw->n_slots,
                               hipHostMallocDefault));

@@ -51,7 +51,8 @@ class Query(C.Structure):
 class BatchConfig(C.Structure):
     _fields_ = [("sampler_blocks_per_cu", C.c_int32), ("refill_chunk", C.c_uint32),
                 ("wave_attempts", C.c_uint64), ("min_share", C.c_uint64),
-                ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+                ("use_graph", C.c_int32), ("greedy_mode", C.c_int32), ("greedy_cus", C.c_int32),
+                ("greedy_batch", C.c_uint32), ("reserved", C.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
@@ -71,7 +72,8 @@ class BatchStats(C.Structure):
         "greedy_launches", "greedy_jobs", "reruns", "evictions", "walk_bytes", "walk_bytes_peak",
         "walk_budget")] + [("slots", C.c_uint32), ("busy_slots", C.c_uint32),
                            ("pending", C.c_uint32), ("reserved", C.c_uint32),
-                           ("config", BatchConfig)]
+                           ("sample_busy_s", C.c_double), ("greedy_busy_s", C.c_double),
+                           ("greedy_index_s", C.c_double), ("config", BatchConfig)]
 
     def as_dict(self):
         d = {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

@@ -96,10 +96,13 @@ def test_mix_matches_solo_and_oracle_er1k(sia, er1k):
             assert got[i]["stats"]["hits"] == ref["walks"].hits
 
 
-def test_mix_matches_solo_rmat16_more_queries_than_slots(sia, rmat16):
+@pytest.mark.parametrize("greedy", [(0, 0, 8), (0, 0, 1), (1, 0, 0), (1, 32, 0)])
+def test_mix_matches_solo_rmat16_more_queries_than_slots(sia, rmat16, greedy):
     wl, g = rmat16
+    mode, cus, batch = greedy
     qs = mix(wl.n, 40, 12, max_sources=1000, k_range=(10, 200), attempts_range=(10_000, 1_000_000))
-    got, st = serve(sia, g, qs)
+    got, st = serve(sia, g, qs, greedy_mode=mode, greedy_cus=cus, greedy_batch=batch)
+    assert st["config"]["greedy_mode"] == mode and st["config"]["greedy_cus"] == cus
     say("served", st["completed"], "in", st["waves"], "waves,", st["greedy_launches"], "greedy launches")
     assert st["completed"] == 40 and st["greedy_jobs"] == 40
     assert st["greedy_launches"] < 40  # greedies shared launches

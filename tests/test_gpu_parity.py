@@ -233,6 +233,31 @@ def test_greedy_ties_and_many_rounds(sia, case):
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
+@pytest.mark.parametrize("case", ["many_pools", "collected_then_zero", "nodes_like"])
+def test_greedy_zero_gain_tails(sia, case):
+    """k far above the number of ids any walk holds: after the last positive
+    gain the remaining picks are the lowest unselected ids, taken across
+    several pool rebuilds; and a pool whose collected ids fall to zero gain
+    mid-pool before the ordered pool of zeros takes over."""
+    rng = np.random.default_rng({"many_pools": 4, "collected_then_zero": 5, "nodes_like": 6}[case])
+    if case == "many_pools":
+        id_space, n_walks, k = 50_000, 300, 20_000
+        walks = [rng.choice(id_space, rng.integers(1, 4), replace=False) for _ in range(n_walks)]
+    elif case == "collected_then_zero":
+        id_space, n_walks, k = 3_000, 600, 3_000
+        walks = [rng.choice(id_space, rng.integers(1, 4), replace=False) for _ in range(n_walks)]
+    else:
+        id_space, n_walks, k = 9_000, 40, 8_999
+        walks = [rng.choice(id_space, rng.integers(1, 30), replace=False) for _ in range(n_walks)]
+    walks = [np.asarray(w, np.uint32) for w in walks]
+    off = np.zeros(n_walks + 1, np.uint64)
+    off[1:] = np.cumsum([w.shape[0] for w in walks])
+    ids = np.concatenate(walks)
+    got = sia.greedy(id_space, off, ids, k)
+    ref = cpu.greedy_csr(id_space, off, ids, k)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
 def test_greedy_empty_and_exhaustive(sia):
     sel, gains = sia.greedy(5, np.zeros(1, np.uint64), np.zeros(0, np.uint32), 5)
     assert sel.tolist() == [0, 1, 2, 3, 4] and gains.tolist() == [0] * 5
