@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_sample_rmat24.json")
 KERNEL_SOURCES = ["paper_1702_05854_amd/csrc/sample.hip", "paper_1702_05854_amd/csrc/philox.hpp",
-                  "paper_1702_05854_amd/csrc/common.hpp"]
+                  "paper_1702_05854_amd/csrc/layout.hpp"]
 
 
 def kernel_sha():

@@ -1,0 +1,75 @@
+// Device-side records shared by the host code and the sampling kernel: the
+// graph's node and edge records, a query slot as the sampler sees it, the
+// work table of one sampling launch and the per-query counters.
+#pragma once
+
+#include <cstdint>
+
+namespace sia {
+
+// One 16-byte record per node: where its in-edges start, how many, the last
+// cumulative threshold (so the dead-end test needs no extra load), and the
+// source tag: bit b is set exactly when the node is a source of the query
+// holding slot bit b (so membership comes with the record the walk loads
+// anyway).  Bit 31 belongs to single-query calls, bits 0..30 to batches.
+struct NodeRec {
+    uint32_t off;
+    uint32_t deg;
+    uint32_t thr_last;
+    uint32_t tag;
+};
+static_assert(sizeof(NodeRec) == 16, "NodeRec layout");
+
+// One 8-byte record per edge: cumulative threshold and tail node u, so the
+// probe that certifies the choice also yields the next node.
+struct EdgeRec {
+    uint32_t thr;
+    uint32_t row;
+};
+static_assert(sizeof(EdgeRec) == 8, "EdgeRec layout");
+
+// Per-query counters written by the sampler.
+enum StatSlot {
+    ST_WALKS = 0, ST_IDS = 1, ST_HITS = 2, ST_DEAD = 3, ST_CYCLE = 4, ST_STEPS = 5,
+    ST_EVALS = 6, ST_OVERFLOW = 7, ST_FAULTS = 8, ST_COUNT = 16
+};
+
+constexpr uint32_t kSoloBit = 31;   // source-tag bit of single-query calls
+constexpr uint32_t kMaxSlots = 31;  // source-tag bits 0..30 for batches
+
+// Device-side state of one query while it samples (read by the sampler).
+struct SlotDev {
+    uint64_t seed;
+    uint64_t attempt_base;   // attempt id of the query's local attempt 0
+    uint64_t n_ns;           // non-sources
+    const uint32_t *src_t;   // t_i = s_i - i over the sorted sources
+    const uint32_t *bucket;  // bucket[b] = #{i : t_i < b << bucket_shift}
+    uint32_t n_src;
+    uint32_t bucket_shift;
+    uint32_t tag_mask;       // source-tag bit of this query
+    uint32_t mode;           // SIA_EDGES / SIA_NODES
+    uint64_t *walk_attempt;  // kept walks: attempt id, offset, length
+    uint64_t *walk_off;
+    uint32_t *walk_len;
+    uint32_t *ids;
+    uint32_t *cnt;           // coverage counts (nullptr: not counted)
+    uint64_t walk_cap;
+    uint64_t id_cap;
+    uint64_t *counters;      // StatSlot entries
+};
+
+// The work table a sampling launch reads from device memory: the wave's
+// items laid end to end and the chunk counter the persistent lanes draw
+// from.  Host code fills it (fill_wave_table) and copies it to the device
+// before each launch, so a captured launch can be replayed with new contents.
+constexpr uint32_t kMaxItems = 32;
+struct WaveTable {
+    uint64_t next[8];                // next[0]: wave-global chunk counter (own 64-B line)
+    uint64_t prefix[kMaxItems + 1];  // wave-global index of each item's first attempt
+    uint64_t local[kMaxItems];       // local attempt index of each item's first attempt
+    uint32_t slot[kMaxItems];
+    uint32_t n_items;
+    uint32_t pad;
+};
+
+}  // namespace sia
