@@ -425,7 +425,14 @@ __device__ __forceinline__ uint32_t load_count(const uint32_t *p)
 }
 
 // One workgroup of T threads per job: rounds [rounds, k) while the pool
-// certifies the pick.
+// certifies the pick.  The pool's ids stay in registers for the whole launch
+// (at most kPoolMax / T per thread), so a round's scan is one load of each
+// pool id's count.  Covering: each pass claims up to T of the chosen id's
+// walks (one list entry per thread), a block scan of their lengths lays
+// their ids end to end, and every thread decrements the counts of the ids
+// at its positions (finding the walk by binary search over the pass's
+// starts in LDS): a fixed number of dependent memory accesses per pass
+// however the ids spread over walks.
 //
 // Zero gains.  When the best key of the pool has gain 0, every unselected id
 // of the pool has count 0.  If the pool is exactly the lowest-id ids that had
@@ -438,10 +445,11 @@ template <int T>
 __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
 {
     constexpr int kWaves = T / kWave;
+    constexpr int kPer = kPoolMax / T;
     __shared__ uint64_t sh[kWaves];
     __shared__ uint32_t sh32[kWaves];
-    __shared__ uint32_t queue[T];
-    __shared__ uint32_t qn;
+    __shared__ uint32_t start[T];  // a pass's walks: first flattened position
+    __shared__ uint64_t woff[T];   //                 and offset into ids
     const GreedyJob J = jobs[blockIdx.x];
     if (job_done(J)) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -452,18 +460,25 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
                              ? ((static_cast<uint64_t>(st->c_tie) + 1) << 32) | (0xFFFFFFFFu - st->next_id)
                              : st->tau;
     const bool ordered_zeros = ties && st->c_tie == 0 && st->pool_n == 0;
+    uint32_t pid[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const uint32_t i = threadIdx.x + j * T;
+        pid[j] = i < P ? J.pool[i] : 0u;
+    }
     int64_t r = st->rounds;
     for (; r < J.k; ++r) {
         // exact keys of the pool; the largest is this round's pick if it beats tau
         uint64_t best = 0;
-        for (uint32_t i = threadIdx.x; i < P; i += T) {
-            const uint32_t id = J.pool[i];
-            const uint64_t key = key_of(load_count(&J.cnt[id]), id);
-            best = key > best ? key : best;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (threadIdx.x + j * T < P) {
+                const uint64_t key = key_of(load_count(&J.cnt[pid[j]]), pid[j]);
+                best = key > best ? key : best;
+            }
         }
         best = wave_max_u64(best);
         if (lane == 0) sh[wid] = best;
-        if (threadIdx.x == 0) qn = 0;
         __syncthreads();
         best = sh[0];
         for (int w = 1; w < kWaves; ++w) best = sh[w] > best ? sh[w] : best;
@@ -505,26 +520,49 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
         const uint32_t lo = J.cur[id], hi = J.cur[id + 1];
         for (uint32_t b0 = lo; b0 < hi; b0 += T) {
             const uint32_t p = b0 + threadIdx.x;
+            uint32_t len = 0;
+            uint64_t off = 0;
             if (p < hi) {
                 const uint32_t w = J.inv[p];
-                if (atomicExch(&J.covered[w], 1u) == 0u) queue[atomicAdd(&qn, 1u)] = w;
-            }
-            __syncthreads();
-            const uint32_t n = qn;
-            for (uint32_t qi = wid; qi < n; qi += kWaves) {
-                const uint32_t w = queue[qi];
+                // the walk record is read beside the claim (used only if claimed)
                 const uint64_t o = J.walk_off[w];
-                const uint32_t L = J.walk_len[w];
-                for (uint32_t e = lane; e < L; e += kWave) {
-                    const uint32_t x = J.ids[o + e];
-                    if (x != id) atomicSub(&J.cnt[x], 1u);
+                const uint32_t l = J.walk_len[w];
+                if (atomicExch(&J.covered[w], 1u) == 0u) {
+                    off = o;
+                    len = l;
                 }
             }
+            uint32_t total;
+            const uint32_t first = block_excl_scan<T>(len, sh32, total);  // ends with a barrier
+            start[threadIdx.x] = first;
+            woff[threadIdx.x] = off;
             __syncthreads();
-            if (threadIdx.x == 0) qn = 0;
-            __syncthreads();
+            // positions f = threadIdx.x + u*T, kUnroll at a time: every id load
+            // of a group is issued before its decrements
+            constexpr int kUnroll = 8;
+            for (uint32_t f0 = threadIdx.x; f0 < total; f0 += kUnroll * T) {
+                uint32_t x[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint32_t f = f0 + u * T;
+                    x[u] = id;
+                    if (f < total) {
+                        // the last pass entry whose first position is <= f holds position f
+                        uint32_t a = 0, b = T - 1;
+                        while (a < b) {
+                            const uint32_t m = (a + b + 1) >> 1;
+                            if (start[m] <= f) a = m;
+                            else b = m - 1;
+                        }
+                        x[u] = J.ids[woff[a] + (f - start[a])];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    if (x[u] != id) atomicSub(&J.cnt[x[u]], 1u);
+            }
+            __syncthreads();  // decrements done and LDS free before the next pass / round
         }
-        __syncthreads();
     }
     __syncthreads();
     if (threadIdx.x == 0) st->rounds = static_cast<uint32_t>(r);

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
     uint64_t a = 0, out_pos = 0, seed = 0;
     uint32_t slot = 0, mode = SIA_EDGES, tag_mask = 0;
     uint32_t phase = PH_START, x1 = 0, cur = 0, tort = 0, power = 1, lam = 0, t = 0, lambda = 0,
-             cnt = 0, pa = 0, pb = 0, evals = 0;
+             cnt = 0, pa = 0, pb = 0, evals = 0, ptort = 0, mbase = 0;
 
     for (;;) {
         // ---- refill idle lanes with new attempts (converged section)
@@ -212,13 +212,21 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 if (t > 0) {
                     ++lam;
                     if (cur == tort) {  // Brent: cycle of length lam (tort is never a source)
+                        // The tortoise sits at positions 2^j - 1 with a window of
+                        // 2^j.  If lam fits half the final window, the previous
+                        // tortoise (position power/2 - 1) was off the cycle --
+                        // else its window would have found it -- so the search
+                        // for the cycle entry mu starts there, not at x1.
+                        const bool past = lam <= (power >> 1);
                         lambda = lam;
                         cnt = lam;
-                        pa = x1;
-                        pb = x1;
+                        mbase = past ? (power >> 1) - 1u : 0u;
+                        pa = past ? ptort : x1;
+                        pb = pa;
                         phase = PH_MU_POS;
                         y = pb;
                     } else if (lam == power) {
+                        ptort = tort;
                         tort = cur;
                         power <<= 1;
                         lam = 0;
@@ -326,9 +334,9 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
             } else if (phase == PH_MU_POS) {
                 pb = u;
                 if (--cnt == 0) {
-                    if (pa == pb) {  // the start lies on the cycle: mu = 0
+                    if (pa == pb) {  // the search start lies on the cycle: mu = mbase (= 0)
                         atomicAdd(&acc[slot][2], 1ull);
-                        atomicAdd(&acc[slot][3], static_cast<unsigned long long>(lambda));
+                        atomicAdd(&acc[slot][3], static_cast<unsigned long long>(mbase) + lambda);
                         done = true;
                     } else {
                         phase = PH_MU_A;
@@ -340,9 +348,9 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
             } else if (phase == PH_MU_B) {
                 pb = u;
                 ++cnt;
-                if (pa == pb) {  // first repeat after mu + lambda draws
+                if (pa == pb) {  // first repeat after mu + lambda draws, mu = mbase + cnt
                     atomicAdd(&acc[slot][2], 1ull);
-                    atomicAdd(&acc[slot][3], static_cast<unsigned long long>(cnt) + lambda);
+                    atomicAdd(&acc[slot][3], static_cast<unsigned long long>(mbase) + cnt + lambda);
                     done = true;
                 } else if (cnt > t) {
                     atomicAdd(&acc[slot][5], 1ull);
