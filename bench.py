@@ -300,7 +300,7 @@ def main():
         "steps_per_s": st["steps"] * args.steps / elapsed,
         "evaluations_per_s": st["evaluations"] * args.steps / elapsed,
         "sampler_attempts_per_s": n_att / (ms_sample * 1e-3),
-        "ms_sample": ms_sample, "ms_count_index": ms_count, "ms_greedy": ms_greedy,
+        "ms_sample": ms_sample, "ms_count": ms_count, "ms_greedy": ms_greedy,
         "ingest_ms": ingest_ms,
         "counts": {key: st[key] for key in ("hits", "dead_ends", "cycles", "steps", "evaluations",
                                             "walk_ids", "covered")},

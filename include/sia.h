@@ -74,8 +74,9 @@ typedef struct {
     double suspension_nodes_est; /* suspension_est + |selected & X| (nodes) */
     float ms_sample;       /* device time of the sampling kernel (HIP events,
                               on hip_stream), 0 unless timing was requested */
-    float ms_count;        /* coverage counting + inverted index */
-    float ms_greedy;       /* greedy rounds */
+    float ms_count;        /* coverage counting and greedy set-up */
+    float ms_greedy;       /* greedy: pool rebuilds, walk lists of pool
+                              ids, rounds */
     float ms_total;        /* whole call on the device */
 } sia_stats;
 

@@ -3,7 +3,6 @@
 //
 //   cnt[id] = number of not-yet-covered walks holding id (Cov of one id),
 //             exact at all times; 0xFFFFFFFF once id is selected;
-//   inv     = inverted index id -> walks, a counting sort driven by cnt;
 //   key(id) = ((cnt+1) << 32) | (2^32-1-id) for an unselected id, 0 once
 //             selected: the largest key is the largest marginal gain with the
 //             lowest id on ties, and once every gain is zero the lowest id not
@@ -20,6 +19,12 @@
 // device, chooses the threshold, and ties at the threshold are taken by
 // ascending id (ordered compaction).  The result is exactly the greedy of
 // Algorithm 4 / 7.
+//
+// Walk lists.  Covering needs the walks holding the chosen id, and only pool
+// ids can be chosen, so with each pool the lists of its ids that still hold
+// uncovered walks are built (a bitmap marks them; one pass over the
+// uncovered walks appends each walk to the lists of its marked ids).  No
+// inverted index over the whole id space is built.
 //
 // Every kernel takes the job table; blockIdx.y (blockIdx.x for the
 // one-workgroup kernels) selects the job, so the greedies of a batch of
@@ -58,14 +63,17 @@ struct GreedyState {
     uint32_t n_tie;     // PLAN_TIES: tied ids taken, lowest ids first
     uint32_t leftover;  // PLAN_TIES: tied ids were left out
     uint32_t next_id;   // PLAN_TIES: lowest tied id left out
-    uint32_t pad;
+    uint32_t plist_total;  // ids' list entries of the current pool
     uint64_t tau;       // bound on keys outside the pool (without left-out ties)
 };
 
 struct GreedyJob {
     uint32_t *cnt;
-    uint32_t *cur;      // id_space + 1
-    uint32_t *inv;      // n_ids
+    uint32_t *pidx;     // id_space: pool position of a marked id
+    uint32_t *plist;    // n_ids: walk lists of the marked pool ids
+    uint32_t *pstart;   // kPoolMax + 1: list starts (pool order)
+    uint32_t *pfill;    // kPoolMax: list fill counters
+    uint32_t *bitmap;   // ceil(id_space / 32): marked ids
     uint32_t *covered;  // n_walks
     const uint64_t *walk_off;
     const uint32_t *walk_len;
@@ -124,6 +132,11 @@ __device__ __forceinline__ bool job_done(const GreedyJob &J)
 
 __device__ __forceinline__ uint64_t n_tiles_of(uint64_t S) { return (S + kScanTile - 1) / kScanTile; }
 
+__device__ __forceinline__ uint32_t pool_size(const GreedyState *st)
+{
+    return st->pool_n + (st->plan == PLAN_TIES ? st->n_tie : 0u);
+}
+
 // block-wide exclusive scan of one value per thread (T threads; sh holds T/64)
 template <int T>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total)
@@ -181,6 +194,7 @@ __global__ void k_init(const GreedyJob *jobs)
     if (J.need_count)
         for (uint64_t i = t; i < J.S; i += stride) J.cnt[i] = 0;
     for (uint64_t i = t; i < kBins; i += stride) J.hist[i] = 0;
+    for (uint64_t i = t; i < (J.S + 31) / 32; i += stride) J.bitmap[i] = 0;
     if (t == 0) *J.st = GreedyState{};
 }
 
@@ -191,67 +205,6 @@ __global__ void k_count(const GreedyJob *jobs)
     uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (; i < J.n_ids; i += stride) atomicAdd(&J.cnt[J.ids[i]], 1u);
-}
-
-// ---------------------------------------------------------------- inverted index
-// cur = inclusive prefix sum of cnt (tiles of 4096 ids), cur[S] = n_ids.
-__global__ __launch_bounds__(256) void k_scan_reduce(const GreedyJob *jobs)
-{
-    __shared__ uint32_t sh[4];
-    const GreedyJob J = jobs[blockIdx.y];
-    if (blockIdx.x >= n_tiles_of(J.S)) return;  // uniform per block
-    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
-    uint32_t s = 0;
-    for (int i = 0; i < 16; ++i)
-        if (base + i < J.S) s += J.cnt[base + i];
-    uint32_t total;
-    block_excl_scan_256(s, sh, total);
-    if (threadIdx.x == 0) J.tiles[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(256) void k_scan_tiles(const GreedyJob *jobs)
-{
-    const GreedyJob J = jobs[blockIdx.y];
-    scan_tiles_256(J.tiles, n_tiles_of(J.S));
-}
-
-__global__ __launch_bounds__(256) void k_scan_down(const GreedyJob *jobs)
-{
-    __shared__ uint32_t sh[4];
-    const GreedyJob J = jobs[blockIdx.y];
-    if (blockIdx.x >= n_tiles_of(J.S)) return;
-    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
-    uint32_t v[16];
-    uint32_t s = 0;
-    for (int i = 0; i < 16; ++i) {
-        v[i] = base + i < J.S ? J.cnt[base + i] : 0u;
-        s += v[i];
-    }
-    uint32_t total;
-    uint32_t run = J.tiles[blockIdx.x] + block_excl_scan_256(s, sh, total);
-    for (int i = 0; i < 16; ++i) {
-        run += v[i];
-        if (base + i < J.S) J.cur[base + i] = run;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) J.cur[J.S] = static_cast<uint32_t>(J.n_ids);
-}
-
-// cur[id] counts down from the inclusive prefix sum to the start of id's
-// list; walk w is listed under each of its ids.  One wave per walk.
-__global__ __launch_bounds__(256) void k_fill(const GreedyJob *jobs)
-{
-    const GreedyJob J = jobs[blockIdx.y];
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
-    for (uint64_t w = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
-         w < J.n_walks; w += waves) {
-        const uint64_t o = J.walk_off[w];
-        const uint32_t L = J.walk_len[w];
-        for (uint32_t e = lane; e < L; e += kWave) {
-            const uint32_t p = atomicSub(&J.cur[J.ids[o + e]], 1u) - 1u;
-            J.inv[p] = static_cast<uint32_t>(w);
-        }
-    }
 }
 
 // ---------------------------------------------------------------- pool rebuild
@@ -418,6 +371,68 @@ __global__ __launch_bounds__(256) void k_tie_emit(const GreedyJob *jobs)
     }
 }
 
+// ---------------------------------------------------------------- walk lists of the pool
+// Mark every pool id that still holds uncovered walks (bitmap bit and its
+// pool position) and lay out its list: pstart = exclusive prefix over the
+// pool of those counts.  One workgroup per job.  Counts do not change until
+// the lists are filled.
+__global__ __launch_bounds__(1024) void k_pool_mark(const GreedyJob *jobs)
+{
+    __shared__ uint32_t sh[1024 / kWave];
+    const GreedyJob J = jobs[blockIdx.x];
+    if (job_done(J)) return;  // uniform per block
+    GreedyState *st = J.st;
+    const uint32_t P = pool_size(st);
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < P; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        uint32_t c = 0;
+        if (i < P) {
+            const uint32_t id = J.pool[i];
+            const uint32_t v = J.cnt[id];
+            if (v != kSelected && v > 0) {
+                c = v;
+                J.pidx[id] = i;
+                atomicOr(&J.bitmap[id >> 5], 1u << (id & 31));
+            }
+        }
+        uint32_t total;
+        const uint32_t ex = block_excl_scan<1024>(c, sh, total);
+        if (i < P) {
+            J.pstart[i] = carry + ex;
+            J.pfill[i] = 0;
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        J.pstart[P] = carry;
+        st->plist_total = carry;
+    }
+}
+
+// Fill the lists: one wave per uncovered walk; each of its ids that is
+// marked gets the walk appended to its list.
+__global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
+{
+    const GreedyJob J = jobs[blockIdx.y];
+    if (job_done(J) || J.st->plist_total == 0) return;  // uniform per block
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
+    for (uint64_t w = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
+         w < J.n_walks; w += waves) {
+        if (J.covered[w]) continue;  // uniform per wave
+        const uint64_t o = J.walk_off[w];
+        const uint32_t L = J.walk_len[w];
+        for (uint32_t e = lane; e < L; e += kWave) {
+            const uint32_t x = J.ids[o + e];
+            if (J.bitmap[x >> 5] & (1u << (x & 31))) {
+                const uint32_t i = J.pidx[x];
+                J.plist[J.pstart[i] + atomicAdd(&J.pfill[i], 1u)] = static_cast<uint32_t>(w);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- lazy rounds
 __device__ __forceinline__ uint32_t load_count(const uint32_t *p)
 {
@@ -450,6 +465,7 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
     __shared__ uint32_t sh32[kWaves];
     __shared__ uint32_t start[T];  // a pass's walks: first flattened position
     __shared__ uint64_t woff[T];   //                 and offset into ids
+    __shared__ uint32_t win;       // pool position of the chosen id
     const GreedyJob J = jobs[blockIdx.x];
     if (job_done(J)) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -517,13 +533,18 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             ++r;
             break;
         }
-        const uint32_t lo = J.cur[id], hi = J.cur[id + 1];
+        // the chosen id's list: its pool position comes from the thread holding it
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (threadIdx.x + j * T < P && pid[j] == id) win = threadIdx.x + j * T;
+        __syncthreads();
+        const uint32_t lo = J.pstart[win], hi = J.pstart[win + 1];
         for (uint32_t b0 = lo; b0 < hi; b0 += T) {
             const uint32_t p = b0 + threadIdx.x;
             uint32_t len = 0;
             uint64_t off = 0;
             if (p < hi) {
-                const uint32_t w = J.inv[p];
+                const uint32_t w = J.plist[p];
                 // the walk record is read beside the claim (used only if claimed)
                 const uint64_t o = J.walk_off[w];
                 const uint32_t l = J.walk_len[w];
@@ -566,6 +587,10 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
     }
     __syncthreads();
     if (threadIdx.x == 0) st->rounds = static_cast<uint32_t>(r);
+    // unmark the pool (the next rebuild marks its own)
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+        if (threadIdx.x + j * T < P) atomicAnd(&J.bitmap[pid[j] >> 5], ~(1u << (pid[j] & 31)));
 }
 
 unsigned grid_for(uint64_t items, unsigned block, unsigned cap)
@@ -588,8 +613,11 @@ GreedyJob carve(const GreedyInput &g)
         p += al256(bytes);
         return q;
     };
-    J.cur = reinterpret_cast<uint32_t *>(take(4 * (S + 1)));
-    J.inv = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_ids, 1)));
+    J.pidx = reinterpret_cast<uint32_t *>(take(4 * S));
+    J.plist = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_ids, 1)));
+    J.pstart = reinterpret_cast<uint32_t *>(take(4 * (kPoolMax + 1)));
+    J.pfill = reinterpret_cast<uint32_t *>(take(4 * kPoolMax));
+    J.bitmap = reinterpret_cast<uint32_t *>(take(4 * ((S + 31) / 32)));
     J.covered = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
     J.sel = reinterpret_cast<int64_t *>(take(8 * g.k));
     J.gain = reinterpret_cast<uint64_t *>(take(8 * g.k));
@@ -614,7 +642,8 @@ GreedyJob carve(const GreedyInput &g)
 size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids, int64_t k)
 {
     const uint64_t S = id_space;
-    return al256(4 * (S + 1)) + al256(4 * std::max<uint64_t>(n_ids, 1)) +
+    return al256(4 * S) + al256(4 * std::max<uint64_t>(n_ids, 1)) + al256(4 * (kPoolMax + 1)) +
+           al256(4 * kPoolMax) + al256(4 * ((S + 31) / 32)) +
            al256(4 * std::max<uint64_t>(n_walks, 1)) + 2 * al256(8 * static_cast<uint64_t>(k)) +
            al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile));
 }
@@ -662,11 +691,6 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     const uint64_t init_items = std::max<uint64_t>({max_walks, max_S, kBins});
     hipLaunchKernelGGL(k_init, dim3(grid_for(init_items, 256, cus * 8), Q), dim3(256), 0, s, d_jobs);
     hipLaunchKernelGGL(k_count, dim3(grid_for(max_ids, 256, cus * 16), Q), dim3(256), 0, s, d_jobs);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1, Q), dim3(256), 0, s, d_jobs);
-    hipLaunchKernelGGL(k_scan_down, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(max_walks * kWave, 256, cus * 32), Q), dim3(256), 0, s,
-                       d_jobs);
     SIA_HIP(hipGetLastError());
     if (timing) SIA_HIP(hipEventRecord(ev[1], s));
 
@@ -675,6 +699,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     const unsigned hist_blocks =
         std::min(grid_for(max_S, T, cus), std::max(1u, cus / std::min<unsigned>(Q, 8)));
     const unsigned collect_blocks = grid_for(max_S, 256, cus * 4);
+    const unsigned fill_blocks = grid_for(max_walks * kWave, 256, cus * 32);
     std::vector<GreedyState> hs(Q);
     for (int group = 1;; group = std::min(group * 2, 8)) {
         for (int gen = 0; gen < group; ++gen) {
@@ -684,6 +709,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
             hipLaunchKernelGGL(k_tie_count, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_tie_scan, dim3(1, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_tie_emit, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_pool_mark, dim3(Q), dim3(1024), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_pool_fill, dim3(fill_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_lazy<T>, dim3(Q), dim3(T), 0, s, d_jobs);
             SIA_HIP(hipGetLastError());
         }
