@@ -48,7 +48,10 @@ constexpr uint32_t kExact = 4096;
 constexpr uint32_t kPerOctave = 512;
 constexpr uint32_t kBins = kExact + 20 * kPerOctave;  // octaves 2^12 .. 2^31
 constexpr uint32_t kPoolTarget = 4096;
-constexpr uint32_t kPoolMax = 16384;
+constexpr uint32_t kPoolMax = 8192;        // the lazy rounds keep the pool in LDS
+constexpr uint32_t kHashBits = 14;         // id -> pool position hash, load <= 1/2
+constexpr uint32_t kHash = 1u << kHashBits;
+static_assert(kHash >= 2 * kPoolMax, "pool hash load factor");
 
 enum PlanKind : uint32_t { PLAN_COLLECT = 0, PLAN_TIES = 1 };
 
@@ -66,6 +69,8 @@ struct GreedyState {
     uint32_t plist_total;  // ids' list entries of the current pool
     uint64_t tau;       // bound on keys outside the pool (without left-out ties)
 };
+
+static_assert(sizeof(GreedyState) % 8 == 0, "GreedyState is cleared in 8-byte words");
 
 struct GreedyJob {
     uint32_t *cnt;
@@ -91,6 +96,75 @@ struct GreedyJob {
     uint32_t *tiles;    // ceil(S / kScanTile)
     GreedyState *st;
 };
+
+// Device view of a job with its arrays in the global address space (see gp).
+
+struct GJob {
+    GLOBAL uint32_t *cnt;
+    GLOBAL uint32_t *pidx;
+    GLOBAL uint32_t *plist;
+    GLOBAL uint32_t *pstart;
+    GLOBAL uint32_t *pfill;
+    GLOBAL uint32_t *bitmap;
+    GLOBAL uint32_t *covered;
+    const GLOBAL uint64_t *walk_off;
+    const GLOBAL uint32_t *walk_len;
+    const GLOBAL uint32_t *ids;
+    uint64_t S, n_walks, n_ids;
+    int64_t k;
+    uint32_t need_count;
+    GLOBAL int64_t *sel;
+    GLOBAL uint64_t *gain;
+    GLOBAL uint32_t *hist;
+    GLOBAL uint32_t *pool;
+    GLOBAL uint32_t *tiles;
+    GLOBAL GreedyState *st;
+};
+
+__device__ __forceinline__ GJob view(const GreedyJob &j)
+{
+    GJob J;
+    J.cnt = gp(j.cnt);
+    J.pidx = gp(j.pidx);
+    J.plist = gp(j.plist);
+    J.pstart = gp(j.pstart);
+    J.pfill = gp(j.pfill);
+    J.bitmap = gp(j.bitmap);
+    J.covered = gp(j.covered);
+    J.walk_off = gp(j.walk_off);
+    J.walk_len = gp(j.walk_len);
+    J.ids = gp(j.ids);
+    J.S = j.S;
+    J.n_walks = j.n_walks;
+    J.n_ids = j.n_ids;
+    J.k = j.k;
+    J.need_count = j.need_count;
+    J.sel = gp(j.sel);
+    J.gain = gp(j.gain);
+    J.hist = gp(j.hist);
+    J.pool = gp(j.pool);
+    J.tiles = gp(j.tiles);
+    J.st = gp(j.st);
+    return J;
+}
+
+// agent-scope relaxed atomics on global memory
+__device__ __forceinline__ uint32_t g_add(GLOBAL uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t g_xchg(GLOBAL uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t g_or(GLOBAL uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t g_and(GLOBAL uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ uint32_t count_bin(uint32_t c)
 {
@@ -125,14 +199,14 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
     return v;
 }
 
-__device__ __forceinline__ bool job_done(const GreedyJob &J)
+__device__ __forceinline__ bool job_done(const GJob &J)
 {
     return J.st->error != 0 || static_cast<int64_t>(J.st->rounds) >= J.k;
 }
 
 __device__ __forceinline__ uint64_t n_tiles_of(uint64_t S) { return (S + kScanTile - 1) / kScanTile; }
 
-__device__ __forceinline__ uint32_t pool_size(const GreedyState *st)
+__device__ __forceinline__ uint32_t pool_size(const GLOBAL GreedyState *st)
 {
     return st->pool_n + (st->plan == PLAN_TIES ? st->n_tie : 0u);
 }
@@ -167,7 +241,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *sh
 }
 
 // exclusive scan of tiles[0 .. n) in place, one 256-thread workgroup
-__device__ void scan_tiles_256(uint32_t *tiles, uint64_t n)
+__device__ void scan_tiles_256(GLOBAL uint32_t *tiles, uint64_t n)
 {
     __shared__ uint32_t sh[4];
     uint32_t carry = 0;
@@ -187,7 +261,7 @@ __device__ void scan_tiles_256(uint32_t *tiles, uint64_t n)
 // no memset nodes.
 __global__ void k_init(const GreedyJob *jobs)
 {
-    const GreedyJob J = jobs[blockIdx.y];
+    const GJob J = view(jobs[blockIdx.y]);
     const uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (uint64_t i = t; i < J.n_walks; i += stride) J.covered[i] = 0;
@@ -195,16 +269,19 @@ __global__ void k_init(const GreedyJob *jobs)
         for (uint64_t i = t; i < J.S; i += stride) J.cnt[i] = 0;
     for (uint64_t i = t; i < kBins; i += stride) J.hist[i] = 0;
     for (uint64_t i = t; i < (J.S + 31) / 32; i += stride) J.bitmap[i] = 0;
-    if (t == 0) *J.st = GreedyState{};
+    if (t == 0) {
+        GLOBAL uint64_t *w = reinterpret_cast<GLOBAL uint64_t *>(J.st);
+        for (uint32_t i = 0; i < sizeof(GreedyState) / 8; ++i) w[i] = 0;
+    }
 }
 
 __global__ void k_count(const GreedyJob *jobs)
 {
-    const GreedyJob J = jobs[blockIdx.y];
+    const GJob J = view(jobs[blockIdx.y]);
     if (!J.need_count) return;
     uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (; i < J.n_ids; i += stride) atomicAdd(&J.cnt[J.ids[i]], 1u);
+    for (; i < J.n_ids; i += stride) g_add(&J.cnt[J.ids[i]], 1u);
 }
 
 // ---------------------------------------------------------------- pool rebuild
@@ -212,7 +289,7 @@ template <int T>
 __global__ __launch_bounds__(T) void k_hist(const GreedyJob *jobs)
 {
     __shared__ uint32_t h[kBins];
-    const GreedyJob J = jobs[blockIdx.y];
+    const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J)) return;  // uniform per block
     for (uint32_t i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
@@ -224,7 +301,7 @@ __global__ __launch_bounds__(T) void k_hist(const GreedyJob *jobs)
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < kBins; b += blockDim.x)
-        if (h[b]) atomicAdd(&J.hist[b], h[b]);
+        if (h[b]) g_add(&J.hist[b], h[b]);
 }
 
 // Choose the next pool from the histogram (and clear it for the next
@@ -241,7 +318,7 @@ __global__ __launch_bounds__(T) void k_plan(const GreedyJob *jobs)
     __shared__ uint32_t h[kBins];
     __shared__ uint32_t wsum[kWaves];
     __shared__ uint32_t found, bstar, ab_sh;
-    const GreedyJob J = jobs[blockIdx.x];
+    const GJob J = view(jobs[blockIdx.x]);
     if (job_done(J)) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     for (uint32_t b = threadIdx.x; b < kBins; b += T) {
@@ -284,7 +361,7 @@ __global__ __launch_bounds__(T) void k_plan(const GreedyJob *jobs)
         ab = ab_sh;
     }
     const uint64_t ge = static_cast<uint64_t>(ab) + h[b];
-    GreedyState *st = J.st;
+    GLOBAL GreedyState *st = J.st;
     st->pool_n = 0;
     st->next_id = 0;
     if (ge <= kPoolMax && b > 0) {
@@ -311,7 +388,7 @@ __global__ __launch_bounds__(T) void k_plan(const GreedyJob *jobs)
 // Pool += every unselected id with cnt >= c_min.
 __global__ void k_collect(const GreedyJob *jobs)
 {
-    const GreedyJob J = jobs[blockIdx.y];
+    const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J)) return;
     const uint32_t c_min = J.st->c_min;
     if (c_min == 0) return;
@@ -319,7 +396,7 @@ __global__ void k_collect(const GreedyJob *jobs)
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (; i < J.S; i += stride) {
         const uint32_t c = J.cnt[i];
-        if (c != kSelected && c >= c_min) J.pool[atomicAdd(&J.st->pool_n, 1u)] = static_cast<uint32_t>(i);
+        if (c != kSelected && c >= c_min) J.pool[g_add(&J.st->pool_n, 1u)] = static_cast<uint32_t>(i);
     }
 }
 
@@ -327,7 +404,7 @@ __global__ void k_collect(const GreedyJob *jobs)
 __global__ __launch_bounds__(256) void k_tie_count(const GreedyJob *jobs)
 {
     __shared__ uint32_t sh[4];
-    const GreedyJob J = jobs[blockIdx.y];
+    const GJob J = view(jobs[blockIdx.y]);
     if (blockIdx.x >= n_tiles_of(J.S) || job_done(J) || J.st->plan != PLAN_TIES) return;
     const uint32_t c = J.st->c_tie;
     const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
@@ -341,7 +418,7 @@ __global__ __launch_bounds__(256) void k_tie_count(const GreedyJob *jobs)
 
 __global__ __launch_bounds__(256) void k_tie_scan(const GreedyJob *jobs)
 {
-    const GreedyJob J = jobs[blockIdx.y];
+    const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J) || J.st->plan != PLAN_TIES) return;  // uniform per block
     scan_tiles_256(J.tiles, n_tiles_of(J.S));
 }
@@ -351,7 +428,7 @@ __global__ __launch_bounds__(256) void k_tie_scan(const GreedyJob *jobs)
 __global__ __launch_bounds__(256) void k_tie_emit(const GreedyJob *jobs)
 {
     __shared__ uint32_t sh[4];
-    const GreedyJob J = jobs[blockIdx.y];
+    const GJob J = view(jobs[blockIdx.y]);
     if (blockIdx.x >= n_tiles_of(J.S) || job_done(J) || J.st->plan != PLAN_TIES) return;
     const uint32_t R = J.st->n_tie, c = J.st->c_tie;
     if (J.tiles[blockIdx.x] > R) return;  // uniform per block
@@ -379,9 +456,9 @@ __global__ __launch_bounds__(256) void k_tie_emit(const GreedyJob *jobs)
 __global__ __launch_bounds__(1024) void k_pool_mark(const GreedyJob *jobs)
 {
     __shared__ uint32_t sh[1024 / kWave];
-    const GreedyJob J = jobs[blockIdx.x];
+    const GJob J = view(jobs[blockIdx.x]);
     if (job_done(J)) return;  // uniform per block
-    GreedyState *st = J.st;
+    GLOBAL GreedyState *st = J.st;
     const uint32_t P = pool_size(st);
     uint32_t carry = 0;
     for (uint32_t base = 0; base < P; base += 1024) {
@@ -393,7 +470,7 @@ __global__ __launch_bounds__(1024) void k_pool_mark(const GreedyJob *jobs)
             if (v != kSelected && v > 0) {
                 c = v;
                 J.pidx[id] = i;
-                atomicOr(&J.bitmap[id >> 5], 1u << (id & 31));
+                g_or(&J.bitmap[id >> 5], 1u << (id & 31));
             }
         }
         uint32_t total;
@@ -414,7 +491,7 @@ __global__ __launch_bounds__(1024) void k_pool_mark(const GreedyJob *jobs)
 // marked gets the walk appended to its list.
 __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
 {
-    const GreedyJob J = jobs[blockIdx.y];
+    const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J) || J.st->plist_total == 0) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
@@ -427,27 +504,49 @@ __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
             const uint32_t x = J.ids[o + e];
             if (J.bitmap[x >> 5] & (1u << (x & 31))) {
                 const uint32_t i = J.pidx[x];
-                J.plist[J.pstart[i] + atomicAdd(&J.pfill[i], 1u)] = static_cast<uint32_t>(w);
+                J.plist[J.pstart[i] + g_add(&J.pfill[i], 1u)] = static_cast<uint32_t>(w);
             }
         }
     }
 }
 
 // ---------------------------------------------------------------- lazy rounds
-__device__ __forceinline__ uint32_t load_count(const uint32_t *p)
+__device__ __forceinline__ uint32_t load_count(const GLOBAL uint32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ uint32_t hash_of(uint32_t x) { return (x * 2654435761u) >> (32 - kHashBits); }
+
+// pool position of id x (slot holds position + 1), or -1 if x is not in the pool
+__device__ __forceinline__ int pool_find(const uint32_t *slot, const uint32_t *pids, uint32_t x)
+{
+    uint32_t h = hash_of(x);
+    for (uint32_t probe = 0; probe < kHash; ++probe) {
+        const uint32_t v = slot[h];
+        if (v == 0) return -1;
+        if (pids[v - 1] == x) return static_cast<int>(v - 1);
+        h = (h + 1) & (kHash - 1);
+    }
+    return -1;
+}
+
 // One workgroup of T threads per job: rounds [rounds, k) while the pool
-// certifies the pick.  The pool's ids stay in registers for the whole launch
-// (at most kPoolMax / T per thread), so a round's scan is one load of each
-// pool id's count.  Covering: each pass claims up to T of the chosen id's
-// walks (one list entry per thread), a block scan of their lengths lays
-// their ids end to end, and every thread decrements the counts of the ids
-// at its positions (finding the walk by binary search over the pass's
-// starts in LDS): a fixed number of dependent memory accesses per pass
-// however the ids spread over walks.
+// certifies the pick.
+//
+// The pool lives in LDS for the whole launch: its ids, their exact counts
+// (kept exact by decrementing them beside the global counts; a walk covered
+// now never holds an id chosen in an earlier round, so chosen entries are
+// never decremented) and a hash from id to pool position.  A round's argmax
+// is then an LDS scan, and the global count decrements are never waited for
+// inside the launch: the ids chosen here are marked in the global counts
+// after a fence at the end.  Each pool id's list range sits in registers of
+// the thread that holds the id.
+//
+// Covering: each pass claims up to T of the chosen id's walks (one list
+// entry per thread), a block scan of their lengths lays their ids end to
+// end, and every thread decrements the counts of the ids at its positions
+// (finding the walk by binary search over the pass's starts in LDS).
 //
 // Zero gains.  When the best key of the pool has gain 0, every unselected id
 // of the pool has count 0.  If the pool is exactly the lowest-id ids that had
@@ -463,33 +562,54 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
     constexpr int kPer = kPoolMax / T;
     __shared__ uint64_t sh[kWaves];
     __shared__ uint32_t sh32[kWaves];
-    __shared__ uint32_t start[T];  // a pass's walks: first flattened position
-    __shared__ uint64_t woff[T];   //                 and offset into ids
-    __shared__ uint32_t win;       // pool position of the chosen id
-    const GreedyJob J = jobs[blockIdx.x];
+    __shared__ uint32_t start[T];        // a pass's walks: first flattened position
+    __shared__ uint64_t woff[T];         //                 and offset into ids
+    __shared__ uint32_t pcnt[kPoolMax];  // exact counts of the pool's ids
+    __shared__ uint32_t pids[kPoolMax];
+    __shared__ uint32_t slot[kHash];
+    __shared__ uint32_t wlo, whi;        // list range of the chosen id
+    const GJob J = view(jobs[blockIdx.x]);
     if (job_done(J)) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    GreedyState *st = J.st;
+    GLOBAL GreedyState *st = J.st;
     const bool ties = st->plan == PLAN_TIES;
-    const uint32_t P = st->pool_n + (ties ? st->n_tie : 0u);
+    const uint32_t P = pool_size(st);
     const uint64_t tau = ties && st->leftover
                              ? ((static_cast<uint64_t>(st->c_tie) + 1) << 32) | (0xFFFFFFFFu - st->next_id)
                              : st->tau;
     const bool ordered_zeros = ties && st->c_tie == 0 && st->pool_n == 0;
-    uint32_t pid[kPer];
+    for (uint32_t i = threadIdx.x; i < kHash; i += T) slot[i] = 0;
+    __syncthreads();
+    uint32_t pid[kPer], plo[kPer], phi[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const uint32_t i = threadIdx.x + j * T;
-        pid[j] = i < P ? J.pool[i] : 0u;
+        pid[j] = plo[j] = phi[j] = 0;
+        if (i < P) {
+            const uint32_t x = J.pool[i];
+            pid[j] = x;
+            pids[i] = x;
+            pcnt[i] = J.cnt[x];
+            plo[j] = J.pstart[i];
+            phi[j] = J.pstart[i + 1];
+            uint32_t h = hash_of(x);
+            for (uint32_t probe = 0; probe < kHash; ++probe) {
+                if (atomicCAS(&slot[h], 0u, i + 1) == 0u) break;
+                h = (h + 1) & (kHash - 1);
+            }
+        }
     }
-    int64_t r = st->rounds;
+    __syncthreads();
+    const int64_t r0 = st->rounds;
+    int64_t r = r0;
     for (; r < J.k; ++r) {
         // exact keys of the pool; the largest is this round's pick if it beats tau
         uint64_t best = 0;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            if (threadIdx.x + j * T < P) {
-                const uint64_t key = key_of(load_count(&J.cnt[pid[j]]), pid[j]);
+            const uint32_t i = threadIdx.x + j * T;
+            if (i < P) {
+                const uint64_t key = key_of(pcnt[i], pid[j]);
                 best = key > best ? key : best;
             }
         }
@@ -506,39 +626,38 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             uint64_t taken = 0;
             for (uint32_t b0 = 0; b0 < P && taken < need; b0 += T) {
                 const uint32_t i = b0 + threadIdx.x;
-                uint32_t x = 0;
-                bool open = false;
-                if (i < P) {
-                    x = J.pool[i];
-                    open = load_count(&J.cnt[x]) != kSelected;
-                }
+                const bool open = i < P && pcnt[i] != kSelected;
                 uint32_t total;
                 const uint64_t rank = taken + block_excl_scan<T>(open ? 1u : 0u, sh32, total);
                 if (open && rank < need) {
-                    J.sel[r + rank] = x;
+                    J.sel[r + rank] = pids[i];
                     J.gain[r + rank] = 0;
-                    atomicExch(&J.cnt[x], kSelected);
+                    pcnt[i] = kSelected;
                 }
                 taken += total;
             }
             r += static_cast<int64_t>(taken < need ? taken : need);
             break;
         }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const uint32_t i = threadIdx.x + j * T;
+            if (i < P && pid[j] == id) {  // the pool holds each id once
+                pcnt[i] = kSelected;
+                wlo = plo[j];
+                whi = phi[j];
+            }
+        }
         if (threadIdx.x == 0) {
             J.sel[r] = id;
             J.gain[r] = g;
-            atomicExch(&J.cnt[id], kSelected);
         }
+        __syncthreads();
         if (g == 0) {  // rebuild into an ordered pool of zeros
             ++r;
             break;
         }
-        // the chosen id's list: its pool position comes from the thread holding it
-#pragma unroll
-        for (int j = 0; j < kPer; ++j)
-            if (threadIdx.x + j * T < P && pid[j] == id) win = threadIdx.x + j * T;
-        __syncthreads();
-        const uint32_t lo = J.pstart[win], hi = J.pstart[win + 1];
+        const uint32_t lo = wlo, hi = whi;
         for (uint32_t b0 = lo; b0 < hi; b0 += T) {
             const uint32_t p = b0 + threadIdx.x;
             uint32_t len = 0;
@@ -548,7 +667,7 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
                 // the walk record is read beside the claim (used only if claimed)
                 const uint64_t o = J.walk_off[w];
                 const uint32_t l = J.walk_len[w];
-                if (atomicExch(&J.covered[w], 1u) == 0u) {
+                if (g_xchg(&J.covered[w], 1u) == 0u) {
                     off = o;
                     len = l;
                 }
@@ -579,18 +698,27 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    if (x[u] != id) atomicSub(&J.cnt[x[u]], 1u);
+                for (int u = 0; u < kUnroll; ++u) {
+                    if (x[u] != id) {
+                        g_add(&J.cnt[x[u]], 0xFFFFFFFFu);
+                        const int pos = pool_find(slot, pids, x[u]);
+                        if (pos >= 0) atomicSub(&pcnt[pos], 1u);
+                    }
+                }
             }
-            __syncthreads();  // decrements done and LDS free before the next pass / round
+            __syncthreads();  // LDS counts final and LDS free before the next pass / round
         }
     }
+    // every global decrement of this workgroup is complete before the ids
+    // chosen here are marked selected in the global counts
+    __threadfence();
     __syncthreads();
+    for (int64_t q = r0 + threadIdx.x; q < r; q += T) J.cnt[J.sel[q]] = kSelected;
     if (threadIdx.x == 0) st->rounds = static_cast<uint32_t>(r);
     // unmark the pool (the next rebuild marks its own)
 #pragma unroll
     for (int j = 0; j < kPer; ++j)
-        if (threadIdx.x + j * T < P) atomicAnd(&J.bitmap[pid[j] >> 5], ~(1u << (pid[j] & 31)));
+        if (threadIdx.x + j * T < P) g_and(&J.bitmap[pid[j] >> 5], ~(1u << (pid[j] & 31)));
 }
 
 unsigned grid_for(uint64_t items, unsigned block, unsigned cap)

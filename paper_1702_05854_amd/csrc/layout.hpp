@@ -3,9 +3,22 @@
 // work table of one sampling launch and the per-query counters.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace sia {
+
+// Global-address-space view of a pointer.  Pointers that reach a kernel
+// inside a record loaded from memory are generic, and the compiler would
+// access them with flat instructions, whose completion every LDS wait (and so
+// every barrier) must also await; explicit global pointers avoid that.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL T *gp(T *p)
+{
+    return (GLOBAL T *)p;
+}
 
 // One 16-byte record per node: where its in-edges start, how many, the last
 // cumulative threshold (so the dead-end test needs no extra load), and the

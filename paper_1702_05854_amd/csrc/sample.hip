@@ -243,8 +243,9 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
             if (phase == PH_START) {
                 const SlotDev &S = sl[slot];
                 const uint64_t idx = __umul64hi(word, S.n_ns);
-                uint32_t c = S.bucket[idx >> S.bucket_shift];
-                while (c < S.n_src && S.src_t[c] <= idx) ++c;
+                const GLOBAL uint32_t *src_t = gp(S.src_t);
+                uint32_t c = gp(S.bucket)[idx >> S.bucket_shift];
+                while (c < S.n_src && src_t[c] <= idx) ++c;
                 x1 = static_cast<uint32_t>(idx + c);
                 cur = x1;
                 tort = x1;
@@ -278,11 +279,11 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
             const uint32_t total_len = __shfl(incl, kWave - 1, kWave);
             uint64_t wbase = 0, ibase = 0;
             if (lane == leader) {
-                uint64_t *ctr = sl[s_lead].counters;
-                wbase = atomicAdd(reinterpret_cast<unsigned long long *>(&ctr[ST_WALKS]),
-                                  static_cast<unsigned long long>(__popcll(mm)));
-                ibase = atomicAdd(reinterpret_cast<unsigned long long *>(&ctr[ST_IDS]),
-                                  static_cast<unsigned long long>(total_len));
+                GLOBAL uint64_t *ctr = gp(sl[s_lead].counters);
+                wbase = __hip_atomic_fetch_add(&ctr[ST_WALKS], static_cast<uint64_t>(__popcll(mm)),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ibase = __hip_atomic_fetch_add(&ctr[ST_IDS], static_cast<uint64_t>(total_len),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             wbase = shfl_u64(wbase, leader);
             ibase = shfl_u64(ibase, leader);
@@ -293,19 +294,21 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 const uint64_t widx = wbase + lanes_below(mm);
                 const uint64_t ioff = ibase + incl - len;
                 if (widx < S.walk_cap && ioff + len <= S.id_cap) {
-                    S.walk_attempt[widx] = a;
-                    S.walk_off[widx] = ioff;
-                    S.walk_len[widx] = len;
+                    gp(S.walk_attempt)[widx] = a;
+                    gp(S.walk_off)[widx] = ioff;
+                    gp(S.walk_len)[widx] = len;
                     out_pos = ioff;
                     if (mode == SIA_NODES) {
-                        S.ids[out_pos++] = x1;
-                        if (S.cnt) atomicAdd(&S.cnt[x1], 1u);
+                        gp(S.ids)[out_pos++] = x1;
+                        if (S.cnt)
+                            __hip_atomic_fetch_add(gp(S.cnt) + x1, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
                     }
                     phase = PH_EMIT;
                     cur = x1;
                     cnt = t;
                 } else {
-                    S.counters[ST_OVERFLOW] = 1;
+                    gp(S.counters)[ST_OVERFLOW] = 1;
                     atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
                     active = false;
                 }
@@ -361,8 +364,9 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
             } else {  // PH_EMIT
                 const SlotDev &S = sl[slot];
                 const uint32_t id = (mode == SIA_EDGES) ? j : u;
-                S.ids[out_pos++] = id;
-                if (S.cnt) atomicAdd(&S.cnt[id], 1u);
+                gp(S.ids)[out_pos++] = id;
+                if (S.cnt)
+                    __hip_atomic_fetch_add(gp(S.cnt) + id, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 cur = u;
                 if (--cnt == 0) done = true;
             }
@@ -379,7 +383,8 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
         const unsigned long long v = acc[i / 6][i % 6];
         if (!v) continue;
         const int map[6] = {ST_HITS, ST_DEAD, ST_CYCLE, ST_STEPS, ST_EVALS, ST_FAULTS};
-        atomicAdd(reinterpret_cast<unsigned long long *>(&sl[i / 6].counters[map[i % 6]]), v);
+        __hip_atomic_fetch_add(gp(sl[i / 6].counters) + map[i % 6], static_cast<uint64_t>(v),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
