@@ -136,10 +136,19 @@ def weights_inv_indeg(col_off):
     return (1.0 / deg.to(torch.float32))[cols]
 
 
-def _col_sums(col_off, x):
-    cs = torch.zeros(x.numel() + 1, dtype=torch.float64, device=x.device)
-    cs[1:] = torch.cumsum(x, 0)
-    return cs[col_off[1:]] - cs[col_off[:-1]]
+def _col_sums(col_off, x, cols_per_call=1 << 22):
+    """Per-column sums of x: a segmented sum (differences of one prefix sum over
+    every edge lose the small columns once the total is large), taken over
+    ranges of columns so each call stays within the reduction's launch limits."""
+    n = col_off.numel() - 1
+    deg = col_off[1:] - col_off[:-1]
+    out = torch.empty(n, dtype=x.dtype, device=x.device)
+    for c0 in range(0, n, cols_per_call):
+        c1 = min(n, c0 + cols_per_call)
+        e0, e1 = int(col_off[c0]), int(col_off[c1])
+        out[c0:c1] = torch.segment_reduce(x[e0:e1], "sum", lengths=deg[c0:c1], unsafe=True,
+                                          initial=0.0)
+    return out
 
 
 def weights_random_colsum(col_off, lo, hi, seed):

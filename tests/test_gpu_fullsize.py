@@ -8,6 +8,11 @@
   attempts one by one; counters against invariants; the greedy on a prefix
   of the kept walks against the oracle; and properties of the full solve
   that hold at any size.
+* rmat26 (R-MAT scale 26, edge factor 24, 1.6*10^9 edges, 10^5 sources,
+  N=2*10^8): the full solve's invariants, a window of kept walks against the
+  oracle attempt by attempt, and the greedy on a prefix of them.
+* rmat22 (R-MAT scale 22) with mixed queries: batched answers equal the
+  single-query path's, the smallest also the oracle's.
 """
 import numpy as np
 import pytest
@@ -136,3 +141,100 @@ def test_rmat24_solve_properties(sia, rmat24):
     chosen[sel] = True
     hit = np.add.reduceat(chosen[walks.ids].astype(np.int64), walks.off[:-1].astype(np.int64)) > 0
     assert int(hit.sum()) == st["covered"]
+
+
+# ---------------------------------------------------------------- billion-edge graph
+@pytest.fixture(scope="module")
+def rmat26(sia):
+    from paper_1702_05854_amd import workloads
+    say("generating rmat26 (R-MAT scale 26, edge factor 24)")
+    wl = workloads.load("rmat26", device="cuda")
+    say("ingest", wl.m, "edges")
+    g = sia.Graph(wl.col_off, wl.row_idx, wl.w)
+    torch.cuda.synchronize()
+    yield wl, g
+    g.close()
+
+
+def test_rmat26_billion_edges(sia, rmat26):
+    """1.6*10^9 edges, 10^5 sources, 2*10^8 attempts, k = 1000 (the launch the
+    bench uses).  The whole solve's invariants; the kept walks of a window of
+    2*10^6 attempts against the oracle walking sampled attempts one by one;
+    the greedy on a prefix of those walks against the oracle's."""
+    wl, g = rmat26
+    N = wl.n_attempts
+    say("gpu solve", N, "attempts")
+    res = sia.solve(g, wl.sources, "edges", wl.k, N, 0, wl.seed)
+    sel, gains, st = res["selected"], res["gains"], res["stats"]
+    assert st["hits"] + st["dead_ends"] + st["cycles"] == N
+    assert st["evaluations"] >= st["steps"]
+    assert len(set(sel.tolist())) == wl.k and sel.min() >= 0 and sel.max() < g.m
+    assert np.all(np.diff(gains.astype(np.int64)) <= 0)
+    assert st["covered"] == int(gains.sum()) <= st["hits"]
+    say("solve:", {k: st[k] for k in ("hits", "dead_ends", "cycles", "steps", "walk_ids", "covered")})
+
+    W, W0 = 2_000_000, N - 2_000_000
+    say("gpu sample of attempts", W0, "..", N)
+    got = sia.sample(g, wl.sources, "edges", W, W0, wl.seed)
+    say("host copy")
+    col_off, row_idx, w = wl.host()
+    say("oracle thresholds")
+    og = cpu.Graph(col_off, row_idx, w)
+    rng = np.random.default_rng(26)
+    kept = got.attempt[rng.choice(got.n_walks, min(1000, got.n_walks), replace=False)]
+    anyid = (W0 + rng.choice(W, 2000, replace=False)).astype(np.uint64)
+    probe = np.unique(np.concatenate([kept, anyid, np.array([W0, N - 1], np.uint64)]))
+    say("oracle on", probe.shape[0], "attempts")
+    ref = og.sample_list(wl.sources, cpu.MODE_EDGES, probe, wl.seed)
+    pos = np.minimum(np.searchsorted(got.attempt, probe), got.n_walks - 1)
+    assert np.array_equal(ref.attempt, probe[got.attempt[pos] == probe])
+    for i, a in enumerate(ref.attempt):
+        j = int(np.searchsorted(got.attempt, a))
+        assert np.array_equal(got.walk(j), ref.walk(i)), int(a)
+    for i in range(min(got.n_walks, 2000)):  # walks chain backwards through the graph
+        e = got.walk(i).astype(np.int64)
+        heads = np.searchsorted(col_off, e, side="right") - 1
+        assert np.all(row_idx[e[:-1]] == heads[1:]), i
+    nw = min(20_000, got.n_walks)
+    off = got.off[: nw + 1].copy()
+    ids = got.ids[: int(off[-1])]
+    say("greedy on", nw, "walks")
+    a = sia.greedy(g.m, off, ids, 200)
+    b = cpu.greedy_csr(g.m, off, ids, 200)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------- mixed queries, full graph
+def test_rmat22_mix_batched_equals_plain(sia):
+    """R-MAT scale 22 with queries drawn as for serving (|X| log-uniform in
+    1..10^4, k in 10..1000, N log-uniform in 10^5..10^7, both modes): every
+    batched answer equals the single-query path's; the smallest query also
+    equals the oracle's."""
+    from paper_1702_05854_amd import workloads
+    say("generating rmat22")
+    wl = workloads.load("rmat22", device="cuda")
+    g = sia.Graph(wl.col_off, wl.row_idx, wl.w)
+    qs = workloads.query_mix(wl.n, 32, seed=22)
+    with sia.Batch(g, use_graph=1) as b:
+        ts = [b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"]) for q in qs]
+        got = []
+        for t in ts:
+            r = b.wait(t, 120_000)
+            assert r is not None, b.stats()
+            got.append(r)
+        say("batched:", {k: b.stats()[k] for k in ("waves", "greedy_launches", "reruns")})
+    for i, q in enumerate(qs):
+        ref = sia.solve(g, q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"])
+        assert np.array_equal(got[i]["selected"], ref["selected"]), i
+        assert np.array_equal(got[i]["gains"], ref["gains"]), i
+        for c in ("hits", "dead_ends", "cycles", "steps", "walk_ids", "covered"):
+            assert got[i]["stats"][c] == ref["stats"][c], (i, c)
+    small = min(range(len(qs)), key=lambda i: qs[i]["n_attempts"])
+    q = qs[small]
+    say("oracle on the smallest query:", q["n_attempts"], "attempts")
+    og = cpu.Graph(*wl.host())
+    om = cpu.MODE_EDGES if q["mode"] == "edges" else cpu.MODE_NODES
+    ref = cpu.solve(og, q["sources"], om, q["k"], q["n_attempts"], 0, q["seed"])
+    assert np.array_equal(got[small]["selected"], ref["selected"])
+    assert np.array_equal(got[small]["gains"], ref["gains"])
+    g.close()
