@@ -261,8 +261,10 @@ typedef struct {
                                       the sampler gets the rest); 0: both
                                       streams use every CU */
     uint32_t greedy_batch;         /* greedy_mode 0: finished queries per
-                                      greedy launch (default 8) */
-    uint32_t reserved;
+                                      greedy launch (default 16) */
+    uint32_t hist_blocks;          /* histogram tiling of the greedy's pool
+                                      rebuilds: workgroups for one query's
+                                      histogram (default: one per CU) */
 } sia_batch_config;
 
 /* Timeline of one query, in seconds since sia_batch_create (host steady
@@ -340,11 +342,12 @@ sia_status sia_batch_cancel(sia_batch *b, uint64_t ticket);
 sia_status sia_batch_stats_get(sia_batch *b, sia_batch_stats *out);
 
 /*
- * Autotune the sampling launch shape on a probe query: sample its attempts
- * once per candidate (workgroups per CU x refill chunk), keep the fastest,
- * and size wave_attempts for launches of about target_ms.  The batch must be
- * idle (no unfinished ticket), else SIA_EBUSY.  *chosen (may be NULL)
- * receives the new shape.
+ * Autotune the launch shapes on a probe query: sample its attempts once per
+ * candidate (workgroups per CU x refill chunk) and keep the fastest; size
+ * wave_attempts for launches of about target_ms; then run the greedy on the
+ * probe's walks (k = the probe's k, or 1000 if 0) once per histogram tiling
+ * candidate and keep the fastest.  The batch must be idle (no unfinished
+ * ticket), else SIA_EBUSY.  *chosen (may be NULL) receives the new shape.
  */
 sia_status sia_batch_tune(sia_batch *b, const sia_query *probe, double target_ms,
                           sia_batch_config *chosen);

@@ -194,8 +194,9 @@ size_t greedy_job_table_bytes(uint32_t n_jobs);  // job records + their states
 // one workgroup per job).  d_job_table: greedy_job_table_bytes(jobs.size())
 // bytes of device memory.  Synchronises s; writes each job's selected ids and
 // gains to its host arrays.  Timing (if requested) covers all jobs.
+// hist_base: histogram workgroups for a single job (0: one per CU).
 void run_greedy_jobs(std::vector<GreedyInput> &jobs, void *d_job_table, hipStream_t s, bool timing,
-                     GreedyResult *res);
+                     GreedyResult *res, unsigned hist_base = 0);
 
 // A single job over the walks held in ws (walk_off / walk_len / ids, n_walks
 // walks, n_ids ids).  counts_ready: ws.cnt already holds the coverage counts.

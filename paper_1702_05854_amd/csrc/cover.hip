@@ -549,12 +549,11 @@ __device__ __forceinline__ int pool_find(const uint32_t *slot, const uint32_t *p
 // (finding the walk by binary search over the pass's starts in LDS).
 //
 // Zero gains.  When the best key of the pool has gain 0, every unselected id
-// of the pool has count 0.  If the pool is exactly the lowest-id ids that had
-// count 0 when it was built (tie plan at count 0, nothing collected above),
-// then every id outside it has count 0 and a higher id, so the remaining
-// rounds take the pool's unselected ids in ascending order: they are written
-// in one pass.  Otherwise the round is taken one by one as usual and the
-// launch ends after it, so the next rebuild forms such a pool.
+// of the pool has count 0 (and the plan is a tie at count 0, so every id
+// outside the pool has count 0 and, if tied ids were left out, an id >=
+// next_id).  The remaining rounds take the pool's unselected ids in ascending
+// order below next_id, all in one pass: directly when the pool is already
+// that ordered list (nothing collected above count 0), else after an LDS sort.
 template <int T>
 __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
 {
@@ -653,8 +652,51 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             J.gain[r] = g;
         }
         __syncthreads();
-        if (g == 0) {  // rebuild into an ordered pool of zeros
-            ++r;
+        if (g == 0) {
+            // Every unselected pool id has count 0, and so has every id
+            // outside the pool (this is a tie plan at count 0: all ids with a
+            // count were collected), whose ids are all >= next_id when tied
+            // ids were left out.  The picks are the pool's unselected ids in
+            // ascending order, below next_id: sort them (the hash space is no
+            // longer needed) and take them.  (The id just chosen is the first.)
+            uint32_t *buf = slot;
+            uint32_t N = 1;
+            while (N < P) N <<= 1;
+            for (uint32_t i = threadIdx.x; i < N; i += T)
+                buf[i] = (i < P && (pcnt[i] != kSelected || pids[i] == id)) ? pids[i] : 0xFFFFFFFFu;
+            __syncthreads();
+            for (uint32_t kk = 2; kk <= N; kk <<= 1) {
+                for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (uint32_t i = threadIdx.x; i < N; i += T) {
+                        const uint32_t o = i ^ jj;
+                        if (o > i) {
+                            const uint32_t a = buf[i], b = buf[o];
+                            if ((a > b) == ((i & kk) == 0)) {
+                                buf[i] = b;
+                                buf[o] = a;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            const uint32_t bound = st->leftover ? st->next_id : 0xFFFFFFFFu;
+            const uint64_t need = static_cast<uint64_t>(J.k - r);
+            uint32_t taken = 0;  // sorted: the valid picks are a prefix
+            {
+                uint32_t a = 0, b = N;  // first position whose id >= bound
+                while (a < b) {
+                    const uint32_t m = (a + b) >> 1;
+                    if (buf[m] < bound) a = m + 1;
+                    else b = m;
+                }
+                taken = static_cast<uint32_t>(a < need ? a : need);
+            }
+            for (uint32_t i = threadIdx.x; i < taken; i += T) {
+                J.sel[r + i] = buf[i];
+                J.gain[r + i] = 0;
+            }
+            r += taken;
             break;
         }
         const uint32_t lo = wlo, hi = whi;
@@ -784,7 +826,7 @@ size_t greedy_job_table_bytes(uint32_t n_jobs)
 }
 
 void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_t s, bool timing,
-                     GreedyResult *res)
+                     GreedyResult *res, unsigned hist_base)
 {
     const uint32_t Q = static_cast<uint32_t>(in.size());
     if (!Q) return;
@@ -824,8 +866,11 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
 
     // pool rebuilds + certified rounds; groups of generations between host checks
     constexpr unsigned T = 1024;
+    // histogram tiling: hist_base workgroups for one job (default: one per CU),
+    // shared out when several jobs run
+    const unsigned base = hist_base ? hist_base : cus;
     const unsigned hist_blocks =
-        std::min(grid_for(max_S, T, cus), std::max(1u, cus / std::min<unsigned>(Q, 8)));
+        std::min(grid_for(max_S, T, base), std::max(1u, base / std::min<unsigned>(Q, 8)));
     const unsigned collect_blocks = grid_for(max_S, 256, cus * 4);
     const unsigned fill_blocks = grid_for(max_walks * kWave, 256, cus * 32);
     std::vector<GreedyState> hs(Q);

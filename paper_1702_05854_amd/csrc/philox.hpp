@@ -23,16 +23,16 @@ __device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t c1, uint6
     uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint64_t hi0 = __umul64hi(kPhiloxM0, x0);
-        const uint64_t lo0 = kPhiloxM0 * x0;
-        const uint64_t hi1 = __umul64hi(kPhiloxM1, x2);
-        const uint64_t lo1 = kPhiloxM1 * x2;
-        const uint64_t y0 = hi1 ^ x1 ^ k0;
-        const uint64_t y2 = hi0 ^ x3 ^ k1;
+        // one 128-bit product per multiplier: its halves share the partial
+        // products (fewer 32-bit multiplies than separate high / low parts)
+        const unsigned __int128 p0 = static_cast<unsigned __int128>(kPhiloxM0) * x0;
+        const unsigned __int128 p1 = static_cast<unsigned __int128>(kPhiloxM1) * x2;
+        const uint64_t y0 = static_cast<uint64_t>(p1 >> 64) ^ x1 ^ k0;
+        const uint64_t y2 = static_cast<uint64_t>(p0 >> 64) ^ x3 ^ k1;
         x0 = y0;
-        x1 = lo1;
+        x1 = static_cast<uint64_t>(p1);
         x2 = y2;
-        x3 = lo0;
+        x3 = static_cast<uint64_t>(p0);
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
     }

@@ -756,7 +756,7 @@ struct sia_batch {
             }
             GreedyResult res;
             const auto g0 = Clock::now();
-            run_greedy_jobs(in, d_jobs.ptr, s_greedy, true, &res);
+            run_greedy_jobs(in, d_jobs.ptr, s_greedy, true, &res, cfg.hist_blocks);
             const double dt = std::chrono::duration<double>(Clock::now() - g0).count();
             std::lock_guard<std::mutex> lk(mu);
             ctr.greedy_busy_s += dt;
@@ -879,9 +879,49 @@ struct sia_batch {
         (void)hipEventDestroy(e1);
         untag(0);
         SIA_HIP(hipStreamSynchronize(s_sample));
+
+        // histogram tiling of the greedy, on the probe's walks (still in slot 0)
+        const uint64_t n_walks = h_ctr_out[ST_WALKS], n_ids = h_ctr_out[ST_IDS];
+        const uint64_t S = q.mode == SIA_EDGES ? static_cast<uint64_t>(g->m) : static_cast<uint64_t>(g->n);
+        const int64_t kq = std::min<int64_t>(q.k > 0 ? q.k : 1000, static_cast<int64_t>(S));
+        Slot &sl = slots[0];
+        sl.cnt.ensure(4 * S);
+        sl.greedy.ensure(greedy_scratch_bytes(S, n_walks, n_ids, kq));
+        std::vector<int64_t> gsel(static_cast<size_t>(kq));
+        std::vector<uint64_t> ggain(static_cast<size_t>(kq));
+        const unsigned cus = static_cast<unsigned>(device_cu_count());
+        unsigned best_h = 0;
+        float best_gms = 0.f;
+        for (unsigned hb : {cus / 8, cus / 4, cus / 2, cus}) {
+            if (!hb) continue;
+            for (int rep = 0; rep < 2; ++rep) {
+                std::vector<GreedyInput> in(1);
+                GreedyInput &gi = in[0];
+                gi.walk_off = sl.walk_off.as<uint64_t>();
+                gi.walk_len = sl.walk_len.as<uint32_t>();
+                gi.ids = sl.ids.as<uint32_t>();
+                gi.id_space = S;
+                gi.n_walks = n_walks;
+                gi.n_ids = n_ids;
+                gi.k = kq;
+                gi.cnt = sl.cnt.as<uint32_t>();
+                gi.counts_ready = false;
+                gi.scratch = sl.greedy.ptr;
+                gi.selected = gsel.data();
+                gi.gains = ggain.data();
+                GreedyResult res;
+                run_greedy_jobs(in, d_jobs.ptr, s_greedy, true, &res, hb);
+                const float ms = res.ms_count + res.ms_greedy;
+                if (rep == 1 && (best_gms == 0.f || ms < best_gms)) {
+                    best_gms = ms;
+                    best_h = hb;
+                }
+            }
+        }
         std::lock_guard<std::mutex> l(mu);
         cfg.sampler_blocks_per_cu = best.blocks_per_cu;
         cfg.refill_chunk = best.chunk;
+        cfg.hist_blocks = best_h;
         if (target_ms > 0 && best_ms > 0) {
             const double rate = q.n_attempts / (best_ms * 1e-3);
             const double w = rate * target_ms * 1e-3;
@@ -901,7 +941,7 @@ sia_batch_config defaults(const sia_batch_config *c)
     if (!d.refill_chunk) d.refill_chunk = 256;
     if (!d.wave_attempts) d.wave_attempts = uint64_t(1) << 23;
     if (!d.min_share) d.min_share = uint64_t(1) << 16;
-    if (!d.greedy_batch) d.greedy_batch = 8;
+    if (!d.greedy_batch) d.greedy_batch = 16;
     return d;
 }
 

@@ -52,10 +52,10 @@ class BatchConfig(C.Structure):
     _fields_ = [("sampler_blocks_per_cu", C.c_int32), ("refill_chunk", C.c_uint32),
                 ("wave_attempts", C.c_uint64), ("min_share", C.c_uint64),
                 ("use_graph", C.c_int32), ("greedy_mode", C.c_int32), ("greedy_cus", C.c_int32),
-                ("greedy_batch", C.c_uint32), ("reserved", C.c_uint32)]
+                ("greedy_batch", C.c_uint32), ("hist_blocks", C.c_uint32)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class TicketInfo(C.Structure):
@@ -320,8 +320,8 @@ class Batch:
         _check(lib().sia_batch_stats_get(self._h, C.byref(s)))
         return s.as_dict()
 
-    def tune(self, sources, mode, n_attempts, attempt_offset=0, seed=2017, target_ms=25.0):
-        q, src = _query(sources, mode, 0, n_attempts, attempt_offset, seed)
+    def tune(self, sources, mode, n_attempts, attempt_offset=0, seed=2017, target_ms=25.0, k=0):
+        q, src = _query(sources, mode, k, n_attempts, attempt_offset, seed)
         cfg = BatchConfig()
         _check(lib().sia_batch_tune(self._h, C.byref(q), target_ms, C.byref(cfg)))
         return cfg.as_dict()

@@ -218,6 +218,7 @@ def test_tune_then_serve(sia, rmat16):
         say("tuned", cfg)
         assert cfg["sampler_blocks_per_cu"] >= 1 and cfg["refill_chunk"] in (64, 128, 256, 512)
         assert cfg["wave_attempts"] >= 1 << 20
+        assert cfg["hist_blocks"] >= 1
         assert b.stats()["config"] == cfg
         qs = mix(wl.n, 8, 17, max_sources=300, k_range=(5, 100), attempts_range=(20_000, 500_000))
         ts = [b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"]) for q in qs]
