@@ -311,6 +311,17 @@ def main():
         "cpu_baseline": None,
     }
     g.close()
+    # random-gather ceiling of the device: the sampler's line rate against it
+    ceil_ind, _ = sia.probe_gather(2 << 30, 512, dependent=False)
+    ceil_dep, _ = sia.probe_gather(2 << 30, 512, dependent=True)
+    traffic = out["roofline"]["traffic"]
+    samp_lines = traffic / 128.0 / (ms_sample * 1e-3) if traffic else None
+    out["gather_ceiling"] = {
+        "probe": "4-byte loads at uniformly random positions of a 2 GiB array, full occupancy",
+        "independent_lines_per_s": ceil_ind, "dependent_lines_per_s": ceil_dep,
+        "sampler_lines_per_s": samp_lines,
+        "sampler_frac_of_independent": samp_lines / ceil_ind if samp_lines else None,
+        "sampler_frac_of_dependent": samp_lines / ceil_dep if samp_lines else None}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, mode, k, args.cpu_budget)

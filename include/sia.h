@@ -198,6 +198,21 @@ sia_status sia_solve(const sia_graph *g, int mode, const int32_t *sources,
                      uint64_t attempt_offset, uint64_t seed, int64_t *selected,
                      uint64_t *gains, sia_stats *stats, int timing, void *hip_stream);
 
+/*
+ * Measuring hook (not part of the method): the device's random-gather
+ * ceiling.  Fills a device array of array_bytes (1 MiB .. 16 GiB) and times
+ * one launch, at full occupancy, in which every lane makes loads_per_lane
+ * 4-byte loads at pseudo-random positions (each its own 128-byte line):
+ * independent loads (dependent = 0) or a chain where each load's value is
+ * the next position (dependent != 0, a walk's access pattern).
+ *   lines_per_s  out: loads (lines) completed per second
+ *   ms           out (may be NULL): launch time
+ * The array is freed before returning.  Errors: SIA_EINVAL, SIA_ENOMEM,
+ * SIA_EDEVICE.
+ */
+sia_status sia_probe_gather(uint64_t array_bytes, uint32_t loads_per_lane, int dependent,
+                            double *lines_per_s, double *ms, void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Batched and served queries.  Not part of the paper's method (which runs
  * one query per launch); the answers are identical to sia_solve's for the

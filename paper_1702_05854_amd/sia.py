@@ -123,9 +123,11 @@ def lib():
         L.sia_batch_cancel.argtypes = [p, u64]
         L.sia_batch_stats_get.argtypes = [p, C.POINTER(BatchStats)]
         L.sia_batch_tune.argtypes = [p, C.POINTER(Query), C.c_double, C.POINTER(BatchConfig)]
+        L.sia_probe_gather.argtypes = [u64, C.c_uint32, i32, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), p]
         for name in ("sia_check_query", "sia_graph_create", "sia_graph_destroy", "sia_graph_info",
                      "sia_graph_thresholds", "sia_quantize", "sia_sample", "sia_greedy",
-                     "sia_solve") + BATCH_SYMBOLS:
+                     "sia_solve", "sia_probe_gather") + BATCH_SYMBOLS:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -342,6 +344,14 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def probe_gather(array_bytes=2 << 30, loads_per_lane=512, dependent=False, stream=None):
+    """Random-gather ceiling (measuring hook): (lines per second, launch ms)."""
+    rate, ms = C.c_double(), C.c_double()
+    _check(lib().sia_probe_gather(array_bytes, loads_per_lane, 1 if dependent else 0, C.byref(rate),
+                                  C.byref(ms), _stream(stream)))
+    return rate.value, ms.value
 
 
 def quantize(w_dev, q_dev, stream=None):

@@ -123,3 +123,10 @@ def test_binding_structs_match_the_header(tmp_path):
         assert c_layout[(cname, "size")] == C.sizeof(py), cname
         for field, _ in py._fields_:
             assert c_layout[(cname, field)] == getattr(py, field).offset, (cname, field)
+
+
+def test_probe_gather_rejects_bad_arguments(L):
+    rate, ms = C.c_double(), C.c_double()
+    assert L.sia_probe_gather(0, 512, 0, C.byref(rate), C.byref(ms), None) == -1
+    assert L.sia_probe_gather(1 << 30, 7, 0, C.byref(rate), C.byref(ms), None) == -1
+    assert L.sia_probe_gather(1 << 30, 512, 0, None, None, None) == -1

@@ -309,3 +309,9 @@ def test_solve_edge_cases(sia):
     g = sia.Graph(np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
     got = sia.solve(g, [0], "nodes", 2, 1000, 0, 3)
     assert got["stats"]["dead_ends"] == 1000 and got["selected"].tolist() == [0, 1]
+
+
+def test_probe_gather_measures(sia):
+    ind, ms_i = sia.probe_gather(64 << 20, 64, dependent=False)
+    dep, ms_d = sia.probe_gather(64 << 20, 64, dependent=True)
+    assert ind > 0 and dep > 0 and ms_i > 0 and ms_d > 0
