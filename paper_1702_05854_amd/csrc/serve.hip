@@ -506,9 +506,11 @@ struct sia_batch {
 
     // Time-sliced mode: run the greedy of the finished queries between
     // sampling launches once enough of them wait (greedy_batch), or when
-    // sampling cannot proceed without it: nothing left to sample, a queued
-    // query waits for a slot they hold, the oldest has waited long, or
-    // (force) the launch planner found no share to run.
+    // sampling cannot proceed without it: nothing left to sample, the oldest
+    // has waited long, or (force) the launch planner found no share to run.
+    // Queued queries may wait for the slots finished queries hold: sampling
+    // throughput hardly depends on how many queries share a launch, while
+    // the greedy's launch time is that of its slowest query.
     bool run_greedy_if(bool force)
     {
         std::vector<TicketP> batch;
@@ -516,7 +518,6 @@ struct sia_batch {
             std::lock_guard<std::mutex> lk(mu);
             if (ready.empty()) return false;
             const bool due = force || ready.size() >= cfg.greedy_batch || !sampling_locked() ||
-                             (!pending.empty() && !free_slot_locked()) ||
                              now() - ready.front()->info.t_sampled > kGreedyMaxWait;
             if (!due) return false;
             batch = take_ready_locked();
