@@ -3,6 +3,7 @@
 #include "common.hpp"
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -166,11 +167,11 @@ sia_status sia_graph_thresholds(const sia_graph *g, uint32_t *thr_host, void *hi
         DeviceScope ds(g->device);
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
         if (!g->m) return;
-        std::vector<EdgeRec> tmp(static_cast<size_t>(g->m));
-        SIA_HIP(hipMemcpyAsync(tmp.data(), g->edges.ptr, sizeof(EdgeRec) * g->m,
-                               hipMemcpyDeviceToHost, s));
+        // thr_hi of every arc: a strided copy straight into the caller's array
+        SIA_HIP(hipMemcpy2DAsync(thr_host, sizeof(uint32_t), g->arcs.as<char>() + offsetof(ArcRec, thr_hi),
+                                 sizeof(ArcRec), sizeof(uint32_t), static_cast<size_t>(g->m),
+                                 hipMemcpyDeviceToHost, s));
         SIA_HIP(hipStreamSynchronize(s));
-        for (int64_t j = 0; j < g->m; ++j) thr_host[j] = tmp[j].thr;
     });
 }
 

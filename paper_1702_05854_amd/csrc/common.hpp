@@ -102,7 +102,7 @@ struct sia_graph {
     int64_t n = 0, m = 0;
     int device = 0;
     sia::DevBuf nodes;  // NodeRec[n]
-    sia::DevBuf edges;  // EdgeRec[m]
+    sia::DevBuf arcs;   // ArcRec[m]
     sia::Workspace ws;
     std::mutex mu;      // one query at a time per graph handle
     std::mutex tag_mu;  // guards tag_bits

@@ -4,8 +4,10 @@
 // lo..j, 2^32 - 1).  Edge j is live with probability (thr_j - thr_{j-1})/2^32.
 //
 // Layout built here (device): NodeRec[n] {off, deg, thr_last, source tag 0}
-// and EdgeRec[m] {thr, tail}.  One wave per column (wave-wide uint64 prefix
-// sums); columns above kBigDeg in-edges are finished by one workgroup each.
+// and ArcRec[m] {thr_{j-1}, thr_j, tail u, tag 0, u's off / deg / thr_last}.
+// One wave per column (wave-wide uint64 prefix sums); columns above kBigDeg
+// in-edges are finished by one workgroup each; a last pass copies each tail's
+// node record into its arcs.
 #include "common.hpp"
 
 #include <algorithm>
@@ -92,10 +94,27 @@ __global__ void k_check_rows(const int32_t *row, int64_t m, int64_t n, int *err)
     }
 }
 
+__device__ __forceinline__ uint32_t clamp32(uint64_t v)
+{
+    return static_cast<uint32_t>(v > 0xFFFFFFFFull ? 0xFFFFFFFFull : v);
+}
+
+// First half of arc j: its threshold interval [clamp(run - q), clamp(run))
+// and tail; the second half (the tail's record) is written by k_arc_tails.
+__device__ __forceinline__ void put_arc_head(ArcRec *arcs, int64_t j, uint64_t run, uint64_t q, int32_t u)
+{
+    uint4 v;
+    v.x = clamp32(run - q);
+    v.y = clamp32(run);
+    v.z = static_cast<uint32_t>(u);
+    v.w = 0u;
+    *reinterpret_cast<uint4 *>(&arcs[j]) = v;
+}
+
 // One wave per column.
 __global__ __launch_bounds__(256) void k_thresholds(const int64_t *col_off, const int32_t *row,
                                                     const float *w, int64_t n, NodeRec *nodes,
-                                                    EdgeRec *edges, uint32_t *big_list,
+                                                    ArcRec *arcs, uint32_t *big_list,
                                                     uint32_t *big_count, int *err)
 {
     const int lane = threadIdx.x & (kWave - 1);
@@ -119,11 +138,7 @@ __global__ __launch_bounds__(256) void k_thresholds(const int64_t *col_off, cons
                 else q = quantize_weight(x);
             }
             const uint64_t s = wave_incl_scan(q, lane);
-            if (j < hi) {
-                const uint64_t run = carry + s;
-                edges[j] = EdgeRec{static_cast<uint32_t>(run > 0xFFFFFFFFull ? 0xFFFFFFFFull : run),
-                                   static_cast<uint32_t>(row[j])};
-            }
+            if (j < hi) put_arc_head(arcs, j, carry + s, q, row[j]);
             carry += shfl_u64(s, kWave - 1);
         }
         if (bad) report(err, E_WEIGHT_RANGE);
@@ -137,7 +152,7 @@ __global__ __launch_bounds__(256) void k_thresholds(const int64_t *col_off, cons
 // One workgroup (256 threads) per column with more than kBigDeg in-edges.
 __global__ __launch_bounds__(256) void k_thresholds_big(const int64_t *col_off, const int32_t *row,
                                                         const float *w, NodeRec *nodes,
-                                                        EdgeRec *edges, const uint32_t *big_list,
+                                                        ArcRec *arcs, const uint32_t *big_list,
                                                         const uint32_t *big_count, int *err)
 {
     __shared__ uint64_t wave_tot[4];
@@ -166,11 +181,7 @@ __global__ __launch_bounds__(256) void k_thresholds_big(const int64_t *col_off, 
                 total += wave_tot[k];
             }
             __syncthreads();
-            if (j < hi) {
-                const uint64_t run = carry + before + s;
-                edges[j] = EdgeRec{static_cast<uint32_t>(run > 0xFFFFFFFFull ? 0xFFFFFFFFull : run),
-                                   static_cast<uint32_t>(row[j])};
-            }
+            if (j < hi) put_arc_head(arcs, j, carry + before + s, q, row[j]);
             carry += total;
         }
         if (bad) report(err, E_WEIGHT_RANGE);
@@ -178,6 +189,21 @@ __global__ __launch_bounds__(256) void k_thresholds_big(const int64_t *col_off, 
             if (!column_sum_ok(carry, static_cast<uint64_t>(hi - lo))) report(err, E_WEIGHT_SUM);
             nodes[v] = make_node(static_cast<uint64_t>(lo), static_cast<uint64_t>(hi - lo), carry);
         }
+    }
+}
+
+// Second half of every arc: a copy of its tail's node record.
+__global__ __launch_bounds__(256) void k_arc_tails(const NodeRec *nodes, ArcRec *arcs, int64_t m)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; j < m; j += stride) {
+        const NodeRec R = nodes[arcs[j].row];
+        uint4 v;
+        v.x = R.off;
+        v.y = R.deg;
+        v.z = R.thr_last;
+        v.w = 0u;
+        *reinterpret_cast<uint4 *>(&arcs[j].u_off) = v;
     }
 }
 
@@ -251,7 +277,7 @@ void ingest_graph(sia_graph *g, const int64_t *col_off, const int32_t *row_idx, 
     SIA_HIP(hipMemsetAsync(scratch.ptr, 0, 64, s));
 
     g->nodes.ensure(sizeof(NodeRec) * static_cast<size_t>(n));
-    g->edges.ensure(sizeof(EdgeRec) * static_cast<size_t>(m > 0 ? m : 1));
+    g->arcs.ensure(sizeof(ArcRec) * static_cast<size_t>(m > 0 ? m : 1));
 
     const int cus = device_cu_count();
     if (on_device) {
@@ -272,11 +298,16 @@ void ingest_graph(sia_graph *g, const int64_t *col_off, const int32_t *row_idx, 
     }
     hipLaunchKernelGGL(k_thresholds, dim3(grid_for(static_cast<uint64_t>(n) * kWave, 256, cus * 32)),
                        dim3(256), 0, s, d_off, d_row, d_w, n, g->nodes.as<NodeRec>(),
-                       g->edges.as<EdgeRec>(), d_big, d_big_count, d_err);
+                       g->arcs.as<ArcRec>(), d_big, d_big_count, d_err);
     SIA_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_thresholds_big, dim3(cus * 2), dim3(256), 0, s, d_off, d_row, d_w,
-                       g->nodes.as<NodeRec>(), g->edges.as<EdgeRec>(), d_big, d_big_count, d_err);
+                       g->nodes.as<NodeRec>(), g->arcs.as<ArcRec>(), d_big, d_big_count, d_err);
     SIA_HIP(hipGetLastError());
+    if (m) {
+        hipLaunchKernelGGL(k_arc_tails, dim3(grid_for(m, 256, cus * 32)), dim3(256), 0, s,
+                           g->nodes.as<NodeRec>(), g->arcs.as<ArcRec>(), m);
+        SIA_HIP(hipGetLastError());
+    }
     int err = 0;
     SIA_HIP(hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
     SIA_HIP(hipStreamSynchronize(s));

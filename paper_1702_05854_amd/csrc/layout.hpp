@@ -23,8 +23,9 @@ __device__ __forceinline__ GLOBAL T *gp(T *p)
 // One 16-byte record per node: where its in-edges start, how many, the last
 // cumulative threshold (so the dead-end test needs no extra load), and the
 // source tag: bit b is set exactly when the node is a source of the query
-// holding slot bit b (so membership comes with the record the walk loads
-// anyway).  Bit 31 belongs to single-query calls, bits 0..30 to batches.
+// holding slot bit b.  Bit 31 belongs to single-query calls, bits 0..30 to
+// batches.  The tag is kept in step with the copies in the node's in-edge
+// records (ArcRec.head_tag).
 struct NodeRec {
     uint32_t off;
     uint32_t deg;
@@ -33,13 +34,24 @@ struct NodeRec {
 };
 static_assert(sizeof(NodeRec) == 16, "NodeRec layout");
 
-// One 8-byte record per edge: cumulative threshold and tail node u, so the
-// probe that certifies the choice also yields the next node.
-struct EdgeRec {
-    uint32_t thr;
-    uint32_t row;
+// One 32-byte record per in-edge j of head x (CSR position j, line-aligned,
+// four to a 128-byte line): the interval [thr_lo, thr_hi) of draws that make
+// j the live in-edge of x (thr_lo is the cumulative threshold of the previous
+// in-edge, 0 for the first), the tail u, a copy of x's source tag, and a copy
+// of u's node record (off, deg, thr_last).  A live-edge evaluation of x reads
+// one record: it certifies the choice, says whether x is a source, and holds
+// all the next evaluation, of u, needs -- one random line per step.
+struct ArcRec {
+    uint32_t thr_lo;
+    uint32_t thr_hi;
+    uint32_t row;       // tail u
+    uint32_t head_tag;  // = NodeRec.tag of the head x
+    uint32_t u_off;     // = NodeRec.off of u
+    uint32_t u_deg;     // = NodeRec.deg of u
+    uint32_t u_thr;     // = NodeRec.thr_last of u
+    uint32_t pad;
 };
-static_assert(sizeof(EdgeRec) == 8, "EdgeRec layout");
+static_assert(sizeof(ArcRec) == 32, "ArcRec layout");
 
 // Per-query counters written by the sampler.
 enum StatSlot {

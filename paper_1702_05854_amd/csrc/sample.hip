@@ -24,10 +24,13 @@
 // counter in chunks and find the slot of each attempt in a small table kept
 // in LDS; kept walks are appended with one pair of atomics per slot per
 // wave.  Every iteration a lane computes one Philox block (its start draw,
-// or the draw of the node it evaluates) and, when evaluating, gathers the
-// 16-byte node record (whose tag bits say which slots have the node as a
-// source) and one or two 8-byte edge records (threshold + tail).  A single
-// query is a wave of one slot, so every call goes through this kernel.
+// or the draw of the node it evaluates) and gathers at most one record: the
+// 32-byte in-edge record at the interpolated position of the draw, which
+// certifies the live edge, says whether the evaluated node is a source and
+// carries the next node's offset, degree and last threshold -- so a step
+// costs one random line.  Node records are read only where a walk (re)starts
+// and, for their source tag, at nodes without a live edge.  A single query
+// is a wave of one slot, so every call goes through this kernel.
 #include "common.hpp"
 #include "philox.hpp"
 
@@ -51,7 +54,7 @@ enum Phase : uint32_t {
 
 struct WaveArgs {
     const NodeRec *nodes;
-    const EdgeRec *edges;
+    const ArcRec *arcs;
     const SlotDev *slots;
     uint32_t n_slots;
     uint32_t chunk;                // attempts taken per refill
@@ -93,42 +96,54 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane)
     return v;
 }
 
-// First in-edge j of the node with record R whose threshold exceeds r, or
-// false for "no live edge" (no in-edge, or r >= thr_last).  The first probe
-// is the interpolation guess r * deg / thr_last, certified by
-// thr[g-1] <= r < thr[g]; otherwise bisection on the side the probe points to.
-__device__ __forceinline__ bool select_edge(const EdgeRec *__restrict__ edges, const NodeRec &R,
-                                            uint32_t r, uint32_t &j, uint32_t &u)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Whole-record loads through global pointers (two and one 16-byte loads).
+__device__ __forceinline__ ArcRec load_arc(const GLOBAL ArcRec *p)
 {
-    if (R.deg == 0 || r >= R.thr_last) return false;
-    const float scale = static_cast<float>(R.deg) * __builtin_amdgcn_rcpf(static_cast<float>(R.thr_last));
-    uint32_t g = __float2uint_rz(static_cast<float>(r) * scale);
-    if (g >= R.deg) g = R.deg - 1;
-    const uint32_t base = R.off;
-    EdgeRec e = edges[base + g];
-    const uint32_t prev = g ? edges[base + g - 1].thr : 0u;
-    if (e.thr > r && prev <= r) {
-        j = base + g;
-        u = e.row;
-        return true;
-    }
-    uint32_t lo, hi;  // answer in [lo, hi]; thr[hi] > r
-    if (e.thr <= r) {
+    const GLOBAL u32x4 *q = reinterpret_cast<const GLOBAL u32x4 *>(p);
+    const u32x4 lo = q[0], hi = q[1];
+    return ArcRec{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+}
+
+__device__ __forceinline__ NodeRec load_node(const GLOBAL NodeRec *p)
+{
+    const u32x4 v = *reinterpret_cast<const GLOBAL u32x4 *>(p);
+    return NodeRec{v.x, v.y, v.z, v.w};
+}
+
+// Interpolation guess for the in-edge that is live for draw r at a node with
+// deg in-edges and last threshold thr_last > r: r * deg / thr_last, exact for
+// equal weights.
+__device__ __forceinline__ uint32_t guess_of(uint32_t r, uint32_t deg, uint32_t thr_last)
+{
+    const float scale = static_cast<float>(deg) * __builtin_amdgcn_rcpf(static_cast<float>(thr_last));
+    const uint32_t g = __float2uint_rz(static_cast<float>(r) * scale);
+    return g >= deg ? deg - 1 : g;
+}
+
+// Index of the live in-edge (the first with thr_hi > r) among the deg arcs at
+// base, given E = arcs[base + g]: g itself when E's interval holds r, else
+// bisection on the side E points to; E ends as the chosen arc.
+__device__ __forceinline__ uint32_t settle_arc(const GLOBAL ArcRec *arcs, uint32_t base, uint32_t deg,
+                                               uint32_t g, uint32_t r, ArcRec &E)
+{
+    if (E.thr_lo <= r && r < E.thr_hi) return g;
+    uint32_t lo, hi;  // answer in [lo, hi]
+    if (E.thr_hi <= r) {
         lo = g + 1;
-        hi = R.deg - 1;
+        hi = deg - 1;
     } else {
         lo = 0;
         hi = g - 1;
     }
     while (lo < hi) {
         const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (edges[base + mid].thr > r) hi = mid;
+        if (arcs[base + mid].thr_hi > r) hi = mid;
         else lo = mid + 1;
     }
-    e = edges[base + lo];
-    j = base + lo;
-    u = e.row;
-    return true;
+    E = load_arc(arcs + base + lo);
+    return lo;
 }
 
 __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
@@ -156,11 +171,14 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
     uint64_t chunk_next = 0, chunk_end = 0;
     bool exhausted = false;
     // lane state
-    bool active = false;
+    bool active = false, fetch = false;  // fetch: load cur's node record next iteration
     uint64_t a = 0, out_pos = 0, seed = 0;
     uint32_t slot = 0, mode = SIA_EDGES, tag_mask = 0;
     uint32_t phase = PH_START, x1 = 0, cur = 0, tort = 0, power = 1, lam = 0, t = 0, lambda = 0,
              cnt = 0, pa = 0, pb = 0, evals = 0, ptort = 0, mbase = 0;
+    // (off, deg, thr_last) of the pointers' nodes: c for cur (and pb in the
+    // cycle-entry search), p for pa
+    uint32_t c_off = 0, c_deg = 0, c_thr = 0, p_off = 0, p_deg = 0, p_thr = 0;
 
     for (;;) {
         // ---- refill idle lanes with new attempts (converged section)
@@ -193,6 +211,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 mode = S.mode;
                 tag_mask = S.tag_mask;
                 phase = PH_START;
+                fetch = false;
                 evals = 0;
                 active = true;
             }
@@ -201,46 +220,17 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
         }
         if (__ballot(active) == 0) break;
 
-        // ---- stage 1: choose this iteration's draw; start draws; load the record
-        bool hit_now = false, do_eval = false;
-        uint32_t y = 0;
+        // ---- stage 1: choose this iteration's draw and its one gather
+        bool hit_now = false, do_eval = false, live = false, fetch_now = false, tag_only = false;
+        uint32_t y = 0, r = 0, yoff = 0, ydeg = 0, g = 0;
         NodeRec R = {0u, 0u, 0u, 0u};
-        uint64_t word = 0;
+        ArcRec E = {};
         if (active) {
-            if (phase == PH_DETECT) {
+            if (fetch) {  // the record of a (re)started walk's first node
                 y = cur;
-                if (t > 0) {
-                    ++lam;
-                    if (cur == tort) {  // Brent: cycle of length lam (tort is never a source)
-                        // The tortoise sits at positions 2^j - 1 with a window of
-                        // 2^j.  If lam fits half the final window, the previous
-                        // tortoise (position power/2 - 1) was off the cycle --
-                        // else its window would have found it -- so the search
-                        // for the cycle entry mu starts there, not at x1.
-                        const bool past = lam <= (power >> 1);
-                        lambda = lam;
-                        cnt = lam;
-                        mbase = past ? (power >> 1) - 1u : 0u;
-                        pa = past ? ptort : x1;
-                        pb = pa;
-                        phase = PH_MU_POS;
-                        y = pb;
-                    } else if (lam == power) {
-                        ptort = tort;
-                        tort = cur;
-                        power <<= 1;
-                        lam = 0;
-                    }
-                }
-            } else if (phase == PH_MU_A) {
-                y = pa;
-            } else if (phase == PH_EMIT) {
-                y = cur;
-            } else {
-                y = pb;
-            }
-            word = phase == PH_START ? philox_word0(0, 1, seed, a) : philox_word0(y, 0, seed, a);
-            if (phase == PH_START) {
+                fetch_now = true;
+            } else if (phase == PH_START) {
+                const uint64_t word = philox_word0(0, 1, seed, a);
                 const SlotDev &S = sl[slot];
                 const uint64_t idx = __umul64hi(word, S.n_ns);
                 const GLOBAL uint32_t *src_t = gp(S.src_t);
@@ -253,17 +243,79 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 lam = 0;
                 t = 0;
                 phase = PH_DETECT;
+                fetch = true;
             } else {
-                R = A.nodes[y];
                 do_eval = true;
-                if (phase == PH_DETECT && t > 0 && (R.tag & tag_mask)) {
+                if (phase == PH_DETECT) {
+                    y = cur;
+                    if (t > 0) {
+                        ++lam;
+                        if (cur == tort) {  // Brent: cycle of length lam (tort is never a source)
+                            // The tortoise sits at positions 2^j - 1 with a window of
+                            // 2^j.  If lam fits half the final window, the previous
+                            // tortoise (position power/2 - 1) was off the cycle --
+                            // else its window would have found it -- so the search
+                            // for the cycle entry mu starts there, not at x1.
+                            const bool past = lam <= (power >> 1);
+                            lambda = lam;
+                            cnt = lam;
+                            mbase = past ? (power >> 1) - 1u : 0u;
+                            pa = past ? ptort : x1;
+                            pb = pa;
+                            phase = PH_MU_POS;
+                            y = pa;
+                            fetch_now = true;  // both pointers start from this record
+                            do_eval = false;
+                        } else if (lam == power) {
+                            ptort = tort;
+                            tort = cur;
+                            power <<= 1;
+                            lam = 0;
+                        }
+                    }
+                } else if (phase == PH_MU_A) {
+                    y = pa;
+                } else if (phase == PH_EMIT) {
+                    y = cur;
+                } else {
+                    y = pb;
+                }
+                if (do_eval) {
+                    const bool pside = phase == PH_MU_A;
+                    yoff = pside ? p_off : c_off;
+                    ydeg = pside ? p_deg : c_deg;
+                    const uint32_t ythr = pside ? p_thr : c_thr;
+                    r = static_cast<uint32_t>(philox_word0(y, 0, seed, a) >> 32);
+                    live = ydeg != 0 && r < ythr;
+                    if (live) {
+                        g = guess_of(r, ydeg, ythr);
+                        E = load_arc(gp(A.arcs) + yoff + g);
+                    } else {
+                        tag_only = phase == PH_DETECT && t > 0;
+                    }
+                }
+            }
+            if (fetch_now || tag_only) R = load_node(gp(A.nodes) + y);
+            if (do_eval && phase == PH_DETECT && t > 0) {
+                if ((live ? E.head_tag : R.tag) & tag_mask) {  // reached a source: kept walk
                     hit_now = true;
                     do_eval = false;
-                } else if (phase == PH_DETECT && t > A.guard_evals) {  // unreachable for a correct walk
+                } else if (t > A.guard_evals) {  // unreachable for a correct walk
                     atomicAdd(&acc[slot][5], 1ull);
                     active = false;
                     do_eval = false;
                 }
+            }
+            if (fetch_now) {
+                c_off = R.off;
+                c_deg = R.deg;
+                c_thr = R.thr_last;
+                if (phase == PH_MU_POS) {
+                    p_off = R.off;
+                    p_deg = R.deg;
+                    p_thr = R.thr_last;
+                }
+                fetch = false;
             }
         }
 
@@ -306,6 +358,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                     }
                     phase = PH_EMIT;
                     cur = x1;
+                    fetch = true;
                     cnt = t;
                 } else {
                     gp(S.counters)[ST_OVERFLOW] = 1;
@@ -319,7 +372,19 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
         // ---- stage 3: one live-edge evaluation per evaluating lane
         if (do_eval) {
             uint32_t j = 0, u = 0;
-            const bool live = select_edge(A.edges, R, static_cast<uint32_t>(word >> 32), j, u);
+            if (live) {
+                j = yoff + settle_arc(gp(A.arcs), yoff, ydeg, g, r, E);
+                u = E.row;
+                if (phase == PH_MU_A) {
+                    p_off = E.u_off;
+                    p_deg = E.u_deg;
+                    p_thr = E.u_thr;
+                } else {
+                    c_off = E.u_off;
+                    c_deg = E.u_deg;
+                    c_thr = E.u_thr;
+                }
+            }
             ++evals;
             bool done = false;
             if (phase == PH_DETECT) {
@@ -388,13 +453,25 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
     }
 }
 
-__global__ void k_tag_sources(const int32_t *src, uint32_t n_src, NodeRec *nodes, uint32_t mask,
-                              int set)
+// Set (or clear) bit mask in the tag of every source and in the head_tag
+// copy of each of its in-edge records; one wave per source.
+__global__ __launch_bounds__(256) void k_tag_sources(const int32_t *src, uint32_t n_src, NodeRec *nodes,
+                                                     ArcRec *arcs, uint32_t mask, int set)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_src) {
-        if (set) atomicOr(&nodes[src[i]].tag, mask);
-        else atomicAnd(&nodes[src[i]].tag, ~mask);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
+    for (uint64_t w = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave; w < n_src;
+         w += waves) {
+        const uint32_t v = static_cast<uint32_t>(src[w]);
+        const uint32_t off = nodes[v].off, deg = nodes[v].deg;
+        for (uint32_t i = lane; i < deg; i += kWave) {
+            if (set) atomicOr(&arcs[off + i].head_tag, mask);
+            else atomicAnd(&arcs[off + i].head_tag, ~mask);
+        }
+        if (lane == 0) {
+            if (set) atomicOr(&nodes[v].tag, mask);
+            else atomicAnd(&nodes[v].tag, ~mask);
+        }
     }
 }
 
@@ -434,8 +511,11 @@ void tag_sources(const sia_graph *g, const int32_t *d_src, uint32_t n_src, uint3
                  hipStream_t s)
 {
     if (!n_src) return;
-    hipLaunchKernelGGL(k_tag_sources, dim3((n_src + 255) / 256), dim3(256), 0, s, d_src, n_src,
-                       const_cast<NodeRec *>(g->nodes.as<NodeRec>()), mask, set ? 1 : 0);
+    const unsigned blocks = static_cast<unsigned>(
+        std::min<uint64_t>((static_cast<uint64_t>(n_src) + 3) / 4, static_cast<uint64_t>(device_cu_count()) * 16));
+    hipLaunchKernelGGL(k_tag_sources, dim3(blocks), dim3(256), 0, s, d_src, n_src,
+                       const_cast<NodeRec *>(g->nodes.as<NodeRec>()), const_cast<ArcRec *>(g->arcs.as<ArcRec>()),
+                       mask, set ? 1 : 0);
     SIA_HIP(hipGetLastError());
 }
 
@@ -448,7 +528,7 @@ void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
                                              : max_blocks_per_cu();
     WaveArgs A;
     A.nodes = g->nodes.as<NodeRec>();
-    A.edges = g->edges.as<EdgeRec>();
+    A.arcs = g->arcs.as<ArcRec>();
     A.slots = d_slots;
     A.n_slots = n_slots;
     A.chunk = cfg.chunk;
