@@ -302,6 +302,7 @@ def main():
         "sampler_attempts_per_s": n_att / (ms_sample * 1e-3),
         "ms_sample": ms_sample, "ms_count": ms_count, "ms_greedy": ms_greedy,
         "ingest_ms": ingest_ms,
+        "arc_record_bytes": g.arc_bytes,
         "counts": {key: st[key] for key in ("hits", "dead_ends", "cycles", "steps", "evaluations",
                                             "walk_ids", "covered")},
         "suspension_est": st["suspension_est"],

@@ -144,6 +144,14 @@ sia_status sia_graph_destroy(sia_graph *g);
 /* n and m of a graph (either pointer may be NULL). */
 sia_status sia_graph_info(const sia_graph *g, int64_t *n, int64_t *m);
 
+/* Bytes of the per-in-edge record the graph was stored with: 16 when every
+ * column carries the weights w = 1/d_in of its node (the setting of the
+ * paper's experiments, Section 6.1), checked exactly on the quantised
+ * weights at ingest -- the live in-edge then follows from the draw and the
+ * in-degree alone; 32 otherwise (each record holds its threshold interval).
+ * Results do not depend on it.  Test and reporting hook. */
+sia_status sia_graph_arc_bytes(const sia_graph *g, uint32_t *arc_bytes);
+
 /* Copy the threshold table thr[m] (see sia_graph_create) to host memory
  * thr_host (caller-allocated, m entries).  Test hook. */
 sia_status sia_graph_thresholds(const sia_graph *g, uint32_t *thr_host, void *hip_stream);

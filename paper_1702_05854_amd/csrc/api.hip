@@ -160,6 +160,14 @@ sia_status sia_graph_info(const sia_graph *g, int64_t *n, int64_t *m)
     });
 }
 
+sia_status sia_graph_arc_bytes(const sia_graph *g, uint32_t *arc_bytes)
+{
+    return guarded([&] {
+        SIA_REQUIRE(g != nullptr && arc_bytes != nullptr, SIA_EINVAL, "NULL argument");
+        *arc_bytes = g->arc_bytes;
+    });
+}
+
 sia_status sia_graph_thresholds(const sia_graph *g, uint32_t *thr_host, void *hip_stream)
 {
     return guarded([&] {
@@ -167,10 +175,18 @@ sia_status sia_graph_thresholds(const sia_graph *g, uint32_t *thr_host, void *hi
         DeviceScope ds(g->device);
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
         if (!g->m) return;
-        // thr_hi of every arc: a strided copy straight into the caller's array
-        SIA_HIP(hipMemcpy2DAsync(thr_host, sizeof(uint32_t), g->arcs.as<char>() + offsetof(ArcRec, thr_hi),
-                                 sizeof(ArcRec), sizeof(uint32_t), static_cast<size_t>(g->m),
-                                 hipMemcpyDeviceToHost, s));
+        if (g->arc_bytes == sizeof(ArcRec)) {
+            // thr_hi of every arc: a strided copy straight into the caller's array
+            SIA_HIP(hipMemcpy2DAsync(thr_host, sizeof(uint32_t), g->arcs.as<char>() + offsetof(ArcRec, thr_hi),
+                                     sizeof(ArcRec), sizeof(uint32_t), static_cast<size_t>(g->m),
+                                     hipMemcpyDeviceToHost, s));
+        } else {  // compact records hold no thresholds: they follow from the in-degrees
+            DevBuf tmp;
+            tmp.ensure(sizeof(uint32_t) * static_cast<size_t>(g->m));
+            compact_thresholds(g, tmp.as<uint32_t>(), s);
+            SIA_HIP(hipMemcpyAsync(thr_host, tmp.ptr, sizeof(uint32_t) * g->m, hipMemcpyDeviceToHost, s));
+            SIA_HIP(hipStreamSynchronize(s));
+        }
         SIA_HIP(hipStreamSynchronize(s));
     });
 }

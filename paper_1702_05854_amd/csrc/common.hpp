@@ -8,6 +8,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/sia.h"
@@ -81,6 +82,11 @@ struct DevBuf {
     void ensure(size_t want);  // grow-only, contents not preserved
     void release();
     template <class T> T *as() const { return static_cast<T *>(ptr); }
+    void swap(DevBuf &o)
+    {
+        std::swap(ptr, o.ptr);
+        std::swap(bytes, o.bytes);
+    }
     ~DevBuf() { release(); }
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
@@ -102,7 +108,8 @@ struct sia_graph {
     int64_t n = 0, m = 0;
     int device = 0;
     sia::DevBuf nodes;  // NodeRec[n]
-    sia::DevBuf arcs;   // ArcRec[m]
+    sia::DevBuf arcs;   // ArcRec[m] or ArcRec16[m] (arc_bytes), in CSR order
+    uint32_t arc_bytes = sizeof(sia::ArcRec);
     sia::Workspace ws;
     std::mutex mu;      // one query at a time per graph handle
     std::mutex tag_mu;  // guards tag_bits
@@ -144,7 +151,7 @@ struct SamplerConfig {
     uint32_t chunk = 256;
     int cus = 0;  // CUs the launch stream may use (0: all of the device)
 };
-int sampler_max_blocks_per_cu();
+int sampler_max_blocks_per_cu(const sia_graph *g);  // for the graph's record format
 
 // Sample the wave described by d_table (device) over the n_slots SlotDev
 // entries at d_slots (device).  Asynchronous on stream s.
@@ -209,6 +216,8 @@ void host_check_structure(int64_t n, int64_t m, const int64_t *col_off, const in
 void ingest_graph(sia_graph *g, const int64_t *col_off, const int32_t *row_idx, const float *w,
                   bool on_device, hipStream_t s);
 void quantize_device(const float *w, uint64_t *q, uint64_t count, hipStream_t s);
+// Threshold table thr[m] (device) of a graph with compact records.
+void compact_thresholds(const sia_graph *g, uint32_t *d_thr, hipStream_t s);
 
 int device_cu_count();
 

@@ -4,10 +4,12 @@
 // lo..j, 2^32 - 1).  Edge j is live with probability (thr_j - thr_{j-1})/2^32.
 //
 // Layout built here (device): NodeRec[n] {off, deg, thr_last, source tag 0}
-// and ArcRec[m] {thr_{j-1}, thr_j, tail u, tag 0, u's off / deg / thr_last}.
-// One wave per column (wave-wide uint64 prefix sums); columns above kBigDeg
-// in-edges are finished by one workgroup each; a last pass copies each tail's
-// node record into its arcs.
+// and one record per in-edge j in CSR order: ArcRec {thr_{j-1}, thr_j, tail u,
+// tag 0, u's off / deg / thr_last}, or, when every column has the weights
+// w = 1/d_in (checked exactly on the quantised values), the compact
+// ArcRec16 {tail u, tag 0, u's off / deg}.  One wave per column (wave-wide
+// uint64 prefix sums); columns above kBigDeg in-edges are finished by one
+// workgroup each; a last pass copies each tail's node record into its arcs.
 #include "common.hpp"
 
 #include <algorithm>
@@ -20,12 +22,6 @@ constexpr uint32_t kBigDeg = 16384;
 constexpr int kWave = 64;
 
 enum ErrCode : int { E_NONE = 0, E_OFFSETS = 1, E_ROWS = 2, E_WEIGHT_RANGE = 3, E_WEIGHT_SUM = 4 };
-
-__device__ __forceinline__ uint64_t quantize_weight(float x)
-{
-    // (double)x is exact and so is the scaling by 2^32; rint rounds half to even.
-    return static_cast<uint64_t>(rint(static_cast<double>(x) * 4294967296.0));
-}
 
 __device__ __forceinline__ bool weight_ok(float x) { return x >= 0.0f && x <= 1.0f; }
 
@@ -115,7 +111,7 @@ __device__ __forceinline__ void put_arc_head(ArcRec *arcs, int64_t j, uint64_t r
 __global__ __launch_bounds__(256) void k_thresholds(const int64_t *col_off, const int32_t *row,
                                                     const float *w, int64_t n, NodeRec *nodes,
                                                     ArcRec *arcs, uint32_t *big_list,
-                                                    uint32_t *big_count, int *err)
+                                                    uint32_t *big_count, int *err, int *general)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) / kWave;
@@ -127,8 +123,9 @@ __global__ __launch_bounds__(256) void k_thresholds(const int64_t *col_off, cons
             if (lane == 0) big_list[atomicAdd(big_count, 1u)] = static_cast<uint32_t>(v);
             continue;
         }
+        const uint64_t qd = deg ? inv_indeg_quantum(static_cast<uint32_t>(deg)) : 0;
         uint64_t carry = 0;
-        bool bad = false;
+        bool bad = false, mixed = false;
         for (int64_t base = lo; base < hi; base += kWave) {
             const int64_t j = base + lane;
             uint64_t q = 0;
@@ -136,12 +133,14 @@ __global__ __launch_bounds__(256) void k_thresholds(const int64_t *col_off, cons
                 const float x = w[j];
                 if (!weight_ok(x)) bad = true;
                 else q = quantize_weight(x);
+                if (q != qd) mixed = true;
             }
             const uint64_t s = wave_incl_scan(q, lane);
             if (j < hi) put_arc_head(arcs, j, carry + s, q, row[j]);
             carry += shfl_u64(s, kWave - 1);
         }
         if (bad) report(err, E_WEIGHT_RANGE);
+        if (mixed) atomicOr(general, 1);
         if (lane == 0) {
             if (!column_sum_ok(carry, deg)) report(err, E_WEIGHT_SUM);
             nodes[v] = make_node(static_cast<uint64_t>(lo), deg, carry);
@@ -153,7 +152,8 @@ __global__ __launch_bounds__(256) void k_thresholds(const int64_t *col_off, cons
 __global__ __launch_bounds__(256) void k_thresholds_big(const int64_t *col_off, const int32_t *row,
                                                         const float *w, NodeRec *nodes,
                                                         ArcRec *arcs, const uint32_t *big_list,
-                                                        const uint32_t *big_count, int *err)
+                                                        const uint32_t *big_count, int *err,
+                                                        int *general)
 {
     __shared__ uint64_t wave_tot[4];
     const int lane = threadIdx.x & (kWave - 1);
@@ -162,8 +162,9 @@ __global__ __launch_bounds__(256) void k_thresholds_big(const int64_t *col_off, 
     for (uint32_t b = blockIdx.x; b < count; b += gridDim.x) {
         const uint32_t v = big_list[b];
         const int64_t lo = col_off[v], hi = col_off[v + 1];
+        const uint64_t qd = inv_indeg_quantum(static_cast<uint32_t>(hi - lo));
         uint64_t carry = 0;
-        bool bad = false;
+        bool bad = false, mixed = false;
         for (int64_t base = lo; base < hi; base += blockDim.x) {
             const int64_t j = base + threadIdx.x;
             uint64_t q = 0;
@@ -171,6 +172,7 @@ __global__ __launch_bounds__(256) void k_thresholds_big(const int64_t *col_off, 
                 const float x = w[j];
                 if (!weight_ok(x)) bad = true;
                 else q = quantize_weight(x);
+                if (q != qd) mixed = true;
             }
             uint64_t s = wave_incl_scan(q, lane);
             if (lane == kWave - 1) wave_tot[wid] = s;
@@ -185,6 +187,7 @@ __global__ __launch_bounds__(256) void k_thresholds_big(const int64_t *col_off, 
             carry += total;
         }
         if (bad) report(err, E_WEIGHT_RANGE);
+        if (mixed) atomicOr(general, 1);
         if (threadIdx.x == 0) {
             if (!column_sum_ok(carry, static_cast<uint64_t>(hi - lo))) report(err, E_WEIGHT_SUM);
             nodes[v] = make_node(static_cast<uint64_t>(lo), static_cast<uint64_t>(hi - lo), carry);
@@ -204,6 +207,40 @@ __global__ __launch_bounds__(256) void k_arc_tails(const NodeRec *nodes, ArcRec 
         v.z = R.thr_last;
         v.w = 0u;
         *reinterpret_cast<uint4 *>(&arcs[j].u_off) = v;
+    }
+}
+
+// Compact records (every column has w = 1/d_in): tail, head tag 0 and the
+// tail's offset and degree, from the tails the threshold pass wrote.
+__global__ __launch_bounds__(256) void k_arc16(const NodeRec *nodes, const ArcRec *arcs, ArcRec16 *out,
+                                               int64_t m)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t j = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; j < m; j += stride) {
+        const uint32_t u = arcs[j].row;
+        const NodeRec R = nodes[u];
+        uint4 v;
+        v.x = u;
+        v.y = 0u;
+        v.z = R.off;
+        v.w = R.deg;
+        *reinterpret_cast<uint4 *>(&out[j]) = v;
+    }
+}
+
+// Threshold table of a compact graph: thr_j = min((j - off + 1) * q(d), 2^32 - 1)
+// over each column's in-edges; one wave per column.
+__global__ __launch_bounds__(256) void k_compact_thresholds(const NodeRec *nodes, int64_t n, uint32_t *thr)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (static_cast<int64_t>(gridDim.x) * blockDim.x) / kWave;
+    for (int64_t v = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave; v < n;
+         v += waves) {
+        const NodeRec R = nodes[v];
+        if (!R.deg) continue;
+        const uint64_t q = inv_indeg_quantum(R.deg);
+        for (uint32_t i = lane; i < R.deg; i += kWave)
+            thr[static_cast<uint64_t>(R.off) + i] = clamp32(static_cast<uint64_t>(i + 1) * q);
     }
 }
 
@@ -269,10 +306,11 @@ void ingest_graph(sia_graph *g, const int64_t *col_off, const int32_t *row_idx, 
         d_row = reinterpret_cast<const int32_t *>(base + off_b);
         d_w = reinterpret_cast<const float *>(base + off_b + row_b);
     }
-    // scratch: err (int), big_count (uint32), big_list (uint32[n])
+    // scratch: err (int), big_count (uint32), general (int), big_list (uint32[n])
     scratch.ensure(64 + sizeof(uint32_t) * static_cast<size_t>(n));
     int *d_err = scratch.as<int>();
     uint32_t *d_big_count = reinterpret_cast<uint32_t *>(scratch.as<char>() + 16);
+    int *d_general = reinterpret_cast<int *>(scratch.as<char>() + 32);
     uint32_t *d_big = reinterpret_cast<uint32_t *>(scratch.as<char>() + 64);
     SIA_HIP(hipMemsetAsync(scratch.ptr, 0, 64, s));
 
@@ -298,23 +336,43 @@ void ingest_graph(sia_graph *g, const int64_t *col_off, const int32_t *row_idx, 
     }
     hipLaunchKernelGGL(k_thresholds, dim3(grid_for(static_cast<uint64_t>(n) * kWave, 256, cus * 32)),
                        dim3(256), 0, s, d_off, d_row, d_w, n, g->nodes.as<NodeRec>(),
-                       g->arcs.as<ArcRec>(), d_big, d_big_count, d_err);
+                       g->arcs.as<ArcRec>(), d_big, d_big_count, d_err, d_general);
     SIA_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_thresholds_big, dim3(cus * 2), dim3(256), 0, s, d_off, d_row, d_w,
-                       g->nodes.as<NodeRec>(), g->arcs.as<ArcRec>(), d_big, d_big_count, d_err);
+                       g->nodes.as<NodeRec>(), g->arcs.as<ArcRec>(), d_big, d_big_count, d_err, d_general);
     SIA_HIP(hipGetLastError());
-    if (m) {
-        hipLaunchKernelGGL(k_arc_tails, dim3(grid_for(m, 256, cus * 32)), dim3(256), 0, s,
-                           g->nodes.as<NodeRec>(), g->arcs.as<ArcRec>(), m);
-        SIA_HIP(hipGetLastError());
-    }
-    int err = 0;
-    SIA_HIP(hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, s));
+    int flags[9] = {};  // err at word 0, general at word 8
+    SIA_HIP(hipMemcpyAsync(flags, scratch.ptr, sizeof(flags), hipMemcpyDeviceToHost, s));
     SIA_HIP(hipStreamSynchronize(s));
+    const int err = flags[0];
     SIA_REQUIRE(err != E_WEIGHT_RANGE, SIA_EWEIGHTS, "a weight is outside [0,1] or NaN");
     SIA_REQUIRE(err != E_WEIGHT_SUM, SIA_EWEIGHTS,
                 "a column's in-weights sum above 1 (LT model requires sum <= 1)");
     SIA_REQUIRE(err == E_NONE, SIA_EDEVICE, "ingest failed");
+    g->arc_bytes = flags[8] ? sizeof(ArcRec) : sizeof(ArcRec16);
+    if (!m) return;
+    if (g->arc_bytes == sizeof(ArcRec)) {
+        hipLaunchKernelGGL(k_arc_tails, dim3(grid_for(m, 256, cus * 32)), dim3(256), 0, s,
+                           g->nodes.as<NodeRec>(), g->arcs.as<ArcRec>(), m);
+        SIA_HIP(hipGetLastError());
+    } else {
+        DevBuf compact;
+        compact.ensure(sizeof(ArcRec16) * static_cast<size_t>(m));
+        hipLaunchKernelGGL(k_arc16, dim3(grid_for(m, 256, cus * 32)), dim3(256), 0, s,
+                           g->nodes.as<NodeRec>(), g->arcs.as<ArcRec>(), compact.as<ArcRec16>(), m);
+        SIA_HIP(hipGetLastError());
+        SIA_HIP(hipStreamSynchronize(s));
+        g->arcs.swap(compact);  // the 32-byte staging records are freed here
+    }
+    SIA_HIP(hipStreamSynchronize(s));
+}
+
+void compact_thresholds(const sia_graph *g, uint32_t *d_thr, hipStream_t s)
+{
+    const int cus = device_cu_count();
+    hipLaunchKernelGGL(k_compact_thresholds, dim3(grid_for(static_cast<uint64_t>(g->n) * kWave, 256, cus * 32)),
+                       dim3(256), 0, s, g->nodes.as<NodeRec>(), g->n, d_thr);
+    SIA_HIP(hipGetLastError());
 }
 
 void quantize_device(const float *w, uint64_t *q, uint64_t count, hipStream_t s)

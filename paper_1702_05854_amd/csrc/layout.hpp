@@ -53,6 +53,35 @@ struct ArcRec {
 };
 static_assert(sizeof(ArcRec) == 32, "ArcRec layout");
 
+// Compact 16-byte record for graphs whose every column has the weights
+// w = 1/d_in of the node (the paper's setting), checked exactly at ingest:
+// all in-edges of a node with in-degree d then carry the same quantised weight
+// q(d) = inv_indeg_quantum(d), the live in-edge for draw r is floor(r / q(d))
+// and the node's last threshold is min(d * q(d), 2^32 - 1), so a record needs
+// no thresholds: the tail u, a copy of the head's source tag and u's offset and
+// degree -- one 16-byte load per step.
+struct ArcRec16 {
+    uint32_t row;       // tail u
+    uint32_t head_tag;  // = NodeRec.tag of the head x
+    uint32_t u_off;     // = NodeRec.off of u
+    uint32_t u_deg;     // = NodeRec.deg of u
+};
+static_assert(sizeof(ArcRec16) == 16, "ArcRec16 layout");
+
+// Live-edge threshold unit of a weight x in [0,1]: round-half-even(x * 2^32).
+// (double)x is exact and so is the scaling by 2^32; rint rounds half to even.
+__device__ __forceinline__ uint64_t quantize_weight(float x)
+{
+    return static_cast<uint64_t>(rint(static_cast<double>(x) * 4294967296.0));
+}
+
+// Quantised weight of every in-edge of a node with in-degree d >= 1 under
+// w = 1/d in fp32 (correctly rounded division).
+__device__ __forceinline__ uint64_t inv_indeg_quantum(uint32_t d)
+{
+    return quantize_weight(1.0f / static_cast<float>(d));
+}
+
 // Per-query counters written by the sampler.
 enum StatSlot {
     ST_WALKS = 0, ST_IDS = 1, ST_HITS = 2, ST_DEAD = 3, ST_CYCLE = 4, ST_STEPS = 5,

@@ -25,12 +25,15 @@
 // in LDS; kept walks are appended with one pair of atomics per slot per
 // wave.  Every iteration a lane computes one Philox block (its start draw,
 // or the draw of the node it evaluates) and gathers at most one record: the
-// 32-byte in-edge record at the interpolated position of the draw, which
-// certifies the live edge, says whether the evaluated node is a source and
-// carries the next node's offset, degree and last threshold -- so a step
-// costs one random line.  Node records are read only where a walk (re)starts
-// and, for their source tag, at nodes without a live edge.  A single query
-// is a wave of one slot, so every call goes through this kernel.
+// in-edge record the draw selects, which says whether the evaluated node is a
+// source and carries the next node's offset and degree -- so a step costs one
+// random line.  With 32-byte records (any weights) the record sits at the
+// interpolated position of the draw and its threshold interval certifies the
+// choice (else bisection); with 16-byte records (w = 1/d_in everywhere) the
+// position is floor(r / q(d)) exactly and needs no certificate.  Node records
+// are read only where a walk (re)starts and, for their source tag, at nodes
+// without a live edge.  A single query is a wave of one slot, so every call
+// goes through this kernel.
 #include "common.hpp"
 #include "philox.hpp"
 
@@ -54,7 +57,7 @@ enum Phase : uint32_t {
 
 struct WaveArgs {
     const NodeRec *nodes;
-    const ArcRec *arcs;
+    const void *arcs;              // ArcRec[m] or ArcRec16[m]
     const SlotDev *slots;
     uint32_t n_slots;
     uint32_t chunk;                // attempts taken per refill
@@ -106,10 +109,36 @@ __device__ __forceinline__ ArcRec load_arc(const GLOBAL ArcRec *p)
     return ArcRec{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 }
 
+__device__ __forceinline__ ArcRec16 load_arc16(const GLOBAL ArcRec16 *p)
+{
+    const u32x4 v = *reinterpret_cast<const GLOBAL u32x4 *>(p);
+    return ArcRec16{v.x, v.y, v.z, v.w};
+}
+
 __device__ __forceinline__ NodeRec load_node(const GLOBAL NodeRec *p)
 {
     const u32x4 v = *reinterpret_cast<const GLOBAL u32x4 *>(p);
     return NodeRec{v.x, v.y, v.z, v.w};
+}
+
+// Compact format: the quantum of a node with in-degree d (>= 1) kept in 32
+// bits (d = 1 has q = 2^32, kept as 2^32 - 1: the live draws r < 2^32 - 1
+// then still give index 0), and its last threshold min(d * q, 2^32 - 1).
+__device__ __forceinline__ void compact_node(uint32_t d, uint32_t &q, uint32_t &thr_last)
+{
+    const uint64_t q64 = d ? inv_indeg_quantum(d) : 0;
+    const uint64_t t = static_cast<uint64_t>(d) * q64;
+    q = static_cast<uint32_t>(q64 > 0xFFFFFFFFull ? 0xFFFFFFFFull : q64);
+    thr_last = static_cast<uint32_t>(t > 0xFFFFFFFFull ? 0xFFFFFFFFull : t);
+}
+
+// floor(r / q) for q >= 1: a float estimate, corrected exactly.
+__device__ __forceinline__ uint32_t quantum_index(uint32_t r, uint32_t q)
+{
+    uint32_t j = __float2uint_rz(static_cast<float>(r) * __builtin_amdgcn_rcpf(static_cast<float>(q)));
+    while (static_cast<uint64_t>(j) * q > r) --j;
+    while (static_cast<uint64_t>(j + 1) * q <= r) ++j;
+    return j;
 }
 
 // Interpolation guess for the in-edge that is live for draw r at a node with
@@ -146,6 +175,7 @@ __device__ __forceinline__ uint32_t settle_arc(const GLOBAL ArcRec *arcs, uint32
     return lo;
 }
 
+template <bool kCompact>
 __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
 {
     __shared__ SlotDev sl[kMaxSlots + 1];
@@ -176,9 +206,9 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
     uint32_t slot = 0, mode = SIA_EDGES, tag_mask = 0;
     uint32_t phase = PH_START, x1 = 0, cur = 0, tort = 0, power = 1, lam = 0, t = 0, lambda = 0,
              cnt = 0, pa = 0, pb = 0, evals = 0, ptort = 0, mbase = 0;
-    // (off, deg, thr_last) of the pointers' nodes: c for cur (and pb in the
-    // cycle-entry search), p for pa
-    uint32_t c_off = 0, c_deg = 0, c_thr = 0, p_off = 0, p_deg = 0, p_thr = 0;
+    // (off, deg, thr_last, compact quantum) of the pointers' nodes: c for cur
+    // (and pb in the cycle-entry search), p for pa
+    uint32_t c_off = 0, c_deg = 0, c_thr = 0, c_q = 0, p_off = 0, p_deg = 0, p_thr = 0, p_q = 0;
 
     for (;;) {
         // ---- refill idle lanes with new attempts (converged section)
@@ -221,29 +251,18 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
         if (__ballot(active) == 0) break;
 
         // ---- stage 1: choose this iteration's draw and its one gather
-        bool hit_now = false, do_eval = false, live = false, fetch_now = false, tag_only = false;
+        bool hit_now = false, do_eval = false, live = false, fetch_now = false, tag_only = false,
+             starting = false;
         uint32_t y = 0, r = 0, yoff = 0, ydeg = 0, g = 0;
         NodeRec R = {0u, 0u, 0u, 0u};
         ArcRec E = {};
+        ArcRec16 E16 = {};
         if (active) {
             if (fetch) {  // the record of a (re)started walk's first node
                 y = cur;
                 fetch_now = true;
             } else if (phase == PH_START) {
-                const uint64_t word = philox_word0(0, 1, seed, a);
-                const SlotDev &S = sl[slot];
-                const uint64_t idx = __umul64hi(word, S.n_ns);
-                const GLOBAL uint32_t *src_t = gp(S.src_t);
-                uint32_t c = gp(S.bucket)[idx >> S.bucket_shift];
-                while (c < S.n_src && src_t[c] <= idx) ++c;
-                x1 = static_cast<uint32_t>(idx + c);
-                cur = x1;
-                tort = x1;
-                power = 1;
-                lam = 0;
-                t = 0;
-                phase = PH_DETECT;
-                fetch = true;
+                starting = true;
             } else {
                 do_eval = true;
                 if (phase == PH_DETECT) {
@@ -280,24 +299,50 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 } else {
                     y = pb;
                 }
-                if (do_eval) {
-                    const bool pside = phase == PH_MU_A;
-                    yoff = pside ? p_off : c_off;
-                    ydeg = pside ? p_deg : c_deg;
-                    const uint32_t ythr = pside ? p_thr : c_thr;
-                    r = static_cast<uint32_t>(philox_word0(y, 0, seed, a) >> 32);
-                    live = ydeg != 0 && r < ythr;
-                    if (live) {
-                        g = guess_of(r, ydeg, ythr);
-                        E = load_arc(gp(A.arcs) + yoff + g);
+            }
+        }
+        // one Philox block per lane and iteration: the start draw (counter
+        // (0,1)) or the draw of node y (counter (y,0)); computed by every lane
+        // so the wave runs the rounds once
+        const uint64_t word = philox_word0(starting ? 0u : y, starting ? 1u : 0u, seed, a);
+        if (active) {
+            if (starting) {
+                const SlotDev &S = sl[slot];
+                const uint64_t idx = __umul64hi(word, S.n_ns);
+                const GLOBAL uint32_t *src_t = gp(S.src_t);
+                uint32_t c = gp(S.bucket)[idx >> S.bucket_shift];
+                while (c < S.n_src && src_t[c] <= idx) ++c;
+                x1 = static_cast<uint32_t>(idx + c);
+                cur = x1;
+                tort = x1;
+                power = 1;
+                lam = 0;
+                t = 0;
+                phase = PH_DETECT;
+                fetch = true;
+            } else if (do_eval) {
+                const bool pside = phase == PH_MU_A;
+                yoff = pside ? p_off : c_off;
+                ydeg = pside ? p_deg : c_deg;
+                const uint32_t ythr = pside ? p_thr : c_thr;
+                r = static_cast<uint32_t>(word >> 32);
+                live = ydeg != 0 && r < ythr;
+                if (live) {
+                    if constexpr (kCompact) {
+                        g = min(quantum_index(r, pside ? p_q : c_q), ydeg - 1u);
+                        E16 = load_arc16(gp(static_cast<const ArcRec16 *>(A.arcs)) + yoff + g);
                     } else {
-                        tag_only = phase == PH_DETECT && t > 0;
+                        g = guess_of(r, ydeg, ythr);
+                        E = load_arc(gp(static_cast<const ArcRec *>(A.arcs)) + yoff + g);
                     }
+                } else {
+                    tag_only = phase == PH_DETECT && t > 0;
                 }
             }
             if (fetch_now || tag_only) R = load_node(gp(A.nodes) + y);
             if (do_eval && phase == PH_DETECT && t > 0) {
-                if ((live ? E.head_tag : R.tag) & tag_mask) {  // reached a source: kept walk
+                const uint32_t tag = live ? (kCompact ? E16.head_tag : E.head_tag) : R.tag;
+                if (tag & tag_mask) {  // reached a source: kept walk
                     hit_now = true;
                     do_eval = false;
                 } else if (t > A.guard_evals) {  // unreachable for a correct walk
@@ -310,10 +355,12 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 c_off = R.off;
                 c_deg = R.deg;
                 c_thr = R.thr_last;
+                if constexpr (kCompact) compact_node(R.deg, c_q, c_thr);
                 if (phase == PH_MU_POS) {
-                    p_off = R.off;
-                    p_deg = R.deg;
-                    p_thr = R.thr_last;
+                    p_off = c_off;
+                    p_deg = c_deg;
+                    p_thr = c_thr;
+                    p_q = c_q;
                 }
                 fetch = false;
             }
@@ -373,16 +420,30 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
         if (do_eval) {
             uint32_t j = 0, u = 0;
             if (live) {
-                j = yoff + settle_arc(gp(A.arcs), yoff, ydeg, g, r, E);
-                u = E.row;
-                if (phase == PH_MU_A) {
-                    p_off = E.u_off;
-                    p_deg = E.u_deg;
-                    p_thr = E.u_thr;
+                uint32_t uo, ud, ut, uq = 0;
+                if constexpr (kCompact) {
+                    j = yoff + g;
+                    u = E16.row;
+                    uo = E16.u_off;
+                    ud = E16.u_deg;
+                    compact_node(ud, uq, ut);
                 } else {
-                    c_off = E.u_off;
-                    c_deg = E.u_deg;
-                    c_thr = E.u_thr;
+                    j = yoff + settle_arc(gp(static_cast<const ArcRec *>(A.arcs)), yoff, ydeg, g, r, E);
+                    u = E.row;
+                    uo = E.u_off;
+                    ud = E.u_deg;
+                    ut = E.u_thr;
+                }
+                if (phase == PH_MU_A) {
+                    p_off = uo;
+                    p_deg = ud;
+                    p_thr = ut;
+                    p_q = uq;
+                } else {
+                    c_off = uo;
+                    c_deg = ud;
+                    c_thr = ut;
+                    c_q = uq;
                 }
             }
             ++evals;
@@ -454,9 +515,11 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
 }
 
 // Set (or clear) bit mask in the tag of every source and in the head_tag
-// copy of each of its in-edge records; one wave per source.
+// copy of each of its in-edge records (word tag_words[j * stride] of record j);
+// one wave per source.
 __global__ __launch_bounds__(256) void k_tag_sources(const int32_t *src, uint32_t n_src, NodeRec *nodes,
-                                                     ArcRec *arcs, uint32_t mask, int set)
+                                                     uint32_t *tag_words, uint32_t stride, uint32_t mask,
+                                                     int set)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
@@ -465,8 +528,9 @@ __global__ __launch_bounds__(256) void k_tag_sources(const int32_t *src, uint32_
         const uint32_t v = static_cast<uint32_t>(src[w]);
         const uint32_t off = nodes[v].off, deg = nodes[v].deg;
         for (uint32_t i = lane; i < deg; i += kWave) {
-            if (set) atomicOr(&arcs[off + i].head_tag, mask);
-            else atomicAnd(&arcs[off + i].head_tag, ~mask);
+            uint32_t *p = tag_words + static_cast<uint64_t>(off + i) * stride;
+            if (set) atomicOr(p, mask);
+            else atomicAnd(p, ~mask);
         }
         if (lane == 0) {
             if (set) atomicOr(&nodes[v].tag, mask);
@@ -475,20 +539,24 @@ __global__ __launch_bounds__(256) void k_tag_sources(const int32_t *src, uint32_
     }
 }
 
-int max_blocks_per_cu()
+int max_blocks_per_cu(bool compact)
 {
-    static int per_cu = 0;
-    if (!per_cu) {
-        int v = 0;
-        SIA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_sample, 256, 0));
-        per_cu = std::max(1, v);
+    static int per_cu[2] = {0, 0};
+    int &v = per_cu[compact ? 1 : 0];
+    if (!v) {
+        int b = 0;
+        if (compact) SIA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sample<true>, 256, 0));
+        else SIA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_sample<false>, 256, 0));
+        v = std::max(1, b);
     }
-    return per_cu;
+    return v;
 }
+
+bool compact_arcs(const sia_graph *g) { return g->arc_bytes == sizeof(ArcRec16); }
 
 }  // namespace
 
-int sampler_max_blocks_per_cu() { return max_blocks_per_cu(); }
+int sampler_max_blocks_per_cu(const sia_graph *g) { return max_blocks_per_cu(compact_arcs(g)); }
 
 void fill_wave_table(WaveTable &t, const WaveItem *items, uint32_t n_items, uint32_t n_slots)
 {
@@ -513,9 +581,17 @@ void tag_sources(const sia_graph *g, const int32_t *d_src, uint32_t n_src, uint3
     if (!n_src) return;
     const unsigned blocks = static_cast<unsigned>(
         std::min<uint64_t>((static_cast<uint64_t>(n_src) + 3) / 4, static_cast<uint64_t>(device_cu_count()) * 16));
+    uint32_t *words = g->arcs.as<uint32_t>();
+    uint32_t stride;
+    if (compact_arcs(g)) {
+        words += offsetof(ArcRec16, head_tag) / sizeof(uint32_t);
+        stride = sizeof(ArcRec16) / sizeof(uint32_t);
+    } else {
+        words += offsetof(ArcRec, head_tag) / sizeof(uint32_t);
+        stride = sizeof(ArcRec) / sizeof(uint32_t);
+    }
     hipLaunchKernelGGL(k_tag_sources, dim3(blocks), dim3(256), 0, s, d_src, n_src,
-                       const_cast<NodeRec *>(g->nodes.as<NodeRec>()), const_cast<ArcRec *>(g->arcs.as<ArcRec>()),
-                       mask, set ? 1 : 0);
+                       const_cast<NodeRec *>(g->nodes.as<NodeRec>()), words, stride, mask, set ? 1 : 0);
     SIA_HIP(hipGetLastError());
 }
 
@@ -524,18 +600,20 @@ void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
 {
     SIA_REQUIRE(n_slots >= 1 && n_slots <= kMaxSlots + 1, SIA_EINVAL, "bad wave shape");
     SIA_REQUIRE(cfg.chunk >= 1 && cfg.chunk <= (1u << 20), SIA_EINVAL, "bad refill chunk");
-    const int per_cu = cfg.blocks_per_cu > 0 ? std::min(cfg.blocks_per_cu, max_blocks_per_cu())
-                                             : max_blocks_per_cu();
+    const bool compact = compact_arcs(g);
+    const int per_cu = cfg.blocks_per_cu > 0 ? std::min(cfg.blocks_per_cu, max_blocks_per_cu(compact))
+                                             : max_blocks_per_cu(compact);
     WaveArgs A;
     A.nodes = g->nodes.as<NodeRec>();
-    A.arcs = g->arcs.as<ArcRec>();
+    A.arcs = g->arcs.ptr;
     A.slots = d_slots;
     A.n_slots = n_slots;
     A.chunk = cfg.chunk;
     A.table = d_table;
     A.guard_evals = 3 * static_cast<uint64_t>(g->n) + 8;
     const int cus = cfg.cus > 0 ? std::min(cfg.cus, device_cu_count()) : device_cu_count();
-    hipLaunchKernelGGL(k_sample, dim3(per_cu * cus), dim3(256), 0, s, A);
+    if (compact) hipLaunchKernelGGL(k_sample<true>, dim3(per_cu * cus), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL(k_sample<false>, dim3(per_cu * cus), dim3(256), 0, s, A);
     SIA_HIP(hipGetLastError());
 }
 

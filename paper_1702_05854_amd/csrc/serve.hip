@@ -828,7 +828,7 @@ struct sia_batch {
             slots[0].t = t;
         }
         upload_sources(0);
-        const int max_b = sampler_max_blocks_per_cu();
+        const int max_b = sampler_max_blocks_per_cu(g);
         std::vector<SamplerConfig> cands;
         for (int b = max_b; b >= std::max(1, max_b - 2); --b)
             for (uint32_t c : {64u, 128u, 256u, 512u}) cands.push_back(SamplerConfig{b, c});
@@ -1076,7 +1076,7 @@ sia_status sia_batch_create(const sia_graph *cg, uint64_t walk_budget_bytes, int
         raw->d_slots.ensure(sizeof(SlotDev) * raw->n_slots);
         raw->d_ctr.ensure(cb);
         raw->d_jobs.ensure(greedy_job_table_bytes(raw->n_slots));
-        (void)sampler_max_blocks_per_cu();  // occupancy query before any capture
+        (void)sampler_max_blocks_per_cu(g);  // occupancy query before any capture
         raw->ctr.walk_budget = walk_budget_bytes;
         raw->ctr.slots = raw->n_slots;
         raw->t0 = Clock::now();

@@ -109,6 +109,7 @@ def lib():
         L.sia_graph_destroy.argtypes = [p]
         L.sia_graph_info.argtypes = [p, C.POINTER(i64), C.POINTER(i64)]
         L.sia_graph_thresholds.argtypes = [p, p, p]
+        L.sia_graph_arc_bytes.argtypes = [p, C.POINTER(C.c_uint32)]
         L.sia_quantize.argtypes = [p, p, u64, p]
         L.sia_sample.argtypes = [p, i32, p, i64, u64, u64, u64, C.POINTER(_Walks), p]
         L.sia_walks_free.argtypes = [C.POINTER(_Walks)]
@@ -126,7 +127,8 @@ def lib():
         L.sia_probe_gather.argtypes = [u64, C.c_uint32, i32, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), p]
         for name in ("sia_check_query", "sia_graph_create", "sia_graph_destroy", "sia_graph_info",
-                     "sia_graph_thresholds", "sia_quantize", "sia_sample", "sia_greedy",
+                     "sia_graph_thresholds", "sia_graph_arc_bytes", "sia_quantize", "sia_sample",
+                     "sia_greedy",
                      "sia_solve", "sia_probe_gather") + BATCH_SYMBOLS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -207,6 +209,13 @@ class Graph:
     @property
     def handle(self):
         return self._h
+
+    @property
+    def arc_bytes(self):
+        """Bytes per stored in-edge record: 16 (every column w = 1/d_in) or 32."""
+        v = C.c_uint32()
+        _check(lib().sia_graph_arc_bytes(self._h, C.byref(v)))
+        return v.value
 
     def thresholds(self, stream=None):
         thr = np.zeros(self.m, dtype=np.uint32)

@@ -72,6 +72,49 @@ def test_thresholds_big_columns_and_device_inputs(sia):
     assert np.array_equal(g.thresholds(), ref)
 
 
+def compact_case(seed=7, n=3000):
+    """A graph with w = 1/d_in (fp32) in every column: ragged small columns,
+    in-degree-1 columns and one column above the one-workgroup size."""
+    rng = np.random.default_rng(seed)
+    degs = rng.integers(0, 7, n)
+    degs[5] = 20_000
+    degs[9] = degs[11] = 1
+    col = np.zeros(n + 1, np.int64)
+    col[1:] = np.cumsum(degs)
+    m = int(col[-1])
+    row = rng.integers(0, n, m).astype(np.int32)
+    w = np.empty(m, np.float32)
+    for v in range(n):
+        if degs[v]:
+            w[col[v]:col[v + 1]] = np.float32(1.0) / np.float32(degs[v])
+    return col, row, w, degs
+
+
+@pytest.mark.parametrize("perturb", [False, True])
+def test_record_format_follows_weights(sia, perturb):
+    """w = 1/d_in in every column gives 16-byte records, anything else (here
+    one weight of one column moved by one ulp) 32-byte ones; thresholds, walks
+    and answers equal the oracle's either way."""
+    col, row, w, degs = compact_case()
+    if perturb:
+        v = int(np.flatnonzero(degs >= 3)[0])
+        w[col[v] + 1] = np.nextafter(w[col[v] + 1], np.float32(0))
+    g = sia.Graph(col, row, w)
+    assert g.arc_bytes == (32 if perturb else 16)
+    og = cpu.Graph(col, row, w)
+    assert np.array_equal(g.thresholds(), og.thr)
+    src = [3, 5, 77, 1234, 2999]
+    for mode in ("edges", "nodes"):
+        for offset, N in ((0, 40_000), (10 ** 12, 7_777)):
+            got = sia.sample(g, src, mode, N, offset, SEED)
+            ref = og.sample(np.array(src, np.int32), omode(mode), N, offset, SEED)
+            assert_walks_equal(got, ref, (perturb, mode, offset))
+        r = sia.solve(g, src, mode, 25, 40_000, 0, SEED)
+        o = cpu.solve(og, np.array(src, np.int32), omode(mode), 25, 40_000, 0, SEED)
+        assert np.array_equal(r["selected"], o["selected"]), (perturb, mode)
+        assert np.array_equal(r["gains"], o["gains"]), (perturb, mode)
+
+
 def test_quantize_exhaustive_all_fp32_in_unit_interval(sia):
     """Every fp32 value in [0, 1] (bit patterns 0 .. 0x3F800000) converts to
     the same integer on the device as in the oracle."""
