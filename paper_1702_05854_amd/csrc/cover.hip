@@ -68,6 +68,10 @@ struct GreedyState {
     uint32_t next_id;   // PLAN_TIES: lowest tied id left out
     uint32_t plist_total;  // ids' list entries of the current pool
     uint64_t tau;       // bound on keys outside the pool (without left-out ties)
+    uint32_t n_claimed;     // walks covered so far (entries of the claimed list)
+    uint32_t claimed_done;  // of them, already taken off the global counts
+    uint32_t marked;        // rounds whose picks are marked selected in the global counts
+    uint32_t pad;
 };
 
 static_assert(sizeof(GreedyState) % 8 == 0, "GreedyState is cleared in 8-byte words");
@@ -80,6 +84,7 @@ struct GreedyJob {
     uint32_t *pfill;    // kPoolMax: list fill counters
     uint32_t *bitmap;   // ceil(id_space / 32): marked ids
     uint32_t *covered;  // n_walks
+    uint32_t *claimed;  // n_walks: covered walks in the order they were covered
     const uint64_t *walk_off;
     const uint32_t *walk_len;
     const uint32_t *ids;
@@ -107,6 +112,7 @@ struct GJob {
     GLOBAL uint32_t *pfill;
     GLOBAL uint32_t *bitmap;
     GLOBAL uint32_t *covered;
+    GLOBAL uint32_t *claimed;
     const GLOBAL uint64_t *walk_off;
     const GLOBAL uint32_t *walk_len;
     const GLOBAL uint32_t *ids;
@@ -131,6 +137,7 @@ __device__ __forceinline__ GJob view(const GreedyJob &j)
     J.pfill = gp(j.pfill);
     J.bitmap = gp(j.bitmap);
     J.covered = gp(j.covered);
+    J.claimed = gp(j.claimed);
     J.walk_off = gp(j.walk_off);
     J.walk_len = gp(j.walk_len);
     J.ids = gp(j.ids);
@@ -535,18 +542,19 @@ __device__ __forceinline__ int pool_find(const uint32_t *slot, const uint32_t *p
 // certifies the pick.
 //
 // The pool lives in LDS for the whole launch: its ids, their exact counts
-// (kept exact by decrementing them beside the global counts; a walk covered
-// now never holds an id chosen in an earlier round, so chosen entries are
-// never decremented) and a hash from id to pool position.  A round's argmax
-// is then an LDS scan, and the global count decrements are never waited for
-// inside the launch: the ids chosen here are marked in the global counts
-// after a fence at the end.  Each pool id's list range sits in registers of
-// the thread that holds the id.
+// (a walk covered now never holds an id chosen in an earlier round, so chosen
+// entries are never decremented) and a hash from id to pool position.  A
+// round's argmax is then an LDS scan.  The global counts are not touched
+// here: each covered walk is appended to the claimed list, and k_uncover
+// (all CUs) takes the list's walks off the global counts after the launch,
+// before k_mark marks this launch's picks selected.  Each pool id's list
+// range sits in registers of the thread that holds the id.
 //
 // Covering: each pass claims up to T of the chosen id's walks (one list
-// entry per thread), a block scan of their lengths lays their ids end to
-// end, and every thread decrements the counts of the ids at its positions
-// (finding the walk by binary search over the pass's starts in LDS).
+// entry per thread); block scans rank the claimed walks and lay their ids end
+// to end; every thread reads the ids at its positions (finding each one's walk
+// by binary search over the claimed walks' first positions in LDS) and
+// decrements the LDS counts of pool ids.
 //
 // Zero gains.  When the best key of the pool has gain 0, every unselected id
 // of the pool has count 0 (and the plan is a tie at count 0, so every id
@@ -601,6 +609,7 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
     __syncthreads();
     const int64_t r0 = st->rounds;
     int64_t r = r0;
+    uint32_t cbase = st->n_claimed;  // uniform: next entry of the claimed list
     for (; r < J.k; ++r) {
         // exact keys of the pool; the largest is this round's pick if it beats tau
         uint64_t best = 0;
@@ -702,35 +711,44 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
         const uint32_t lo = wlo, hi = whi;
         for (uint32_t b0 = lo; b0 < hi; b0 += T) {
             const uint32_t p = b0 + threadIdx.x;
-            uint32_t len = 0;
+            uint32_t len = 0, w = 0;
             uint64_t off = 0;
             if (p < hi) {
-                const uint32_t w = J.plist[p];
+                w = J.plist[p];
                 // the walk record is read beside the claim (used only if claimed)
                 const uint64_t o = J.walk_off[w];
                 const uint32_t l = J.walk_len[w];
-                if (g_xchg(&J.covered[w], 1u) == 0u) {
+                if (g_xchg(&J.covered[w], 1u) == 0u) {  // a kept walk has >= 1 id
                     off = o;
                     len = l;
                 }
             }
-            uint32_t total;
-            const uint32_t first = block_excl_scan<T>(len, sh32, total);  // ends with a barrier
-            start[threadIdx.x] = first;
-            woff[threadIdx.x] = off;
+            uint32_t n_new;
+            const uint32_t rank = block_excl_scan<T>(len ? 1u : 0u, sh32, n_new);  // ends with a barrier
+            if (len) {
+                start[rank] = len;
+                woff[rank] = off;
+                J.claimed[cbase + rank] = w;
+            }
+            cbase += n_new;
             __syncthreads();
-            // positions f = threadIdx.x + u*T, kUnroll at a time: every id load
-            // of a group is issued before its decrements
-            constexpr int kUnroll = 8;
-            for (uint32_t f0 = threadIdx.x; f0 < total; f0 += kUnroll * T) {
-                uint32_t x[kUnroll];
+            const uint32_t mylen = threadIdx.x < n_new ? start[threadIdx.x] : 0u;
+            uint32_t total;
+            const uint32_t first = block_excl_scan<T>(mylen, sh32, total);  // ends with a barrier
+            start[threadIdx.x] = first;  // first position of claimed walk threadIdx.x
+            __syncthreads();
+            // positions f = threadIdx.x + u*T, kSpan at a time: every id load of
+            // a group is issued before its LDS updates
+            constexpr uint32_t kSpan = 8;
+            for (uint32_t f0 = threadIdx.x; f0 < total; f0 += kSpan * T) {
+                uint32_t x[kSpan];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                for (uint32_t u = 0; u < kSpan; ++u) {
                     const uint32_t f = f0 + u * T;
                     x[u] = id;
                     if (f < total) {
-                        // the last pass entry whose first position is <= f holds position f
-                        uint32_t a = 0, b = T - 1;
+                        // the last claimed walk whose first position is <= f holds f
+                        uint32_t a = 0, b = n_new - 1;
                         while (a < b) {
                             const uint32_t m = (a + b + 1) >> 1;
                             if (start[m] <= f) a = m;
@@ -740,9 +758,8 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                for (uint32_t u = 0; u < kSpan; ++u) {
                     if (x[u] != id) {
-                        g_add(&J.cnt[x[u]], 0xFFFFFFFFu);
                         const int pos = pool_find(slot, pids, x[u]);
                         if (pos >= 0) atomicSub(&pcnt[pos], 1u);
                     }
@@ -751,16 +768,48 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             __syncthreads();  // LDS counts final and LDS free before the next pass / round
         }
     }
-    // every global decrement of this workgroup is complete before the ids
-    // chosen here are marked selected in the global counts
-    __threadfence();
-    __syncthreads();
-    for (int64_t q = r0 + threadIdx.x; q < r; q += T) J.cnt[J.sel[q]] = kSelected;
-    if (threadIdx.x == 0) st->rounds = static_cast<uint32_t>(r);
+    if (threadIdx.x == 0) {
+        st->rounds = static_cast<uint32_t>(r);
+        st->n_claimed = cbase;
+    }
     // unmark the pool (the next rebuild marks its own)
 #pragma unroll
     for (int j = 0; j < kPer; ++j)
         if (threadIdx.x + j * T < P) g_and(&J.bitmap[pid[j] >> 5], ~(1u << (pid[j] & 31)));
+}
+
+// Take the walks covered by the last k_lazy launch off the global counts:
+// one wave per claimed walk, its lanes along the walk's ids.  The picks'
+// own counts drop too; k_mark overwrites them next.
+__global__ __launch_bounds__(256) void k_uncover(const GreedyJob *jobs)
+{
+    const GJob J = view(jobs[blockIdx.y]);
+    const GLOBAL GreedyState *st = J.st;
+    const uint32_t lo = st->claimed_done, hi = st->n_claimed;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
+    for (uint64_t c = lo + (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave; c < hi;
+         c += waves) {
+        const uint32_t w = J.claimed[c];
+        const uint64_t o = J.walk_off[w];
+        const uint32_t L = J.walk_len[w];
+        for (uint32_t e = lane; e < L; e += kWave) g_add(&J.cnt[J.ids[o + e]], 0xFFFFFFFFu);
+    }
+}
+
+// Mark the picks of the rounds since the last call selected in the global
+// counts (after k_uncover) and retire the claimed entries.
+__global__ __launch_bounds__(256) void k_mark(const GreedyJob *jobs)
+{
+    const GJob J = view(jobs[blockIdx.x]);
+    GLOBAL GreedyState *st = J.st;
+    const uint32_t from = st->marked, r = st->rounds, claimed = st->n_claimed;
+    for (uint32_t q = from + threadIdx.x; q < r; q += blockDim.x) J.cnt[J.sel[q]] = kSelected;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->marked = r;
+        st->claimed_done = claimed;
+    }
 }
 
 unsigned grid_for(uint64_t items, unsigned block, unsigned cap)
@@ -789,6 +838,7 @@ GreedyJob carve(const GreedyInput &g)
     J.pfill = reinterpret_cast<uint32_t *>(take(4 * kPoolMax));
     J.bitmap = reinterpret_cast<uint32_t *>(take(4 * ((S + 31) / 32)));
     J.covered = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
+    J.claimed = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
     J.sel = reinterpret_cast<int64_t *>(take(8 * g.k));
     J.gain = reinterpret_cast<uint64_t *>(take(8 * g.k));
     J.hist = reinterpret_cast<uint32_t *>(take(4 * kBins));
@@ -814,7 +864,7 @@ size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids,
     const uint64_t S = id_space;
     return al256(4 * S) + al256(4 * std::max<uint64_t>(n_ids, 1)) + al256(4 * (kPoolMax + 1)) +
            al256(4 * kPoolMax) + al256(4 * ((S + 31) / 32)) +
-           al256(4 * std::max<uint64_t>(n_walks, 1)) + 2 * al256(8 * static_cast<uint64_t>(k)) +
+           2 * al256(4 * std::max<uint64_t>(n_walks, 1)) + 2 * al256(8 * static_cast<uint64_t>(k)) +
            al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile));
 }
 
@@ -885,6 +935,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
             hipLaunchKernelGGL(k_pool_mark, dim3(Q), dim3(1024), 0, s, d_jobs);
             hipLaunchKernelGGL(k_pool_fill, dim3(fill_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_lazy<T>, dim3(Q), dim3(T), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_uncover, dim3(cus * 4, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_mark, dim3(Q), dim3(256), 0, s, d_jobs);
             SIA_HIP(hipGetLastError());
         }
         SIA_HIP(hipMemcpyAsync(hs.data(), d_states, sizeof(GreedyState) * Q, hipMemcpyDeviceToHost, s));
