@@ -51,6 +51,8 @@ constexpr uint32_t kPoolTarget = 4096;
 constexpr uint32_t kPoolMax = 8192;        // the lazy rounds keep the pool in LDS
 constexpr uint32_t kHashBits = 14;         // id -> pool position hash, load <= 1/2
 constexpr uint32_t kHash = 1u << kHashBits;
+constexpr uint32_t kFilterBits = 17;       // LDS bit filter of pool ids (false positives <= 1/16)
+constexpr uint32_t kFilterWords = (1u << kFilterBits) / 32;
 static_assert(kHash >= 2 * kPoolMax, "pool hash load factor");
 
 enum PlanKind : uint32_t { PLAN_COLLECT = 0, PLAN_TIES = 1 };
@@ -460,6 +462,31 @@ __global__ __launch_bounds__(256) void k_tie_emit(const GreedyJob *jobs)
 // pool position) and lay out its list: pstart = exclusive prefix over the
 // pool of those counts.  One workgroup per job.  Counts do not change until
 // the lists are filled.
+// One bit per hash value of the pool's ids: a clear bit proves an id is not
+// in the pool, so most ids need no further lookup.
+__device__ __forceinline__ uint32_t filter_hash(uint32_t x)
+{
+    return (x * 0x9E3779B1u) >> (32 - kFilterBits);
+}
+
+__device__ __forceinline__ bool filter_has(const uint32_t *filt, uint32_t x)
+{
+    const uint32_t h = filter_hash(x);
+    return (filt[h >> 5] >> (h & 31)) & 1u;
+}
+
+// Build the filter of the pool's P ids in LDS (all threads of the block).
+__device__ __forceinline__ void filter_build(uint32_t *filt, const GLOBAL uint32_t *pool, uint32_t P)
+{
+    for (uint32_t i = threadIdx.x; i < kFilterWords; i += blockDim.x) filt[i] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        const uint32_t h = filter_hash(pool[i]);
+        atomicOr(&filt[h >> 5], 1u << (h & 31));
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(1024) void k_pool_mark(const GreedyJob *jobs)
 {
     __shared__ uint32_t sh[1024 / kWave];
@@ -495,11 +522,14 @@ __global__ __launch_bounds__(1024) void k_pool_mark(const GreedyJob *jobs)
 }
 
 // Fill the lists: one wave per uncovered walk; each of its ids that is
-// marked gets the walk appended to its list.
+// marked gets the walk appended to its list (ids outside the LDS filter of the
+// pool skip the bitmap).
 __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
 {
+    __shared__ uint32_t filt[kFilterWords];
     const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J) || J.st->plist_total == 0) return;  // uniform per block
+    filter_build(filt, J.pool, pool_size(J.st));
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
     for (uint64_t w = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
@@ -509,7 +539,7 @@ __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
         const uint32_t L = J.walk_len[w];
         for (uint32_t e = lane; e < L; e += kWave) {
             const uint32_t x = J.ids[o + e];
-            if (J.bitmap[x >> 5] & (1u << (x & 31))) {
+            if (filter_has(filt, x) && (J.bitmap[x >> 5] & (1u << (x & 31)))) {
                 const uint32_t i = J.pidx[x];
                 J.plist[J.pstart[i] + g_add(&J.pfill[i], 1u)] = static_cast<uint32_t>(w);
             }
@@ -574,6 +604,7 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
     __shared__ uint32_t pcnt[kPoolMax];  // exact counts of the pool's ids
     __shared__ uint32_t pids[kPoolMax];
     __shared__ uint32_t slot[kHash];
+    __shared__ uint32_t filt[kFilterWords];
     __shared__ uint32_t wlo, whi;        // list range of the chosen id
     const GJob J = view(jobs[blockIdx.x]);
     if (job_done(J)) return;  // uniform per block
@@ -586,7 +617,7 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
                              : st->tau;
     const bool ordered_zeros = ties && st->c_tie == 0 && st->pool_n == 0;
     for (uint32_t i = threadIdx.x; i < kHash; i += T) slot[i] = 0;
-    __syncthreads();
+    filter_build(filt, J.pool, P);  // (ends with a barrier)
     uint32_t pid[kPer], plo[kPer], phi[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -759,7 +790,7 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
                 }
 #pragma unroll
                 for (uint32_t u = 0; u < kSpan; ++u) {
-                    if (x[u] != id) {
+                    if (x[u] != id && filter_has(filt, x[u])) {
                         const int pos = pool_find(slot, pids, x[u]);
                         if (pos >= 0) atomicSub(&pcnt[pos], 1u);
                     }
@@ -922,7 +953,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     const unsigned hist_blocks =
         std::min(grid_for(max_S, T, base), std::max(1u, base / std::min<unsigned>(Q, 8)));
     const unsigned collect_blocks = grid_for(max_S, 256, cus * 4);
-    const unsigned fill_blocks = grid_for(max_walks * kWave, 256, cus * 32);
+    const unsigned fill_blocks = grid_for(max_walks * kWave, 256, cus * 4);
     std::vector<GreedyState> hs(Q);
     for (int group = 1;; group = std::min(group * 2, 8)) {
         for (int gen = 0; gen < group; ++gen) {
