@@ -152,24 +152,47 @@ __device__ __forceinline__ uint32_t guess_of(uint32_t r, uint32_t deg, uint32_t 
 }
 
 // Index of the live in-edge (the first with thr_hi > r) among the deg arcs at
-// base, given E = arcs[base + g]: g itself when E's interval holds r, else
-// bisection on the side E points to; E ends as the chosen arc.
+// base, given E = arcs[base + g] for the interpolation guess g (r < thr_last):
+// g itself when E's interval holds r; else a search of the side E points to
+// that keeps the exact thresholds at both ends of its bracket (each probe's
+// interval gives them) and interpolates within it for the first kInterp
+// probes (close to linear cumulative weights converge in two or three), then
+// bisects (bounded in the worst case).  E ends as the chosen arc.
 __device__ __forceinline__ uint32_t settle_arc(const GLOBAL ArcRec *arcs, uint32_t base, uint32_t deg,
-                                               uint32_t g, uint32_t r, ArcRec &E)
+                                               uint32_t thr_last, uint32_t g, uint32_t r, ArcRec &E)
 {
     if (E.thr_lo <= r && r < E.thr_hi) return g;
-    uint32_t lo, hi;  // answer in [lo, hi]
+    constexpr int kInterp = 3;
+    uint32_t lo, hi, tlo, thi;  // answer in [lo, hi]; thr_{lo-1} = tlo <= r < thi = thr_hi
     if (E.thr_hi <= r) {
         lo = g + 1;
         hi = deg - 1;
+        tlo = E.thr_hi;
+        thi = thr_last;
     } else {
         lo = 0;
         hi = g - 1;
+        tlo = 0;
+        thi = E.thr_lo;
     }
-    while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        if (arcs[base + mid].thr_hi > r) hi = mid;
-        else lo = mid + 1;
+    for (int step = 0; lo < hi; ++step) {
+        uint32_t m;
+        if (step < kInterp) {
+            const float f = static_cast<float>(r - tlo) * __builtin_amdgcn_rcpf(static_cast<float>(thi - tlo));
+            m = lo + __float2uint_rz(f * static_cast<float>(hi - lo + 1));
+            m = m > hi ? hi : m;
+        } else {
+            m = lo + ((hi - lo) >> 1);
+        }
+        E = load_arc(arcs + base + m);
+        if (E.thr_lo <= r && r < E.thr_hi) return m;
+        if (E.thr_hi <= r) {
+            lo = m + 1;
+            tlo = E.thr_hi;
+        } else {
+            hi = m - 1;
+            thi = E.thr_lo;
+        }
     }
     E = load_arc(arcs + base + lo);
     return lo;
@@ -253,7 +276,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
         // ---- stage 1: choose this iteration's draw and its one gather
         bool hit_now = false, do_eval = false, live = false, fetch_now = false, tag_only = false,
              starting = false;
-        uint32_t y = 0, r = 0, yoff = 0, ydeg = 0, g = 0;
+        uint32_t y = 0, r = 0, yoff = 0, ydeg = 0, ylast = 0, g = 0;
         NodeRec R = {0u, 0u, 0u, 0u};
         ArcRec E = {};
         ArcRec16 E16 = {};
@@ -325,6 +348,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 yoff = pside ? p_off : c_off;
                 ydeg = pside ? p_deg : c_deg;
                 const uint32_t ythr = pside ? p_thr : c_thr;
+                ylast = ythr;
                 r = static_cast<uint32_t>(word >> 32);
                 live = ydeg != 0 && r < ythr;
                 if (live) {
@@ -428,7 +452,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                     ud = E16.u_deg;
                     compact_node(ud, uq, ut);
                 } else {
-                    j = yoff + settle_arc(gp(static_cast<const ArcRec *>(A.arcs)), yoff, ydeg, g, r, E);
+                    j = yoff + settle_arc(gp(static_cast<const ArcRec *>(A.arcs)), yoff, ydeg, ylast, g, r, E);
                     u = E.row;
                     uo = E.u_off;
                     ud = E.u_deg;
