@@ -46,6 +46,17 @@ def rmat16(sia):
     g.close()
 
 
+@pytest.fixture(scope="module")
+def rmat16_general(sia):
+    """R-MAT s16 with random normalised weights: stored with 32-byte records."""
+    from paper_1702_05854_amd import workloads
+    wl = workloads.load("rmat22", device="cuda", scale=16, weights="normalized")
+    g = sia.Graph(wl.col_off, wl.row_idx, wl.w)
+    assert g.arc_bytes == 32
+    yield wl, g
+    g.close()
+
+
 def mix(n, count, seed, **kw):
     from paper_1702_05854_amd import workloads
     return workloads.query_mix(n, count, seed, **kw)
@@ -110,6 +121,16 @@ def test_mix_matches_solo_rmat16_more_queries_than_slots(sia, rmat16, greedy):
         assert_same(got[i], solo(sia, g, q), i)
         info = got[i]["info"]
         assert info["t_submit"] <= info["t_admit"] <= info["t_sampled"] <= info["t_done"]
+
+
+def test_mix_matches_solo_general_records(sia, rmat16_general):
+    """Batches on a graph with 32-byte records (per-slot tag bits in them)."""
+    wl, g = rmat16_general
+    qs = mix(wl.n, 20, 21, max_sources=1000, k_range=(10, 200), attempts_range=(10_000, 500_000))
+    got, st = serve(sia, g, qs, max_slots=8)
+    assert st["completed"] == len(qs) and st["failed"] == 0
+    for i, q in enumerate(qs):
+        assert_same(got[i], solo(sia, g, q), i)
 
 
 def test_graph_replays_match_eager(sia, rmat16):

@@ -115,6 +115,47 @@ def test_record_format_follows_weights(sia, perturb):
         assert np.array_equal(r["gains"], o["gains"]), (perturb, mode)
 
 
+@pytest.mark.parametrize("shape", ["geometric", "one_heavy", "zeros", "ramp"])
+def test_skewed_weights_search(sia, shape):
+    """Weight shapes far from equal (where the interpolated first guess and
+    the interpolation steps of the in-edge search miss, and it must bisect):
+    walks and answers equal the oracle's."""
+    rng = np.random.default_rng({"geometric": 1, "one_heavy": 2, "zeros": 3, "ramp": 4}[shape])
+    n = 4000
+    degs = rng.integers(0, 40, n)
+    degs[17] = 20_000
+    degs[18] = 300
+    col = np.zeros(n + 1, np.int64)
+    col[1:] = np.cumsum(degs)
+    m = int(col[-1])
+    row = rng.integers(0, n, m).astype(np.int32)
+    w = np.zeros(m, np.float32)
+    for v in range(n):
+        d = int(degs[v])
+        if not d:
+            continue
+        if shape == "geometric":
+            x = 0.7 ** np.arange(d)
+        elif shape == "one_heavy":
+            x = np.full(d, 1e-4)
+            x[rng.integers(d)] = 1.0
+        elif shape == "zeros":
+            x = rng.uniform(0, 1, d) * (rng.uniform(0, 1, d) < 0.3)
+            x[rng.integers(d)] += 0.5
+        else:
+            x = np.arange(1, d + 1, dtype=np.float64) ** 3
+        w[col[v]:col[v + 1]] = (x / x.sum() * rng.uniform(0.6, 1.0)).astype(np.float32)
+    g = sia.Graph(col, row, w)
+    assert g.arc_bytes == 32
+    og = cpu.Graph(col, row, w)
+    assert np.array_equal(g.thresholds(), og.thr)
+    src = sorted(rng.choice(n, size=8, replace=False).tolist())
+    for mode in ("edges", "nodes"):
+        got = sia.sample(g, src, mode, 60_000, 0, SEED)
+        ref = og.sample(np.array(src, np.int32), omode(mode), 60_000, 0, SEED)
+        assert_walks_equal(got, ref, (shape, mode))
+
+
 def test_quantize_exhaustive_all_fp32_in_unit_interval(sia):
     """Every fp32 value in [0, 1] (bit patterns 0 .. 0x3F800000) converts to
     the same integer on the device as in the oracle."""
