@@ -98,6 +98,9 @@ SourceTables build_source_tables(int64_t n, const int32_t *sources, int64_t n_so
         while (c < static_cast<uint64_t>(n_sources) && st.t[c] < lo) ++c;
         st.bucket[b] = static_cast<uint32_t>(c);
     }
+    // whole 16-byte blocks: the sampler reads both tables a block at a time
+    st.t.resize((st.t.size() + 3) & ~size_t(3), 0xFFFFFFFFu);
+    st.bucket.resize((st.bucket.size() + 3) & ~size_t(3), static_cast<uint32_t>(n_sources));
     return st;
 }
 

@@ -52,7 +52,8 @@ enum Phase : uint32_t {
     PH_MU_POS = 2,  // cycle found: advance the second pointer lambda steps
     PH_MU_A = 3,    // advance the first pointer
     PH_MU_B = 4,    // advance the second pointer, compare
-    PH_EMIT = 5     // kept walk: re-walk and write its ids
+    PH_EMIT = 5,    // kept walk: re-walk and write its ids
+    PH_SRC = 6      // start: the rank of the start among the sources, a 4-entry window at a time
 };
 
 struct WaveArgs {
@@ -139,6 +140,11 @@ __device__ __forceinline__ uint32_t quantum_index(uint32_t r, uint32_t q)
     while (static_cast<uint64_t>(j) * q > r) --j;
     while (static_cast<uint64_t>(j + 1) * q <= r) ++j;
     return j;
+}
+
+__device__ __forceinline__ uint32_t pick4(const u32x4 &v, uint32_t i)
+{
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
 }
 
 // Interpolation guess for the in-edge that is live for draw r at a node with
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
 
         // ---- stage 1: choose this iteration's draw and its one gather
         bool hit_now = false, do_eval = false, live = false, fetch_now = false, tag_only = false,
-             starting = false;
+             starting = false, in_src = false;
         uint32_t y = 0, r = 0, yoff = 0, ydeg = 0, ylast = 0, g = 0;
         NodeRec R = {0u, 0u, 0u, 0u};
         ArcRec E = {};
@@ -286,6 +292,8 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 fetch_now = true;
             } else if (phase == PH_START) {
                 starting = true;
+            } else if (phase == PH_SRC) {
+                in_src = true;
             } else {
                 do_eval = true;
                 if (phase == PH_DETECT) {
@@ -330,19 +338,9 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
         const uint64_t word = philox_word0(starting ? 0u : y, starting ? 1u : 0u, seed, a);
         if (active) {
             if (starting) {
-                const SlotDev &S = sl[slot];
-                const uint64_t idx = __umul64hi(word, S.n_ns);
-                const GLOBAL uint32_t *src_t = gp(S.src_t);
-                uint32_t c = gp(S.bucket)[idx >> S.bucket_shift];
-                while (c < S.n_src && src_t[c] <= idx) ++c;
-                x1 = static_cast<uint32_t>(idx + c);
-                cur = x1;
-                tort = x1;
-                power = 1;
-                lam = 0;
-                t = 0;
-                phase = PH_DETECT;
-                fetch = true;
+                // the start is the idx-th non-source: idx + #{i : t_i <= idx}, from
+                // the bucket block now and 4-entry windows of t in PH_SRC
+                x1 = static_cast<uint32_t>(__umul64hi(word, sl[slot].n_ns));  // idx (< n)
             } else if (do_eval) {
                 const bool pside = phase == PH_MU_A;
                 yoff = pside ? p_off : c_off;
@@ -352,18 +350,68 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 r = static_cast<uint32_t>(word >> 32);
                 live = ydeg != 0 && r < ythr;
                 if (live) {
-                    if constexpr (kCompact) {
-                        g = min(quantum_index(r, pside ? p_q : c_q), ydeg - 1u);
-                        E16 = load_arc16(gp(static_cast<const ArcRec16 *>(A.arcs)) + yoff + g);
-                    } else {
-                        g = guess_of(r, ydeg, ythr);
-                        E = load_arc(gp(static_cast<const ArcRec *>(A.arcs)) + yoff + g);
-                    }
+                    if constexpr (kCompact) g = min(quantum_index(r, pside ? p_q : c_q), ydeg - 1u);
+                    else g = guess_of(r, ydeg, ythr);
                 } else {
                     tag_only = phase == PH_DETECT && t > 0;
                 }
             }
-            if (fetch_now || tag_only) R = load_node(gp(A.nodes) + y);
+            // one 16-byte gather instruction per iteration: the node record (a
+            // walk's first node, or the tag of a node without a live edge) or
+            // the selected in-edge record (its first half for 32-byte records)
+            // (or, for a starting walk, a 16-byte block of its query's bucket or t table)
+            const GLOBAL u32x4 *src = nullptr;
+            if (fetch_now || tag_only) {
+                src = reinterpret_cast<const GLOBAL u32x4 *>(gp(A.nodes) + y);
+            } else if (live) {
+                if constexpr (kCompact)
+                    src = reinterpret_cast<const GLOBAL u32x4 *>(gp(static_cast<const ArcRec16 *>(A.arcs)) + yoff + g);
+                else
+                    src = reinterpret_cast<const GLOBAL u32x4 *>(gp(static_cast<const ArcRec *>(A.arcs)) + yoff + g);
+            } else if (starting) {
+                src = reinterpret_cast<const GLOBAL u32x4 *>(gp(sl[slot].bucket) +
+                                                              ((x1 >> sl[slot].bucket_shift) & ~3u));
+            } else if (in_src) {
+                src = reinterpret_cast<const GLOBAL u32x4 *>(gp(sl[slot].src_t) + (cnt & ~3u));
+            }
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (src) v = *src;
+            if (fetch_now || tag_only) {
+                R = NodeRec{v.x, v.y, v.z, v.w};
+            } else if (live) {
+                if constexpr (kCompact) {
+                    E16 = ArcRec16{v.x, v.y, v.z, v.w};
+                } else {
+                    const u32x4 h = src[1];
+                    E = ArcRec{v.x, v.y, v.z, v.w, h.x, h.y, h.z, h.w};
+                }
+            } else if (starting || in_src) {
+                const SlotDev &D = sl[slot];
+                uint32_t c;
+                bool more = false;  // the next window of t is needed
+                if (starting) {
+                    c = pick4(v, (x1 >> D.bucket_shift) & 3u);
+                    more = c < D.n_src;
+                } else {
+                    c = cnt;
+                    const uint32_t end = (c | 3u) + 1u;
+                    while (c < end && c < D.n_src && pick4(v, c & 3u) <= x1) ++c;
+                    more = c == end && c < D.n_src;
+                }
+                if (more) {
+                    cnt = c;
+                    phase = PH_SRC;
+                } else {  // start at x1 = idx + c: fetch its record next
+                    x1 += c;
+                    cur = x1;
+                    tort = x1;
+                    power = 1;
+                    lam = 0;
+                    t = 0;
+                    phase = PH_DETECT;
+                    fetch = true;
+                }
+            }
             if (do_eval && phase == PH_DETECT && t > 0) {
                 const uint32_t tag = live ? (kCompact ? E16.head_tag : E.head_tag) : R.tag;
                 if (tag & tag_mask) {  // reached a source: kept walk
@@ -651,12 +699,12 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
     const uint32_t mask = 1u << kSoloBit;
 
     ws.src_sorted.ensure(sizeof(int32_t) * n_src);
-    ws.src_t.ensure(sizeof(uint32_t) * n_src);
+    ws.src_t.ensure(sizeof(uint32_t) * st.t.size());
     ws.bucket.ensure(sizeof(uint32_t) * st.bucket.size());
     ws.counters.ensure(sizeof(uint64_t) * ST_COUNT + sizeof(SlotDev) + sizeof(WaveTable) + 256);
     SIA_HIP(hipMemcpyAsync(ws.src_sorted.ptr, st.sorted.data(), sizeof(int32_t) * n_src,
                            hipMemcpyHostToDevice, s));
-    SIA_HIP(hipMemcpyAsync(ws.src_t.ptr, st.t.data(), sizeof(uint32_t) * n_src,
+    SIA_HIP(hipMemcpyAsync(ws.src_t.ptr, st.t.data(), sizeof(uint32_t) * st.t.size(),
                            hipMemcpyHostToDevice, s));
     SIA_HIP(hipMemcpyAsync(ws.bucket.ptr, st.bucket.data(), sizeof(uint32_t) * st.bucket.size(),
                            hipMemcpyHostToDevice, s));

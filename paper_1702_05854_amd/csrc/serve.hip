@@ -284,10 +284,10 @@ struct sia_batch {
         const SourceTables &st = sl.t->st;
         const size_t ns = st.sorted.size();
         sl.src_sorted.ensure(4 * ns);
-        sl.src_t.ensure(4 * ns);
+        sl.src_t.ensure(4 * st.t.size());
         sl.bucket.ensure(4 * st.bucket.size());
         SIA_HIP(hipMemcpyAsync(sl.src_sorted.ptr, st.sorted.data(), 4 * ns, hipMemcpyHostToDevice, s_sample));
-        SIA_HIP(hipMemcpyAsync(sl.src_t.ptr, st.t.data(), 4 * ns, hipMemcpyHostToDevice, s_sample));
+        SIA_HIP(hipMemcpyAsync(sl.src_t.ptr, st.t.data(), 4 * st.t.size(), hipMemcpyHostToDevice, s_sample));
         SIA_HIP(hipMemcpyAsync(sl.bucket.ptr, st.bucket.data(), 4 * st.bucket.size(), hipMemcpyHostToDevice,
                                s_sample));
         tag_sources(g, sl.src_sorted.as<int32_t>(), static_cast<uint32_t>(ns), sl.tag_mask, true, s_sample);
