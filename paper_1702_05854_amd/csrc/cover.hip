@@ -953,7 +953,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     const unsigned hist_blocks =
         std::min(grid_for(max_S, T, base), std::max(1u, base / std::min<unsigned>(Q, 8)));
     const unsigned collect_blocks = grid_for(max_S, 256, cus * 4);
-    const unsigned fill_blocks = grid_for(max_walks * kWave, 256, cus * 4);
+    const unsigned fill_blocks = grid_for(max_walks * kWave, 256, cus * 16);
     std::vector<GreedyState> hs(Q);
     for (int group = 1;; group = std::min(group * 2, 8)) {
         for (int gen = 0; gen < group; ++gen) {
