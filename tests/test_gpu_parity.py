@@ -395,6 +395,37 @@ def test_solve_edge_cases(sia):
     assert got["stats"]["dead_ends"] == 1000 and got["selected"].tolist() == [0, 1]
 
 
+@pytest.mark.parametrize("layout", ["dense", "runs", "ends"])
+def test_start_ranks_with_dense_sources(sia, layout):
+    """The start of an attempt is the idx-th non-source; its rank among the
+    sources is read a bucket block and then 4-entry windows at a time.  Source
+    sets with long runs of consecutive ids, almost every node a source, and
+    sources at both ends of the id range: walks and answers equal the oracle's."""
+    from paper_1702_05854_amd import workloads
+    wl = workloads.load("er1k")
+    col, row, w = wl.host()
+    n = wl.n
+    rng = np.random.default_rng(9)
+    if layout == "dense":  # all but 7 nodes
+        keep = set(rng.choice(n, size=7, replace=False).tolist())
+        src = [v for v in range(n) if v not in keep]
+    elif layout == "runs":  # a few long runs of consecutive ids
+        src = list(range(0, 90)) + list(range(300, 555)) + list(range(700, 703)) + list(range(960, 1000))
+    else:  # the ends of the id range and a few more
+        src = [0, 1, 2, n - 3, n - 2, n - 1, 500]
+    g = sia.Graph(col, row, w)
+    og = cpu.Graph(col, row, w)
+    s = np.array(sorted(src), np.int32)
+    for mode in ("edges", "nodes"):
+        got = sia.sample(g, s, mode, 30_000, 777, SEED)
+        ref = og.sample(s, omode(mode), 30_000, 777, SEED)
+        assert_walks_equal(got, ref, (layout, mode))
+        r = sia.solve(g, s, mode, 10, 30_000, 777, SEED)
+        o = cpu.solve(og, s, omode(mode), 10, 30_000, 777, SEED)
+        assert np.array_equal(r["selected"], o["selected"]), (layout, mode)
+        assert np.array_equal(r["gains"], o["gains"]), (layout, mode)
+
+
 def test_probe_gather_measures(sia):
     ind, ms_i = sia.probe_gather(64 << 20, 64, dependent=False)
     dep, ms_d = sia.probe_gather(64 << 20, 64, dependent=True)
