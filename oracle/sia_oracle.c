@@ -18,7 +18,7 @@
  * (arXiv 1702.05854).  Passages are cited by section / definition /
  * algorithm / equation.
  *
- * Readings where the paper is silent or garbled (all listed in the design doc):
+ * Readings where the paper is silent or garbled:
  *  R1  Live-edge selection is discretised: weight w_j becomes the integer
  *      q_j = round-half-even(w_j * 2^32); thresholds are the per-column
  *      running sums clamped to 2^32-1; the draw r (32 bits) selects the

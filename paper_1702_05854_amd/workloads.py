@@ -203,7 +203,7 @@ class Workload:
 
 RMAT_ABCD = (0.57, 0.19, 0.19, 0.05)
 
-CONFIGS = {
+WORKLOAD_SPECS = {
     # name: (generator description, sources, attempts, k, modes)
     "er1k": dict(kind="er", n=1000, m=8000, gseed=1, weights="inv_indeg", n_src=10, sseed=101,
                  n_attempts=100_000, k=10, modes=("edges",)),
@@ -247,7 +247,7 @@ def build_graph(spec, device="cpu"):
 
 
 def load(name, device="cpu", **override):
-    spec = dict(CONFIGS[name])
+    spec = dict(WORKLOAD_SPECS[name])
     spec.update(override)
     n, col_off, row_idx, w = build_graph(spec, device)
     sources = pick_sources(n, spec["n_src"], spec["sseed"])
