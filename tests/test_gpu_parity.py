@@ -426,6 +426,30 @@ def test_start_ranks_with_dense_sources(sia, layout):
         assert np.array_equal(r["gains"], o["gains"]), (layout, mode)
 
 
+def test_golden_three_node_law(sia):
+    """The hand-derived law of tests/golden/three_node_cycle.json: the HIP
+    sampler equals the oracle walk for walk, and its outcome rates match the
+    law within sampling error."""
+    import json
+    import os
+    from fractions import Fraction
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "three_node_cycle.json")) as f:
+        fx = json.load(f)
+    edges = [(int(u), int(v), float(w)) for u, v, w in fx["graph"]["edges_u_v_w"]]
+    col, row, w = csc_from_edges(fx["graph"]["n"], edges)
+    g = sia.Graph(col, row, w)
+    og = cpu.Graph(col, row, w)
+    src = np.array(fx["sources"], np.int32)
+    N = 1_000_000
+    for mode in ("edges", "nodes"):
+        got = sia.sample(g, src, mode, N, 0, SEED)
+        ref = og.sample(src, omode(mode), N, 0, SEED)
+        assert_walks_equal(got, ref, mode)
+        for k, c in (("hit", "hits"), ("dead_end", "dead_ends"), ("cycle", "cycles")):
+            p = float(Fraction(fx["quantized"][k]))
+            assert abs(got.stats[c] - N * p) < 5 * np.sqrt(N * p * (1 - p)) + 1, (mode, k)
+
+
 def test_probe_gather_measures(sia):
     ind, ms_i = sia.probe_gather(64 << 20, 64, dependent=False)
     dep, ms_d = sia.probe_gather(64 << 20, 64, dependent=True)
