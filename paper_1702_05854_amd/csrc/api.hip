@@ -91,12 +91,15 @@ SourceTables build_source_tables(int64_t n, const int32_t *sources, int64_t n_so
     while (((st.n_ns + (uint64_t(1) << shift) - 1) >> shift) > kMaxBuckets) ++shift;
     st.shift = shift;
     const uint64_t nb = ((st.n_ns + (uint64_t(1) << shift) - 1) >> shift) + 1;
-    st.bucket.resize(nb);
+    // pairs (c_b, t_{c_b}): the count below the bucket and the next t at or
+    // after its start (0xFFFFFFFF past the last source)
+    st.bucket.resize(2 * nb);
     uint64_t c = 0;
     for (uint64_t b = 0; b < nb; ++b) {
         const uint64_t lo = b << shift;
         while (c < static_cast<uint64_t>(n_sources) && st.t[c] < lo) ++c;
-        st.bucket[b] = static_cast<uint32_t>(c);
+        st.bucket[2 * b] = static_cast<uint32_t>(c);
+        st.bucket[2 * b + 1] = c < static_cast<uint64_t>(n_sources) ? st.t[c] : 0xFFFFFFFFu;
     }
     // whole 16-byte blocks: the sampler reads both tables a block at a time
     st.t.resize((st.t.size() + 3) & ~size_t(3), 0xFFFFFFFFu);

@@ -122,7 +122,7 @@ namespace sia {
 struct SourceTables {
     std::vector<int32_t> sorted;   // ascending sources
     std::vector<uint32_t> t;       // t_i = s_i - i (non-sources below s_i)
-    std::vector<uint32_t> bucket;  // bucket[b] = #{i : t_i < b << shift}
+    std::vector<uint32_t> bucket;  // pairs: [2b] = #{i : t_i < b << shift}, [2b+1] = t at that count
     // (t and bucket are padded to whole 16-byte blocks: 0xFFFFFFFF, |X|)
     uint32_t shift = 0;
     uint64_t n_ns = 0;

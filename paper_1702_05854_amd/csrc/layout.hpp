@@ -97,7 +97,7 @@ struct SlotDev {
     uint64_t attempt_base;   // attempt id of the query's local attempt 0
     uint64_t n_ns;           // non-sources
     const uint32_t *src_t;   // t_i = s_i - i over the sorted sources
-    const uint32_t *bucket;  // bucket[b] = #{i : t_i < b << bucket_shift}
+    const uint32_t *bucket;  // pairs: [2b] = #{i : t_i < b << bucket_shift}, [2b+1] = t at that count
     uint32_t n_src;
     uint32_t bucket_shift;
     uint32_t tag_mask;       // source-tag bit of this query

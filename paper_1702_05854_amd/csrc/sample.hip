@@ -339,7 +339,8 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
         if (active) {
             if (starting) {
                 // the start is the idx-th non-source: idx + #{i : t_i <= idx}, from
-                // the bucket block now and 4-entry windows of t in PH_SRC
+                // the bucket block now (done when the next t exceeds idx) and
+                // 4-entry windows of t in PH_SRC
                 x1 = static_cast<uint32_t>(__umul64hi(word, sl[slot].n_ns));  // idx (< n)
             } else if (do_eval) {
                 const bool pside = phase == PH_MU_A;
@@ -370,7 +371,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                     src = reinterpret_cast<const GLOBAL u32x4 *>(gp(static_cast<const ArcRec *>(A.arcs)) + yoff + g);
             } else if (starting) {
                 src = reinterpret_cast<const GLOBAL u32x4 *>(gp(sl[slot].bucket) +
-                                                              ((x1 >> sl[slot].bucket_shift) & ~3u));
+                                                              ((2u * (x1 >> sl[slot].bucket_shift)) & ~3u));
             } else if (in_src) {
                 src = reinterpret_cast<const GLOBAL u32x4 *>(gp(sl[slot].src_t) + (cnt & ~3u));
             }
@@ -389,9 +390,10 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 const SlotDev &D = sl[slot];
                 uint32_t c;
                 bool more = false;  // the next window of t is needed
-                if (starting) {
-                    c = pick4(v, (x1 >> D.bucket_shift) & 3u);
-                    more = c < D.n_src;
+                if (starting) {  // the bucket's pair: the count below it, the next t
+                    const uint32_t k = (2u * (x1 >> D.bucket_shift)) & 3u;
+                    c = pick4(v, k);
+                    more = c < D.n_src && pick4(v, k + 1u) <= x1;
                 } else {
                     c = cnt;
                     const uint32_t end = (c | 3u) + 1u;
