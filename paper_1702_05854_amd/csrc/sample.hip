@@ -24,16 +24,17 @@
 // counter in chunks and find the slot of each attempt in a small table kept
 // in LDS; kept walks are appended with one pair of atomics per slot per
 // wave.  Every iteration a lane computes one Philox block (its start draw,
-// or the draw of the node it evaluates) and gathers at most one record: the
-// in-edge record the draw selects, which says whether the evaluated node is a
-// source and carries the next node's offset and degree -- so a step costs one
-// random line.  With 32-byte records (any weights) the record sits at the
-// interpolated position of the draw and its threshold interval certifies the
-// choice (else bisection); with 16-byte records (w = 1/d_in everywhere) the
-// position is floor(r / q(d)) exactly and needs no certificate.  Node records
-// are read only where a walk (re)starts and, for their source tag, at nodes
-// without a live edge.  A single query is a wave of one slot, so every call
-// goes through this kernel.
+// or the draw of the node it evaluates) and issues at most one 16-byte gather:
+// mostly the in-edge record the draw selects, which says whether the evaluated
+// node is a source and carries the next node's offset and degree -- so a step
+// costs one random line.  With 32-byte records (any weights) the record sits
+// at the interpolated position of the draw and its threshold interval
+// certifies the choice (else a bracketed search); with 16-byte records
+// (w = 1/d_in everywhere) the position is floor(r / q(d)) exactly and needs
+// no certificate.  Node records are read only where a walk (re)starts and,
+// for their source tag, at nodes without a live edge; a starting walk reads
+// its rank among the sources from its query's tables a block at a time.  A
+// single query is a wave of one slot, so every call goes through this kernel.
 #include "common.hpp"
 #include "philox.hpp"
 
@@ -47,7 +48,7 @@ namespace {
 constexpr int kWave = 64;
 
 enum Phase : uint32_t {
-    PH_START = 0,   // compute the start node
+    PH_START = 0,   // start draw; its bucket pair of the start tables
     PH_DETECT = 1,  // walk with Brent's cycle detection
     PH_MU_POS = 2,  // cycle found: advance the second pointer lambda steps
     PH_MU_A = 3,    // advance the first pointer
@@ -79,17 +80,6 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
-{
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), d, kWave);
-        uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), d, kWave);
-        v += (static_cast<uint64_t>(hi) << 32) | lo;
-    }
-    return v;
-}
-
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane)
 {
 #pragma unroll
@@ -102,24 +92,12 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane)
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Whole-record loads through global pointers (two and one 16-byte loads).
+// Whole 32-byte record load through a global pointer (two 16-byte loads).
 __device__ __forceinline__ ArcRec load_arc(const GLOBAL ArcRec *p)
 {
     const GLOBAL u32x4 *q = reinterpret_cast<const GLOBAL u32x4 *>(p);
     const u32x4 lo = q[0], hi = q[1];
     return ArcRec{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-}
-
-__device__ __forceinline__ ArcRec16 load_arc16(const GLOBAL ArcRec16 *p)
-{
-    const u32x4 v = *reinterpret_cast<const GLOBAL u32x4 *>(p);
-    return ArcRec16{v.x, v.y, v.z, v.w};
-}
-
-__device__ __forceinline__ NodeRec load_node(const GLOBAL NodeRec *p)
-{
-    const u32x4 v = *reinterpret_cast<const GLOBAL u32x4 *>(p);
-    return NodeRec{v.x, v.y, v.z, v.w};
 }
 
 // Compact format: the quantum of a node with in-degree d (>= 1) kept in 32
