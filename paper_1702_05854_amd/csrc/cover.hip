@@ -548,11 +548,6 @@ __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
 }
 
 // ---------------------------------------------------------------- lazy rounds
-__device__ __forceinline__ uint32_t load_count(const GLOBAL uint32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ uint32_t hash_of(uint32_t x) { return (x * 2654435761u) >> (32 - kHashBits); }
 
 // pool position of id x (slot holds position + 1), or -1 if x is not in the pool
