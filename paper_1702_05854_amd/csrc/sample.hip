@@ -353,8 +353,16 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
             } else if (in_src) {
                 src = reinterpret_cast<const GLOBAL u32x4 *>(gp(sl[slot].src_t) + (cnt & ~3u));
             }
+            // compact records are loaded non-temporally: the line is not read
+            // again soon, and keeping it out of the caches' recent set leaves
+            // them to the hot small tables (6% faster on rmat24).  A 32-byte
+            // record's line is read again at once (its second half, search
+            // probes), so it is cached normally (non-temporal: 10% slower).
             u32x4 v = {0u, 0u, 0u, 0u};
-            if (src) v = *src;
+            if (src) {
+                if constexpr (kCompact) v = __builtin_nontemporal_load(src);
+                else v = *src;
+            }
             if (fetch_now || tag_only) {
                 R = NodeRec{v.x, v.y, v.z, v.w};
             } else if (live) {
