@@ -230,8 +230,7 @@ sia_status sia_sample(const sia_graph *cg, int mode, const int32_t *sources, int
         DeviceScope ds(g->device);
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
         const SourceTables st = build_source_tables(g->n, sources, n_sources);
-        const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, false,
-                                           false);
+        const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, false);
 
         std::vector<uint64_t> att(r.walks), off(r.walks);
         std::vector<uint32_t> len(r.walks), ids(r.ids);
@@ -333,11 +332,13 @@ sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int6
             SIA_HIP(hipEventRecord(e0, s));
         }
         const SourceTables st = build_source_tables(g->n, sources, n_sources);
-        const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s,
-                                           timing != 0, true);
+        // counts are taken by the greedy's counting pass: atomics fused into the
+        // sampler's emission cost it 15% on rmat24 (their random lines compete
+        // with its gathers)
+        const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, timing != 0);
         const int64_t id_space = mode == SIA_EDGES ? g->m : g->n;
         const GreedyResult gr = run_greedy(g->ws, id_space, r.walks, r.ids, k, selected, gains, s,
-                                           timing != 0, true);
+                                           timing != 0, false);
         float ms_total = 0.f;
         if (timing) {
             SIA_HIP(hipEventRecord(e1, s));

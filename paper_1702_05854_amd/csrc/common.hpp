@@ -169,11 +169,9 @@ struct SampleResult {
 
 // A single query (slot bit 31): upload sources, tag them, run one wave
 // (rerunning with larger buffers if the output did not fit), untag.
-// Results stay in g->ws.  With count_ids, ws.cnt[id_space] receives the
-// coverage count of every id.
+// Results stay in g->ws; coverage counts are taken by the greedy (k_count).
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
-                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing,
-                         bool count_ids);
+                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing);
 
 struct GreedyResult {
     float ms_count = 0.f, ms_greedy = 0.f;

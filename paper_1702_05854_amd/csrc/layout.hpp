@@ -106,7 +106,6 @@ struct SlotDev {
     uint64_t *walk_off;
     uint32_t *walk_len;
     uint32_t *ids;
-    uint32_t *cnt;           // coverage counts (nullptr: not counted)
     uint64_t walk_cap;
     uint64_t id_cap;
     uint64_t *counters;      // StatSlot entries

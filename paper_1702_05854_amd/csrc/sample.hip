@@ -15,8 +15,8 @@
 //    (the paper's heuristics had false negatives because its draws depended
 //    on the step, not the node).
 //  * A kept walk is re-walked to emit its ids, so no per-lane path storage
-//    is needed either; coverage counts are incremented as the ids are
-//    written.
+//    is needed either.  Coverage counts are taken afterwards, in one pass
+//    over the written ids (atomics here would compete with the gathers).
 //
 // One launch samples a wave: attempt ranges of up to 31 queries ("slots",
 // each with its own sources, seed, mode and output buffers) laid end to end.
@@ -457,12 +457,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                     gp(S.walk_off)[widx] = ioff;
                     gp(S.walk_len)[widx] = len;
                     out_pos = ioff;
-                    if (mode == SIA_NODES) {
-                        gp(S.ids)[out_pos++] = x1;
-                        if (S.cnt)
-                            __hip_atomic_fetch_add(gp(S.cnt) + x1, 1u, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                    }
+                    if (mode == SIA_NODES) gp(S.ids)[out_pos++] = x1;
                     phase = PH_EMIT;
                     cur = x1;
                     fetch = true;
@@ -551,8 +546,6 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 const SlotDev &S = sl[slot];
                 const uint32_t id = (mode == SIA_EDGES) ? j : u;
                 gp(S.ids)[out_pos++] = id;
-                if (S.cnt)
-                    __hip_atomic_fetch_add(gp(S.cnt) + id, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 cur = u;
                 if (--cnt == 0) done = true;
             }
@@ -678,12 +671,10 @@ void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
 }
 
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
-                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing,
-                         bool count_ids)
+                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing)
 {
     Workspace &ws = g->ws;
     const uint32_t n_src = static_cast<uint32_t>(st.sorted.size());
-    const uint64_t id_space = mode == SIA_EDGES ? static_cast<uint64_t>(g->m) : static_cast<uint64_t>(g->n);
     const uint32_t mask = 1u << kSoloBit;
 
     ws.src_sorted.ensure(sizeof(int32_t) * n_src);
@@ -697,7 +688,6 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
     SIA_HIP(hipMemcpyAsync(ws.bucket.ptr, st.bucket.data(), sizeof(uint32_t) * st.bucket.size(),
                            hipMemcpyHostToDevice, s));
     tag_sources(g, ws.src_sorted.as<int32_t>(), n_src, mask, true, s);
-    if (count_ids) ws.cnt.ensure(sizeof(uint32_t) * std::max<uint64_t>(id_space, 1));
     char *cbase = ws.counters.as<char>();
     uint64_t *d_counters = reinterpret_cast<uint64_t *>(cbase);
     SlotDev *d_slot = reinterpret_cast<SlotDev *>(cbase + sizeof(uint64_t) * ST_COUNT);
@@ -717,7 +707,6 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
         ws.walk_len.ensure(sizeof(uint32_t) * ws.walk_cap);
         ws.ids.ensure(sizeof(uint32_t) * ws.id_cap);
         SIA_HIP(hipMemsetAsync(d_counters, 0, sizeof(uint64_t) * ST_COUNT, s));
-        if (count_ids) SIA_HIP(hipMemsetAsync(ws.cnt.ptr, 0, sizeof(uint32_t) * id_space, s));
 
         SlotDev S{};
         S.seed = seed;
@@ -733,7 +722,6 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
         S.walk_off = ws.walk_off.as<uint64_t>();
         S.walk_len = ws.walk_len.as<uint32_t>();
         S.ids = ws.ids.as<uint32_t>();
-        S.cnt = count_ids ? ws.cnt.as<uint32_t>() : nullptr;
         S.walk_cap = ws.walk_cap;
         S.id_cap = ws.id_cap;
         S.counters = d_counters;

@@ -322,7 +322,6 @@ struct sia_batch {
         S.walk_off = sl.walk_off.as<uint64_t>();
         S.walk_len = sl.walk_len.as<uint32_t>();
         S.ids = sl.ids.as<uint32_t>();
-        S.cnt = nullptr;  // counted by the greedy
         S.walk_cap = sl.walk_cap;
         S.id_cap = sl.id_cap;
         S.counters = d_ctr.as<uint64_t>() + static_cast<size_t>(i) * ST_COUNT;
