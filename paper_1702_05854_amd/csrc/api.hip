@@ -307,7 +307,7 @@ sia_status sia_greedy(int64_t id_space, const uint64_t *walk_off, const uint32_t
             SIA_HIP(hipMemcpyAsync(ws.walk_len.ptr, len.data(), 4 * n_walks, hipMemcpyHostToDevice, s));
         }
         if (n_ids) SIA_HIP(hipMemcpyAsync(ws.ids.ptr, ids, 4 * n_ids, hipMemcpyHostToDevice, s));
-        run_greedy(ws, id_space, n_walks, n_ids, k, selected, gains, s, false, false);
+        run_greedy(ws, id_space, n_walks, n_ids, k, selected, gains, s, false);
     });
 }
 
@@ -338,7 +338,7 @@ sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int6
         const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, timing != 0);
         const int64_t id_space = mode == SIA_EDGES ? g->m : g->n;
         const GreedyResult gr = run_greedy(g->ws, id_space, r.walks, r.ids, k, selected, gains, s,
-                                           timing != 0, false);
+                                           timing != 0);
         float ms_total = 0.f;
         if (timing) {
             SIA_HIP(hipEventRecord(e1, s));

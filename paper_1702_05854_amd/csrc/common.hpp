@@ -169,7 +169,7 @@ struct SampleResult {
 
 // A single query (slot bit 31): upload sources, tag them, run one wave
 // (rerunning with larger buffers if the output did not fit), untag.
-// Results stay in g->ws; coverage counts are taken by the greedy (k_count).
+// Results stay in g->ws; coverage counts are taken by the greedy.
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
                          uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing);
 
@@ -186,8 +186,7 @@ struct GreedyInput {
     const uint32_t *ids = nullptr;
     uint64_t id_space = 0, n_walks = 0, n_ids = 0;
     int64_t k = 0;
-    uint32_t *cnt = nullptr;    // id_space coverage counts (device)
-    bool counts_ready = false;  // cnt already holds the counts; else counted here
+    uint32_t *cnt = nullptr;    // id_space coverage counts (device), written here
     void *scratch = nullptr;
     int64_t *selected = nullptr;  // k entries each; host memory
     uint64_t *gains = nullptr;
@@ -205,10 +204,10 @@ void run_greedy_jobs(std::vector<GreedyInput> &jobs, void *d_job_table, hipStrea
                      GreedyResult *res, unsigned hist_base = 0);
 
 // A single job over the walks held in ws (walk_off / walk_len / ids, n_walks
-// walks, n_ids ids).  counts_ready: ws.cnt already holds the coverage counts.
+// walks, n_ids ids); the counts go to ws.cnt.
 GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
                         int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s,
-                        bool timing, bool counts_ready);
+                        bool timing);
 
 // Ingest: host structure checks (no device needed) and the device kernels.
 void host_check_structure(int64_t n, int64_t m, const int64_t *col_off, const int32_t *row_idx);

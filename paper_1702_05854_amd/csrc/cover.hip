@@ -52,6 +52,14 @@ constexpr uint32_t kPoolMax = 8192;        // the lazy rounds keep the pool in L
 constexpr uint32_t kHashBits = 14;         // id -> pool position hash, load <= 1/2
 constexpr uint32_t kHash = 1u << kHashBits;
 constexpr uint32_t kFilterBits = 17;       // LDS bit filter of pool ids (false positives <= 1/16)
+// Coverage counting by id ranges (k_bin_sort, k_bin_count): bins of 2^rbits
+// ids, at most kCountBins of them; up to kCountTilesMax tiles of the walk ids.
+constexpr uint32_t kCountBinsLog = 14;
+constexpr uint32_t kCountBins = 1u << kCountBinsLog;
+constexpr uint32_t kCountSpanLog = 14;  // LDS counters of one counting pass
+constexpr uint32_t kCountSpan = 1u << kCountSpanLog;
+constexpr uint32_t kCountTilesMax = 512;
+constexpr uint64_t kCountTileMin = 32768;
 constexpr uint32_t kFilterWords = (1u << kFilterBits) / 32;
 static_assert(kHash >= 2 * kPoolMax, "pool hash load factor");
 
@@ -94,8 +102,12 @@ struct GreedyJob {
     uint64_t n_walks;
     uint64_t n_ids;
     int64_t k;
-    uint32_t need_count;
-    uint32_t pad;
+    uint32_t c_rbits;   // counting: ids per bin = 2^c_rbits
+    uint32_t c_bins;    // counting: bins over [0, S)
+    uint32_t c_tiles;   // counting: tiles of the walk ids
+    uint32_t c_parts;   // counting: workgroups per bin (> 1: they add into cnt)
+    uint64_t c_tile_len;
+    uint32_t *coffs;    // c_tiles x (c_bins + 1): where each tile's bins start in plist
     int64_t *sel;       // k
     uint64_t *gain;     // k
     uint32_t *hist;     // kBins
@@ -120,7 +132,9 @@ struct GJob {
     const GLOBAL uint32_t *ids;
     uint64_t S, n_walks, n_ids;
     int64_t k;
-    uint32_t need_count;
+    uint32_t c_rbits, c_bins, c_tiles, c_parts;
+    uint64_t c_tile_len;
+    GLOBAL uint32_t *coffs;
     GLOBAL int64_t *sel;
     GLOBAL uint64_t *gain;
     GLOBAL uint32_t *hist;
@@ -147,7 +161,12 @@ __device__ __forceinline__ GJob view(const GreedyJob &j)
     J.n_walks = j.n_walks;
     J.n_ids = j.n_ids;
     J.k = j.k;
-    J.need_count = j.need_count;
+    J.c_rbits = j.c_rbits;
+    J.c_bins = j.c_bins;
+    J.c_tiles = j.c_tiles;
+    J.c_parts = j.c_parts;
+    J.c_tile_len = j.c_tile_len;
+    J.coffs = gp(j.coffs);
     J.sel = gp(j.sel);
     J.gain = gp(j.gain);
     J.hist = gp(j.hist);
@@ -265,16 +284,16 @@ __device__ void scan_tiles_256(GLOBAL uint32_t *tiles, uint64_t n)
 }
 
 // ---------------------------------------------------------------- set-up
-// Zero the per-job state, histogram, covered flags and (when the job counts
-// here) the counts.  A kernel rather than memsets, so a captured graph holds
-// no memset nodes.
+// Zero the per-job state, histogram, covered flags and, when the counting
+// pass adds partial counts, the counts (else it writes every count).  A
+// kernel rather than memsets, so a captured graph holds no memset nodes.
 __global__ void k_init(const GreedyJob *jobs)
 {
     const GJob J = view(jobs[blockIdx.y]);
     const uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     for (uint64_t i = t; i < J.n_walks; i += stride) J.covered[i] = 0;
-    if (J.need_count)
+    if (J.c_parts > 1)
         for (uint64_t i = t; i < J.S; i += stride) J.cnt[i] = 0;
     for (uint64_t i = t; i < kBins; i += stride) J.hist[i] = 0;
     for (uint64_t i = t; i < (J.S + 31) / 32; i += stride) J.bitmap[i] = 0;
@@ -284,13 +303,135 @@ __global__ void k_init(const GreedyJob *jobs)
     }
 }
 
-__global__ void k_count(const GreedyJob *jobs)
+// ---------------------------------------------------------------- coverage counts
+// cnt[id] = number of kept walks holding id (the initial Cov of each id),
+// taken without global atomics: random atomics over an id space of 10^8 ids
+// and more miss every cache.  The id space is cut into bins of 2^rbits ids.
+// k_bin_sort: each tile of the walk ids is histogrammed by bin in LDS and
+// scattered bin by bin into plist (unused until the first pool is filled);
+// coffs records where each of the tile's bins starts.  k_bin_count: one
+// workgroup per bin gathers that bin's segment of every tile, counts in LDS
+// (kCountSpan ids per pass) and writes the count of every id of the bin, so
+// cnt needs no clearing.  When the bins are too few to fill the GPU, each
+// bin's tiles are split among c_parts workgroups that add their counts.
+
+template <int T>
+__global__ __launch_bounds__(T) void k_bin_sort(const GreedyJob *jobs)
 {
+    constexpr int U = 8;                        // loads in flight per lane
+    constexpr uint32_t kPer = kCountBins / T;   // bins each thread scans
+    static_assert(kCountBins % T == 0, "bins per thread");
+    __shared__ uint32_t h[kCountBins];
+    __shared__ uint32_t sh[T / kWave];
     const GJob J = view(jobs[blockIdx.y]);
-    if (!J.need_count) return;
-    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (; i < J.n_ids; i += stride) g_add(&J.cnt[J.ids[i]], 1u);
+    const uint32_t w = blockIdx.x;
+    if (w >= J.c_tiles) return;  // uniform per block
+    const uint64_t lo = min(J.n_ids, w * J.c_tile_len), hi = min(J.n_ids, lo + J.c_tile_len);
+    const uint32_t B = J.c_bins, rb = J.c_rbits;
+    for (uint32_t b = threadIdx.x; b < B; b += T) h[b] = 0;
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * T) {
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = i + u * T < hi ? J.ids[i + u * T] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * T < hi) atomicAdd(&h[v[u] >> rb], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of h[0 .. B) in place; thread t holds bins [t*kPer, (t+1)*kPer)
+    const uint32_t b0 = threadIdx.x * kPer;
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < kPer; ++r) sum += b0 + r < B ? h[b0 + r] : 0u;
+    uint32_t total;
+    uint32_t run = block_excl_scan<T>(sum, sh, total);
+    GLOBAL uint32_t *offs = J.coffs + static_cast<uint64_t>(w) * (B + 1);
+#pragma unroll
+    for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t b = b0 + r;
+        if (b < B) {
+            const uint32_t c = h[b];
+            h[b] = run;
+            offs[b] = static_cast<uint32_t>(lo) + run;
+            run += c;
+        }
+    }
+    if (threadIdx.x == 0) offs[B] = static_cast<uint32_t>(hi);
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * T) {
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = i + u * T < hi ? J.ids[i + u * T] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * T < hi) J.plist[lo + atomicAdd(&h[v[u] >> rb], 1u)] = v[u];
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_bin_count(const GreedyJob *jobs)
+{
+    constexpr int U = 4;
+    static_assert(kCountTilesMax <= T, "one tile per thread");
+    __shared__ uint32_t c[kCountSpan];
+    __shared__ uint32_t seg_lo[kCountTilesMax], seg_pre[kCountTilesMax];
+    __shared__ uint32_t sh[T / kWave];
+    const GJob J = view(jobs[blockIdx.y]);
+    const uint32_t P = J.c_parts, b = blockIdx.x / P, part = blockIdx.x % P;
+    if (b >= J.c_bins) return;  // uniform per block
+    // this workgroup's tiles: [t0, t0 + nt)
+    const uint32_t t0 = static_cast<uint32_t>(static_cast<uint64_t>(J.c_tiles) * part / P);
+    const uint32_t nt = static_cast<uint32_t>(static_cast<uint64_t>(J.c_tiles) * (part + 1) / P) - t0;
+    const uint64_t stride = J.c_bins + 1;
+    uint32_t len = 0;
+    if (threadIdx.x < nt) {
+        const GLOBAL uint32_t *o = J.coffs + (t0 + threadIdx.x) * stride + b;
+        seg_lo[threadIdx.x] = o[0];
+        len = o[1] - o[0];
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<T>(len, sh, total);
+    if (threadIdx.x < nt) seg_pre[threadIdx.x] = ex;
+    __syncthreads();
+    const uint64_t base = static_cast<uint64_t>(b) << J.c_rbits;
+    const uint64_t span = min(static_cast<uint64_t>(1) << J.c_rbits, J.S - base);
+    for (uint64_t s0 = 0; s0 < span; s0 += kCountSpan) {
+        for (uint32_t j = threadIdx.x; j < kCountSpan; j += T) c[j] = 0;
+        __syncthreads();
+        const uint64_t first = base + s0;
+        for (uint32_t e = threadIdx.x; e < total; e += U * T) {
+            uint32_t v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t x = e + u * T;
+                v[u] = 0u;
+                if (x < total) {
+                    // the tile holding position x: last w with seg_pre[w] <= x
+                    uint32_t a = 0, z = nt;
+                    while (z - a > 1) {
+                        const uint32_t m = (a + z) >> 1;
+                        if (seg_pre[m] <= x) a = m; else z = m;
+                    }
+                    v[u] = J.plist[seg_lo[a] + (x - seg_pre[a])];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t r = static_cast<uint64_t>(v[u]) - first;  // wraps when below
+                if (e + u * T < total && r < kCountSpan) atomicAdd(&c[r], 1u);
+            }
+        }
+        __syncthreads();
+        const uint64_t n = min<uint64_t>(kCountSpan, span - s0);
+        if (P == 1) {
+            for (uint32_t j = threadIdx.x; j < n; j += T) J.cnt[first + j] = c[j];
+        } else {
+            for (uint32_t j = threadIdx.x; j < n; j += T)
+                if (c[j]) g_add(&J.cnt[first + j], c[j]);
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------- pool rebuild
@@ -847,6 +988,35 @@ unsigned grid_for(uint64_t items, unsigned block, unsigned cap)
 
 uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
 
+// Counting plan of a job: bins of 2^rbits ids (rbits >= kCountSpanLog, at
+// most kCountBins bins), tiles of at least kCountTileMin walk ids, and, when
+// there are fewer than kCountBinsFull bins, several workgroups per bin.
+constexpr uint32_t kCountBinsFull = 256;
+struct CountPlan {
+    uint32_t rbits, bins, tiles, parts;
+    uint64_t tile_len;
+};
+CountPlan count_plan(uint64_t S, uint64_t n_ids)
+{
+    uint32_t L = 0;  // ceil(log2 S)
+    while ((uint64_t(1) << L) < S) ++L;
+    CountPlan P;
+    P.rbits = std::max(kCountSpanLog, L > kCountBinsLog ? L - kCountBinsLog : 0u);
+    P.bins = static_cast<uint32_t>((S + (uint64_t(1) << P.rbits) - 1) >> P.rbits);
+    P.tiles = static_cast<uint32_t>(
+        std::min<uint64_t>(kCountTilesMax, std::max<uint64_t>(1, (n_ids + kCountTileMin - 1) / kCountTileMin)));
+    P.tile_len = (n_ids + P.tiles - 1) / P.tiles;
+    P.parts = P.bins >= kCountBinsFull
+                  ? 1u
+                  : std::min(P.tiles, (2 * kCountBinsFull + P.bins - 1) / P.bins);
+    return P;
+}
+uint64_t count_offs_words(uint64_t S, uint64_t n_ids)
+{
+    const CountPlan P = count_plan(S, n_ids);
+    return static_cast<uint64_t>(P.tiles) * (P.bins + 1);
+}
+
 // Carve a job's buffers from its scratch block (layout of greedy_scratch_bytes).
 GreedyJob carve(const GreedyInput &g)
 {
@@ -870,6 +1040,13 @@ GreedyJob carve(const GreedyInput &g)
     J.hist = reinterpret_cast<uint32_t *>(take(4 * kBins));
     J.pool = reinterpret_cast<uint32_t *>(take(4 * kPoolMax));
     J.tiles = reinterpret_cast<uint32_t *>(take(4 * ((S + kScanTile - 1) / kScanTile)));
+    J.coffs = reinterpret_cast<uint32_t *>(take(4 * count_offs_words(S, g.n_ids)));
+    const CountPlan P = count_plan(S, g.n_ids);
+    J.c_rbits = P.rbits;
+    J.c_bins = P.bins;
+    J.c_tiles = P.tiles;
+    J.c_parts = P.parts;
+    J.c_tile_len = P.tile_len;
     J.cnt = g.cnt;
     J.walk_off = g.walk_off;
     J.walk_len = g.walk_len;
@@ -878,7 +1055,6 @@ GreedyJob carve(const GreedyInput &g)
     J.n_walks = g.n_walks;
     J.n_ids = g.n_ids;
     J.k = g.k;
-    J.need_count = g.counts_ready ? 0u : 1u;
     return J;
 }
 
@@ -891,7 +1067,8 @@ size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids,
     return al256(4 * S) + al256(4 * std::max<uint64_t>(n_ids, 1)) + al256(4 * (kPoolMax + 1)) +
            al256(4 * kPoolMax) + al256(4 * ((S + 31) / 32)) +
            2 * al256(4 * std::max<uint64_t>(n_walks, 1)) + 2 * al256(8 * static_cast<uint64_t>(k)) +
-           al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile));
+           al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile)) +
+           al256(4 * count_offs_words(S, n_ids));
 }
 
 // job table: n_jobs GreedyJob records, then their n_jobs states (one copy
@@ -906,7 +1083,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
 {
     const uint32_t Q = static_cast<uint32_t>(in.size());
     if (!Q) return;
-    uint64_t max_S = 0, max_walks = 0, max_ids = 0;
+    uint64_t max_S = 0, max_walks = 0;
+    uint32_t max_bins = 1, max_ctiles = 1;
     std::vector<GreedyJob> jobs(Q);
     for (uint32_t q = 0; q < Q; ++q) {
         GreedyInput &g = in[q];
@@ -919,7 +1097,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
         g.rounds_seen = 0;
         max_S = std::max(max_S, g.id_space);
         max_walks = std::max(max_walks, g.n_walks);
-        max_ids = std::max(max_ids, g.n_ids);
+        max_bins = std::max(max_bins, jobs[q].c_bins * jobs[q].c_parts);
+        max_ctiles = std::max(max_ctiles, jobs[q].c_tiles);
     }
     const unsigned cus = static_cast<unsigned>(device_cu_count());
     const unsigned tiles = static_cast<unsigned>((max_S + kScanTile - 1) / kScanTile);
@@ -936,7 +1115,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     SIA_HIP(hipMemcpyAsync(d_jobs, jobs.data(), sizeof(GreedyJob) * Q, hipMemcpyHostToDevice, s));
     const uint64_t init_items = std::max<uint64_t>({max_walks, max_S, kBins});
     hipLaunchKernelGGL(k_init, dim3(grid_for(init_items, 256, cus * 8), Q), dim3(256), 0, s, d_jobs);
-    hipLaunchKernelGGL(k_count, dim3(grid_for(max_ids, 256, cus * 16), Q), dim3(256), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_bin_sort<1024>, dim3(max_ctiles, Q), dim3(1024), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_bin_count<1024>, dim3(max_bins, Q), dim3(1024), 0, s, d_jobs);
     SIA_HIP(hipGetLastError());
     if (timing) SIA_HIP(hipEventRecord(ev[1], s));
 
@@ -997,8 +1177,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
 }
 
 GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
-                        int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s, bool timing,
-                        bool counts_ready)
+                        int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s, bool timing)
 {
     const uint64_t S = static_cast<uint64_t>(id_space);
     ws.greedy.ensure(greedy_scratch_bytes(S, n_walks, n_ids, k));
@@ -1014,7 +1193,6 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
     g.n_ids = n_ids;
     g.k = k;
     g.cnt = ws.cnt.as<uint32_t>();
-    g.counts_ready = counts_ready;
     g.scratch = ws.greedy.ptr;
     g.selected = selected;
     g.gains = gains;

@@ -749,7 +749,6 @@ struct sia_batch {
                 gi.n_ids = t.wm_ids;
                 gi.k = t.k;
                 gi.cnt = sl.cnt.as<uint32_t>();
-                gi.counts_ready = false;
                 gi.scratch = sl.greedy.ptr;
                 gi.selected = t.selected.data();
                 gi.gains = t.gains.data();
@@ -905,7 +904,6 @@ struct sia_batch {
                 gi.n_ids = n_ids;
                 gi.k = kq;
                 gi.cnt = sl.cnt.as<uint32_t>();
-                gi.counts_ready = false;
                 gi.scratch = sl.greedy.ptr;
                 gi.selected = gsel.data();
                 gi.gains = ggain.data();

@@ -351,6 +351,42 @@ def test_greedy_empty_and_exhaustive(sia):
     assert sel.tolist() == [1, 3, 0, 2, 4, 5] and gains.tolist() == [1, 1, 0, 0, 0, 0]
 
 
+@pytest.mark.parametrize("case", ["few_bins", "sub_passes", "many_tiles"])
+def test_greedy_counts_exact(sia, case):
+    """Walks of one id each: covering an id then lowers no other id's count,
+    so the greedy takes ids by count (ties by ascending id, then the lowest
+    ids of count 0) and each gain is the id's count -- the counting pass is
+    checked id by id.  few_bins: 300 ids, 3*10^6 walks (each range of ids is
+    counted by several workgroups); sub_passes: an id space above 2^30 (ranges
+    wider than one LDS pass), both ends of it used; many_tiles: 2*10^7 walks
+    over 2^24 + 3 ids (the most tiles)."""
+    rng = np.random.default_rng({"few_bins": 11, "sub_passes": 12, "many_tiles": 13}[case])
+    if case == "few_bins":
+        S, k = 300, 300
+        ids = np.minimum(rng.zipf(1.3, 3_000_000) - 1, S - 1)
+    elif case == "sub_passes":
+        S, k = (1 << 30) + 5, 3000
+        hot = rng.integers(0, S, 2000)
+        ids = np.concatenate([rng.integers(0, S, 1_000_000), hot[rng.integers(0, 2000, 1_000_000)],
+                              [0, 0, S - 1, S - 1, S - 1]])
+    else:
+        S, k = (1 << 24) + 3, 5000
+        ids = np.concatenate([rng.integers(0, S, 19_000_000), rng.integers(S - 70_000, S, 1_000_000)])
+    ids = rng.permutation(ids).astype(np.uint32)
+    off = np.arange(ids.shape[0] + 1, dtype=np.uint64)
+    sel, gains = sia.greedy(S, off, ids, k)
+    u, c = np.unique(ids, return_counts=True)
+    order = np.lexsort((u, -c))
+    exp_sel, exp_gain = u[order][:k].astype(np.int64), c[order][:k].astype(np.uint64)
+    if exp_sel.shape[0] < k:
+        rest = k - exp_sel.shape[0]
+        zeros = np.setdiff1d(np.arange(min(S, u.shape[0] + rest)), u)[:rest]
+        exp_sel = np.concatenate([exp_sel, zeros])
+        exp_gain = np.concatenate([exp_gain, np.zeros(rest, np.uint64)])
+    assert np.array_equal(sel, exp_sel)
+    assert np.array_equal(gains, exp_gain)
+
+
 # ------------------------------------------------------------------ solve
 @pytest.mark.parametrize("mode", ["edges", "nodes"])
 def test_solve_er1k_matches_oracle(sia, mode):
