@@ -52,14 +52,19 @@ constexpr uint32_t kPoolMax = 8192;        // the lazy rounds keep the pool in L
 constexpr uint32_t kHashBits = 14;         // id -> pool position hash, load <= 1/2
 constexpr uint32_t kHash = 1u << kHashBits;
 constexpr uint32_t kFilterBits = 17;       // LDS bit filter of pool ids (false positives <= 1/16)
-// Coverage counting by id ranges (k_bin_sort, k_bin_count): bins of 2^rbits
-// ids, at most kCountBins of them; up to kCountTilesMax tiles of the walk ids.
+// Coverage counting by id ranges (k_bin_sort .. k_bin_count): fine bins of
+// 2^rbits ids, at most kCountBins of them; up to kCountTilesMax tiles of the
+// walk ids.
 constexpr uint32_t kCountBinsLog = 14;
 constexpr uint32_t kCountBins = 1u << kCountBinsLog;
 constexpr uint32_t kCountSpanLog = 14;  // LDS counters of one counting pass
 constexpr uint32_t kCountSpan = 1u << kCountSpanLog;
 constexpr uint32_t kCountTilesMax = 512;
 constexpr uint64_t kCountTileMin = 32768;
+constexpr uint32_t kCoarseLog = 8;          // first level: at most 256 coarse bins
+constexpr uint32_t kCoarseMax = 1u << kCoarseLog;
+constexpr uint32_t kFineMax = 1u << (kCountBinsLog - kCoarseLog);  // fine bins per coarse bin
+constexpr uint32_t kChunk = 8192;           // second level: ids sorted per LDS chunk
 constexpr uint32_t kFilterWords = (1u << kFilterBits) / 32;
 static_assert(kHash >= 2 * kPoolMax, "pool hash load factor");
 
@@ -104,10 +109,19 @@ struct GreedyJob {
     int64_t k;
     uint32_t c_rbits;   // counting: ids per bin = 2^c_rbits
     uint32_t c_bins;    // counting: bins over [0, S)
+    uint32_t c_fbits;   // counting: fine bins per coarse bin = 2^c_fbits
+    uint32_t c_coarse;  // counting: coarse bins
     uint32_t c_tiles;   // counting: tiles of the walk ids
-    uint32_t c_parts;   // counting: workgroups per bin (> 1: they add into cnt)
+    uint32_t c_parts;   // counting: workgroups per fine bin (> 1: they add into cnt)
+    uint32_t c_chunks_max;  // counting: bound on the chunks of all coarse bins
+    uint32_t c_pad;
     uint64_t c_tile_len;
-    uint32_t *coffs;    // c_tiles x (c_bins + 1): where each tile's bins start in plist
+    uint32_t *coffs;    // c_tiles x (c_coarse + 1): where each tile's coarse bins start in plist
+    uint32_t *ctab;     // c_coarse x c_tiles pairs: segment start in the bin, in plist
+    uint32_t *cn;       // c_coarse: ids per coarse bin
+    uint32_t *cchunk;   // c_coarse + 1: first chunk of each coarse bin
+    uint32_t *coffs2;   // c_chunks_max x (2^c_fbits + 1): fine-bin starts in a chunk
+    uint32_t *cbuf;     // c_chunks_max x kChunk: chunks sorted by fine bin
     int64_t *sel;       // k
     uint64_t *gain;     // k
     uint32_t *hist;     // kBins
@@ -132,9 +146,14 @@ struct GJob {
     const GLOBAL uint32_t *ids;
     uint64_t S, n_walks, n_ids;
     int64_t k;
-    uint32_t c_rbits, c_bins, c_tiles, c_parts;
+    uint32_t c_rbits, c_bins, c_fbits, c_coarse, c_tiles, c_parts, c_chunks_max;
     uint64_t c_tile_len;
     GLOBAL uint32_t *coffs;
+    GLOBAL uint32_t *ctab;
+    GLOBAL uint32_t *cn;
+    GLOBAL uint32_t *cchunk;
+    GLOBAL uint32_t *coffs2;
+    GLOBAL uint32_t *cbuf;
     GLOBAL int64_t *sel;
     GLOBAL uint64_t *gain;
     GLOBAL uint32_t *hist;
@@ -163,10 +182,18 @@ __device__ __forceinline__ GJob view(const GreedyJob &j)
     J.k = j.k;
     J.c_rbits = j.c_rbits;
     J.c_bins = j.c_bins;
+    J.c_fbits = j.c_fbits;
+    J.c_coarse = j.c_coarse;
     J.c_tiles = j.c_tiles;
     J.c_parts = j.c_parts;
+    J.c_chunks_max = j.c_chunks_max;
     J.c_tile_len = j.c_tile_len;
     J.coffs = gp(j.coffs);
+    J.ctab = gp(j.ctab);
+    J.cn = gp(j.cn);
+    J.cchunk = gp(j.cchunk);
+    J.coffs2 = gp(j.coffs2);
+    J.cbuf = gp(j.cbuf);
     J.sel = gp(j.sel);
     J.gain = gp(j.gain);
     J.hist = gp(j.hist);
@@ -306,29 +333,51 @@ __global__ void k_init(const GreedyJob *jobs)
 // ---------------------------------------------------------------- coverage counts
 // cnt[id] = number of kept walks holding id (the initial Cov of each id),
 // taken without global atomics: random atomics over an id space of 10^8 ids
-// and more miss every cache.  The id space is cut into bins of 2^rbits ids.
-// k_bin_sort: each tile of the walk ids is histogrammed by bin in LDS and
-// scattered bin by bin into plist (unused until the first pool is filled);
-// coffs records where each of the tile's bins starts.  k_bin_count: one
-// workgroup per bin gathers that bin's segment of every tile, counts in LDS
-// (kCountSpan ids per pass) and writes the count of every id of the bin, so
-// cnt needs no clearing.  When the bins are too few to fill the GPU, each
-// bin's tiles are split among c_parts workgroups that add their counts.
+// and more miss every cache.  The id space is cut into fine bins of 2^rbits
+// ids (at most kCountBins), grouped into at most kCoarseMax coarse bins of
+// 2^fbits fine bins.  The ids are partitioned in two levels, each narrow
+// enough that the lines being written stay in L2 until they are whole (a
+// single 2^14-way scatter wrote every 4-byte id as a separate partial line):
+//   k_bin_sort   each tile of the walk ids is split by coarse bin into plist
+//                (unused until the first pool is filled); coffs records where
+//                each of the tile's coarse bins starts;
+//   k_bin_plan   per coarse bin: where its segment of each tile starts in the
+//                bin's concatenation (ctab) and its size (cn);
+//   k_bin_bases  chunks of kChunk ids per coarse bin, numbered (cchunk);
+//   k_bin_sort2  each chunk is sorted by fine bin in LDS and written whole
+//                to its kChunk slots of cbuf; coffs2 records the fine bins;
+//   k_bin_count  one workgroup per fine bin counts its run of every chunk of
+//                its coarse bin in LDS (kCountSpan ids per pass) and writes
+//                the count of every id of the bin, so cnt needs no clearing.
+//                When the fine bins are too few to fill the GPU, each bin's
+//                chunks are split among c_parts workgroups that add their
+//                counts (cnt is then cleared by k_init).
+
+// last index i in [0, n) with pre[i] <= x (pre ascending, pre[0] <= x)
+__device__ __forceinline__ uint32_t last_le(const uint32_t *pre, uint32_t n, uint32_t x)
+{
+    uint32_t a = 0, z = n;
+    while (z - a > 1) {
+        const uint32_t m = (a + z) >> 1;
+        if (pre[m] <= x) a = m;
+        else z = m;
+    }
+    return a;
+}
 
 template <int T>
 __global__ __launch_bounds__(T) void k_bin_sort(const GreedyJob *jobs)
 {
-    constexpr int U = 8;                        // loads in flight per lane
-    constexpr uint32_t kPer = kCountBins / T;   // bins each thread scans
-    static_assert(kCountBins % T == 0, "bins per thread");
-    __shared__ uint32_t h[kCountBins];
+    constexpr int U = 8;  // loads in flight per lane
+    static_assert(kCoarseMax <= T, "one coarse bin per thread");
+    __shared__ uint32_t h[kCoarseMax];
     __shared__ uint32_t sh[T / kWave];
     const GJob J = view(jobs[blockIdx.y]);
     const uint32_t w = blockIdx.x;
     if (w >= J.c_tiles) return;  // uniform per block
     const uint64_t lo = min(J.n_ids, w * J.c_tile_len), hi = min(J.n_ids, lo + J.c_tile_len);
-    const uint32_t B = J.c_bins, rb = J.c_rbits;
-    for (uint32_t b = threadIdx.x; b < B; b += T) h[b] = 0;
+    const uint32_t C = J.c_coarse, sft = J.c_rbits + J.c_fbits;
+    if (threadIdx.x < kCoarseMax) h[threadIdx.x] = 0;
     __syncthreads();
     for (uint64_t i = lo + threadIdx.x; i < hi; i += U * T) {
         uint32_t v[U];
@@ -336,99 +385,194 @@ __global__ __launch_bounds__(T) void k_bin_sort(const GreedyJob *jobs)
         for (int u = 0; u < U; ++u) v[u] = i + u * T < hi ? J.ids[i + u * T] : 0u;
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (i + u * T < hi) atomicAdd(&h[v[u] >> rb], 1u);
+            if (i + u * T < hi) atomicAdd(&h[v[u] >> sft], 1u);
     }
     __syncthreads();
-    // exclusive scan of h[0 .. B) in place; thread t holds bins [t*kPer, (t+1)*kPer)
-    const uint32_t b0 = threadIdx.x * kPer;
-    uint32_t sum = 0;
-#pragma unroll
-    for (uint32_t r = 0; r < kPer; ++r) sum += b0 + r < B ? h[b0 + r] : 0u;
+    const uint32_t mine = threadIdx.x < C ? h[threadIdx.x] : 0u;
     uint32_t total;
-    uint32_t run = block_excl_scan<T>(sum, sh, total);
-    GLOBAL uint32_t *offs = J.coffs + static_cast<uint64_t>(w) * (B + 1);
+    const uint32_t ex = block_excl_scan<T>(mine, sh, total);  // ends with a barrier
+    GLOBAL uint32_t *offs = J.coffs + static_cast<uint64_t>(w) * (C + 1);
+    if (threadIdx.x < C) {
+        h[threadIdx.x] = ex;
+        offs[threadIdx.x] = static_cast<uint32_t>(lo) + ex;
+    }
+    if (threadIdx.x == 0) offs[C] = static_cast<uint32_t>(hi);
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * T) {
+        uint32_t v[U];
 #pragma unroll
-    for (uint32_t r = 0; r < kPer; ++r) {
-        const uint32_t b = b0 + r;
-        if (b < B) {
-            const uint32_t c = h[b];
-            h[b] = run;
-            offs[b] = static_cast<uint32_t>(lo) + run;
-            run += c;
+        for (int u = 0; u < U; ++u) v[u] = i + u * T < hi ? J.ids[i + u * T] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * T < hi) J.plist[lo + atomicAdd(&h[v[u] >> sft], 1u)] = v[u];
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_bin_plan(const GreedyJob *jobs)
+{
+    static_assert(kCountTilesMax <= T, "one tile per thread");
+    __shared__ uint32_t sh[T / kWave];
+    const GJob J = view(jobs[blockIdx.y]);
+    const uint32_t c = blockIdx.x;
+    if (c >= J.c_coarse) return;  // uniform per block
+    const uint32_t nt = J.c_tiles, C = J.c_coarse;
+    uint32_t len = 0, at = 0;
+    if (threadIdx.x < nt) {
+        const GLOBAL uint32_t *o = J.coffs + static_cast<uint64_t>(threadIdx.x) * (C + 1) + c;
+        at = o[0];
+        len = o[1] - at;
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<T>(len, sh, total);
+    if (threadIdx.x < nt) {
+        GLOBAL uint32_t *row = J.ctab + 2ull * (static_cast<uint64_t>(c) * nt + threadIdx.x);
+        row[0] = ex;  // start in the coarse bin's concatenation
+        row[1] = at;  // start in plist
+    }
+    if (threadIdx.x == 0) J.cn[c] = total;
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_bin_bases(const GreedyJob *jobs)
+{
+    static_assert(kCoarseMax <= T, "one coarse bin per thread");
+    __shared__ uint32_t sh[T / kWave];
+    const GJob J = view(jobs[blockIdx.y]);
+    const uint32_t C = J.c_coarse;
+    const uint32_t n = threadIdx.x < C ? (J.cn[threadIdx.x] + kChunk - 1) / kChunk : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<T>(n, sh, total);
+    if (threadIdx.x < C) J.cchunk[threadIdx.x] = ex;
+    if (threadIdx.x == 0) J.cchunk[C] = total;
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_bin_sort2(const GreedyJob *jobs)
+{
+    constexpr int U = kChunk / T;  // every load of the chunk in flight at once
+    static_assert(kChunk % T == 0 && kFineMax <= T, "chunk and fine bins per thread");
+    __shared__ uint32_t vpre[kCountTilesMax], vphys[kCountTilesMax];
+    __shared__ uint32_t base[kCoarseMax + 1];
+    __shared__ uint32_t fh[kFineMax];
+    __shared__ uint32_t wr[2];  // tiles holding the chunk's first and last id
+    __shared__ uint32_t sh[T / kWave];
+    const GJob J = view(jobs[blockIdx.y]);
+    const uint32_t g = blockIdx.x;
+    if (g >= J.c_chunks_max) return;  // uniform per block
+    const uint32_t C = J.c_coarse, nt = J.c_tiles, F = 1u << J.c_fbits;
+    for (uint32_t t = threadIdx.x; t <= C; t += T) base[t] = J.cchunk[t];
+    if (threadIdx.x < kFineMax) fh[threadIdx.x] = 0;
+    __syncthreads();
+    if (g >= base[C]) return;  // uniform: past the last chunk
+    const uint32_t c = last_le(base, C + 1, g);  // coarse bin of chunk g
+    const uint32_t v0 = (g - base[c]) * kChunk;
+    const uint32_t n = min(kChunk, J.cn[c] - v0);
+    for (uint32_t t = threadIdx.x; t < nt; t += T) {
+        const GLOBAL uint32_t *row = J.ctab + 2ull * (static_cast<uint64_t>(c) * nt + t);
+        vpre[t] = row[0];
+        vphys[t] = row[1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        wr[0] = last_le(vpre, nt, v0);
+        wr[1] = last_le(vpre, nt, v0 + n - 1);
+    }
+    __syncthreads();
+    // the chunk spans tiles w0 .. w1 of its coarse bin (a few, unless they are tiny)
+    const uint32_t w0 = wr[0], nw = wr[1] - w0 + 1;
+    const uint32_t rb = J.c_rbits;
+    uint32_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t i = threadIdx.x + u * T;
+        x[u] = 0u;
+        if (i < n) {
+            const uint32_t v = v0 + i;
+            const uint32_t w = w0 + last_le(vpre + w0, nw, v);
+            x[u] = J.plist[vphys[w] + (v - vpre[w])];
         }
     }
-    if (threadIdx.x == 0) offs[B] = static_cast<uint32_t>(hi);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (threadIdx.x + u * T < n) atomicAdd(&fh[(x[u] >> rb) & (F - 1)], 1u);
     __syncthreads();
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += U * T) {
-        uint32_t v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = i + u * T < hi ? J.ids[i + u * T] : 0u;
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (i + u * T < hi) J.plist[lo + atomicAdd(&h[v[u] >> rb], 1u)] = v[u];
+    const uint32_t mine = threadIdx.x < F ? fh[threadIdx.x] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<T>(mine, sh, total);  // ends with a barrier
+    GLOBAL uint32_t *offs = J.coffs2 + static_cast<uint64_t>(g) * (F + 1);
+    if (threadIdx.x < F) {
+        fh[threadIdx.x] = ex;
+        offs[threadIdx.x] = ex;
     }
+    if (threadIdx.x == 0) offs[F] = n;
+    __syncthreads();
+    GLOBAL uint32_t *out = J.cbuf + static_cast<uint64_t>(g) * kChunk;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (threadIdx.x + u * T < n) out[atomicAdd(&fh[(x[u] >> rb) & (F - 1)], 1u)] = x[u];
 }
 
 template <int T>
 __global__ __launch_bounds__(T) void k_bin_count(const GreedyJob *jobs)
 {
     constexpr int U = 4;
-    static_assert(kCountTilesMax <= T, "one tile per thread");
-    __shared__ uint32_t c[kCountSpan];
-    __shared__ uint32_t seg_lo[kCountTilesMax], seg_pre[kCountTilesMax];
+    __shared__ uint32_t lc[kCountSpan];
+    __shared__ uint32_t sat[T], spre[T];  // a batch of chunks: run start in cbuf, prefix
     __shared__ uint32_t sh[T / kWave];
     const GJob J = view(jobs[blockIdx.y]);
     const uint32_t P = J.c_parts, b = blockIdx.x / P, part = blockIdx.x % P;
     if (b >= J.c_bins) return;  // uniform per block
-    // this workgroup's tiles: [t0, t0 + nt)
-    const uint32_t t0 = static_cast<uint32_t>(static_cast<uint64_t>(J.c_tiles) * part / P);
-    const uint32_t nt = static_cast<uint32_t>(static_cast<uint64_t>(J.c_tiles) * (part + 1) / P) - t0;
-    const uint64_t stride = J.c_bins + 1;
-    uint32_t len = 0;
-    if (threadIdx.x < nt) {
-        const GLOBAL uint32_t *o = J.coffs + (t0 + threadIdx.x) * stride + b;
-        seg_lo[threadIdx.x] = o[0];
-        len = o[1] - o[0];
-    }
-    uint32_t total;
-    const uint32_t ex = block_excl_scan<T>(len, sh, total);
-    if (threadIdx.x < nt) seg_pre[threadIdx.x] = ex;
-    __syncthreads();
-    const uint64_t base = static_cast<uint64_t>(b) << J.c_rbits;
-    const uint64_t span = min(static_cast<uint64_t>(1) << J.c_rbits, J.S - base);
+    const uint32_t F = 1u << J.c_fbits, c = b >> J.c_fbits, f = b & (F - 1);
+    const uint32_t g0 = J.cchunk[c], g1 = J.cchunk[c + 1];
+    // this workgroup's chunks: [ga, gb)
+    const uint32_t ga = g0 + static_cast<uint32_t>(static_cast<uint64_t>(g1 - g0) * part / P);
+    const uint32_t gb = g0 + static_cast<uint32_t>(static_cast<uint64_t>(g1 - g0) * (part + 1) / P);
+    const uint64_t lo_id = static_cast<uint64_t>(b) << J.c_rbits;
+    const uint64_t span = min(static_cast<uint64_t>(1) << J.c_rbits, J.S - lo_id);
     for (uint64_t s0 = 0; s0 < span; s0 += kCountSpan) {
-        for (uint32_t j = threadIdx.x; j < kCountSpan; j += T) c[j] = 0;
+        for (uint32_t j = threadIdx.x; j < kCountSpan; j += T) lc[j] = 0;
         __syncthreads();
-        const uint64_t first = base + s0;
-        for (uint32_t e = threadIdx.x; e < total; e += U * T) {
-            uint32_t v[U];
+        const uint64_t first = lo_id + s0;
+        for (uint32_t gq = ga; gq < gb; gq += T) {
+            const uint32_t nb = min(static_cast<uint32_t>(T), gb - gq);
+            uint32_t len = 0;
+            if (threadIdx.x < nb) {
+                const uint32_t g = gq + threadIdx.x;
+                const GLOBAL uint32_t *o = J.coffs2 + static_cast<uint64_t>(g) * (F + 1) + f;
+                const uint32_t r0 = o[0];
+                len = o[1] - r0;
+                sat[threadIdx.x] = r0;
+            }
+            uint32_t total;
+            const uint32_t ex = block_excl_scan<T>(len, sh, total);  // ends with a barrier
+            if (threadIdx.x < nb) spre[threadIdx.x] = ex;
+            __syncthreads();
+            for (uint32_t e = threadIdx.x; e < total; e += U * T) {
+                uint32_t v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t x = e + u * T;
-                v[u] = 0u;
-                if (x < total) {
-                    // the tile holding position x: last w with seg_pre[w] <= x
-                    uint32_t a = 0, z = nt;
-                    while (z - a > 1) {
-                        const uint32_t m = (a + z) >> 1;
-                        if (seg_pre[m] <= x) a = m; else z = m;
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t x = e + u * T;
+                    v[u] = 0u;
+                    if (x < total) {
+                        const uint32_t k = last_le(spre, nb, x);
+                        v[u] = J.cbuf[static_cast<uint64_t>(gq + k) * kChunk + sat[k] + (x - spre[k])];
                     }
-                    v[u] = J.plist[seg_lo[a] + (x - seg_pre[a])];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint64_t r = static_cast<uint64_t>(v[u]) - first;  // wraps when below
+                    if (e + u * T < total && r < kCountSpan) atomicAdd(&lc[r], 1u);
                 }
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint64_t r = static_cast<uint64_t>(v[u]) - first;  // wraps when below
-                if (e + u * T < total && r < kCountSpan) atomicAdd(&c[r], 1u);
-            }
+            __syncthreads();  // the batch tables are rewritten next
         }
-        __syncthreads();
         const uint64_t n = min<uint64_t>(kCountSpan, span - s0);
         if (P == 1) {
-            for (uint32_t j = threadIdx.x; j < n; j += T) J.cnt[first + j] = c[j];
+            for (uint32_t j = threadIdx.x; j < n; j += T) J.cnt[first + j] = lc[j];
         } else {
             for (uint32_t j = threadIdx.x; j < n; j += T)
-                if (c[j]) g_add(&J.cnt[first + j], c[j]);
+                if (lc[j]) g_add(&J.cnt[first + j], lc[j]);
         }
         __syncthreads();
     }
@@ -988,33 +1132,45 @@ unsigned grid_for(uint64_t items, unsigned block, unsigned cap)
 
 uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
 
-// Counting plan of a job: bins of 2^rbits ids (rbits >= kCountSpanLog, at
-// most kCountBins bins), tiles of at least kCountTileMin walk ids, and, when
-// there are fewer than kCountBinsFull bins, several workgroups per bin.
+// Counting plan of a job: fine bins of 2^rbits ids (rbits >= kCountSpanLog,
+// at most kCountBins of them) in at most kCoarseMax coarse bins, tiles of at
+// least kCountTileMin walk ids, and, when there are fewer than kCountBinsFull
+// fine bins, several workgroups per fine bin.
 constexpr uint32_t kCountBinsFull = 256;
 struct CountPlan {
-    uint32_t rbits, bins, tiles, parts;
+    uint32_t rbits, bins, fbits, coarse, tiles, parts, chunks_max;
     uint64_t tile_len;
+    // scratch words: coffs, ctab, cn, cchunk, coffs2, cbuf
+    uint64_t w_offs, w_tab, w_cn, w_chunk, w_offs2, w_buf;
 };
+uint32_t ceil_log2(uint64_t x)
+{
+    uint32_t L = 0;
+    while ((uint64_t(1) << L) < x) ++L;
+    return L;
+}
 CountPlan count_plan(uint64_t S, uint64_t n_ids)
 {
-    uint32_t L = 0;  // ceil(log2 S)
-    while ((uint64_t(1) << L) < S) ++L;
+    const uint32_t L = ceil_log2(S);
     CountPlan P;
     P.rbits = std::max(kCountSpanLog, L > kCountBinsLog ? L - kCountBinsLog : 0u);
     P.bins = static_cast<uint32_t>((S + (uint64_t(1) << P.rbits) - 1) >> P.rbits);
+    const uint32_t Lb = ceil_log2(P.bins);
+    P.fbits = Lb > kCoarseLog ? Lb - kCoarseLog : 0u;
+    P.coarse = (P.bins + (1u << P.fbits) - 1) >> P.fbits;
     P.tiles = static_cast<uint32_t>(
         std::min<uint64_t>(kCountTilesMax, std::max<uint64_t>(1, (n_ids + kCountTileMin - 1) / kCountTileMin)));
     P.tile_len = (n_ids + P.tiles - 1) / P.tiles;
-    P.parts = P.bins >= kCountBinsFull
-                  ? 1u
-                  : std::min(P.tiles, (2 * kCountBinsFull + P.bins - 1) / P.bins);
+    P.parts = P.bins >= kCountBinsFull ? 1u : (2 * kCountBinsFull + P.bins - 1) / P.bins;
+    // each coarse bin ends in at most one partial chunk
+    P.chunks_max = static_cast<uint32_t>((n_ids + kChunk - 1) / kChunk + P.coarse);
+    P.w_offs = static_cast<uint64_t>(P.tiles) * (P.coarse + 1);
+    P.w_tab = 2ull * P.coarse * P.tiles;
+    P.w_cn = P.coarse;
+    P.w_chunk = P.coarse + 1;
+    P.w_offs2 = static_cast<uint64_t>(P.chunks_max) * ((1u << P.fbits) + 1);
+    P.w_buf = static_cast<uint64_t>(P.chunks_max) * kChunk;
     return P;
-}
-uint64_t count_offs_words(uint64_t S, uint64_t n_ids)
-{
-    const CountPlan P = count_plan(S, n_ids);
-    return static_cast<uint64_t>(P.tiles) * (P.bins + 1);
 }
 
 // Carve a job's buffers from its scratch block (layout of greedy_scratch_bytes).
@@ -1040,12 +1196,20 @@ GreedyJob carve(const GreedyInput &g)
     J.hist = reinterpret_cast<uint32_t *>(take(4 * kBins));
     J.pool = reinterpret_cast<uint32_t *>(take(4 * kPoolMax));
     J.tiles = reinterpret_cast<uint32_t *>(take(4 * ((S + kScanTile - 1) / kScanTile)));
-    J.coffs = reinterpret_cast<uint32_t *>(take(4 * count_offs_words(S, g.n_ids)));
     const CountPlan P = count_plan(S, g.n_ids);
+    J.coffs = reinterpret_cast<uint32_t *>(take(4 * P.w_offs));
+    J.ctab = reinterpret_cast<uint32_t *>(take(4 * P.w_tab));
+    J.cn = reinterpret_cast<uint32_t *>(take(4 * P.w_cn));
+    J.cchunk = reinterpret_cast<uint32_t *>(take(4 * P.w_chunk));
+    J.coffs2 = reinterpret_cast<uint32_t *>(take(4 * P.w_offs2));
+    J.cbuf = reinterpret_cast<uint32_t *>(take(4 * P.w_buf));
     J.c_rbits = P.rbits;
     J.c_bins = P.bins;
+    J.c_fbits = P.fbits;
+    J.c_coarse = P.coarse;
     J.c_tiles = P.tiles;
     J.c_parts = P.parts;
+    J.c_chunks_max = P.chunks_max;
     J.c_tile_len = P.tile_len;
     J.cnt = g.cnt;
     J.walk_off = g.walk_off;
@@ -1061,6 +1225,15 @@ GreedyJob carve(const GreedyInput &g)
 }  // namespace
 
 // ---------------------------------------------------------------- host side
+namespace {
+uint64_t count_scratch_bytes(uint64_t S, uint64_t n_ids)
+{
+    const CountPlan P = count_plan(S, n_ids);
+    return al256(4 * P.w_offs) + al256(4 * P.w_tab) + al256(4 * P.w_cn) + al256(4 * P.w_chunk) +
+           al256(4 * P.w_offs2) + al256(4 * P.w_buf);
+}
+}  // namespace
+
 size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids, int64_t k)
 {
     const uint64_t S = id_space;
@@ -1068,7 +1241,7 @@ size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids,
            al256(4 * kPoolMax) + al256(4 * ((S + 31) / 32)) +
            2 * al256(4 * std::max<uint64_t>(n_walks, 1)) + 2 * al256(8 * static_cast<uint64_t>(k)) +
            al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile)) +
-           al256(4 * count_offs_words(S, n_ids));
+           count_scratch_bytes(S, n_ids);
 }
 
 // job table: n_jobs GreedyJob records, then their n_jobs states (one copy
@@ -1084,7 +1257,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     const uint32_t Q = static_cast<uint32_t>(in.size());
     if (!Q) return;
     uint64_t max_S = 0, max_walks = 0;
-    uint32_t max_bins = 1, max_ctiles = 1;
+    uint32_t max_bins = 1, max_ctiles = 1, max_coarse = 1, max_chunks = 1;
     std::vector<GreedyJob> jobs(Q);
     for (uint32_t q = 0; q < Q; ++q) {
         GreedyInput &g = in[q];
@@ -1099,6 +1272,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
         max_walks = std::max(max_walks, g.n_walks);
         max_bins = std::max(max_bins, jobs[q].c_bins * jobs[q].c_parts);
         max_ctiles = std::max(max_ctiles, jobs[q].c_tiles);
+        max_coarse = std::max(max_coarse, jobs[q].c_coarse);
+        max_chunks = std::max(max_chunks, jobs[q].c_chunks_max);
     }
     const unsigned cus = static_cast<unsigned>(device_cu_count());
     const unsigned tiles = static_cast<unsigned>((max_S + kScanTile - 1) / kScanTile);
@@ -1116,6 +1291,9 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     const uint64_t init_items = std::max<uint64_t>({max_walks, max_S, kBins});
     hipLaunchKernelGGL(k_init, dim3(grid_for(init_items, 256, cus * 8), Q), dim3(256), 0, s, d_jobs);
     hipLaunchKernelGGL(k_bin_sort<1024>, dim3(max_ctiles, Q), dim3(1024), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_bin_plan<512>, dim3(max_coarse, Q), dim3(512), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_bin_bases<256>, dim3(1, Q), dim3(256), 0, s, d_jobs);
+    hipLaunchKernelGGL(k_bin_sort2<256>, dim3(max_chunks, Q), dim3(256), 0, s, d_jobs);
     hipLaunchKernelGGL(k_bin_count<1024>, dim3(max_bins, Q), dim3(1024), 0, s, d_jobs);
     SIA_HIP(hipGetLastError());
     if (timing) SIA_HIP(hipEventRecord(ev[1], s));
