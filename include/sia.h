@@ -206,6 +206,55 @@ sia_status sia_solve(const sia_graph *g, int mode, const int32_t *sources,
                      uint64_t attempt_offset, uint64_t seed, int64_t *selected,
                      uint64_t *gains, sia_stats *stats, int timing, void *hip_stream);
 
+/* Figures of a Stop-and-Stare run (sia_sas_solve). */
+typedef struct {
+    int32_t status;        /* 1: Check passed at iteration t; 0: |R_t| reached
+                              N_max first; -1: max_attempts ran out first */
+    int32_t t;             /* iterations run (the last one's figures follow) */
+    uint64_t n_t;          /* |R_t| = |R'_t| = ceil(Lambda * 2^(t-1)) HSAWs */
+    uint64_t attempts_r;   /* R_t = the HSAWs of attempts [0, attempts_r) */
+    uint64_t attempts_rp;  /* R'_t = the HSAWs of attempts [attempts_r, attempts_rp) */
+    uint64_t cov_r;        /* Cov_{R_t}(selected) = sum of the gains */
+    uint64_t cov_rp;       /* Cov_{R'_t}(selected): walks of R'_t holding a selected id */
+    uint64_t attempts_sampled; /* attempts the driver sampled in all */
+    double eps_t;          /* Check's bound at the last iteration (NaN when
+                              Cov_{R'_t} < Lambda_1, where it is not formed) */
+    double lambda;         /* equation "lambda" */
+    double lambda1;        /* equation "lambda_1" */
+    double n_max;          /* equation "guard" (edges) / "nguard" (nodes) */
+    int32_t t_max;         /* ceil(log2(2 N_max / Upsilon(eps, delta/3))) */
+    int32_t reserved;
+    double spread_est;     /* |X| + |V\X| * n_t / attempts_r */
+    double suspension_est; /* |V\X| * cov_r / attempts_r */
+    double suspension_nodes_est; /* suspension_est + |selected & X| (nodes) */
+    float ms_total;        /* wall time of the call */
+    float reserved2;
+} sia_sas_info;
+
+/*
+ * eSIA (Algorithm 6, mode SIA_EDGES) / nSIA (Algorithm 9, SIA_NODES): the
+ * Stop-and-Stare driver over the hot path.  The HSAW stream R_1, R_2, ...
+ * is the kept walks in attempt-id order (attempts 0, 1, 2, ... of seed).
+ * Iteration t takes the first N_t = ceil(Lambda 2^(t-1)) HSAWs as R_t and
+ * the next N_t as R'_t, picks k ids by the greedy on R_t and verifies them
+ * on R'_t with Check (Algorithm 5 / 8); it stops when Check passes or
+ * N_t >= N_max.  t_max reads the iteration lemma's Upsilon(eps, delta/3)
+ * (the displayed formula takes the logarithm of delta/3).  Every iteration
+ * samples R_t and R'_t afresh (a walk is a function of its attempt id).
+ *   eps        in (0, 1 - 1/e); delta in (0, 1) (the paper uses 1/n)
+ *   max_attempts  in [1, 2^32): the attempts the stream may use
+ *   selected   host int64[k] (out), gains host uint64[k] (out): the last
+ *              iteration's candidate; not written when status is -1 (then
+ *              info holds status, t and n_t of the iteration that could not
+ *              get its 2 N_t HSAWs, the parameters and attempts_sampled)
+ *   info       host (out)
+ * Errors as sia_solve.
+ */
+sia_status sia_sas_solve(const sia_graph *g, int mode, const int32_t *sources,
+                         int64_t n_sources, int64_t k, double eps, double delta,
+                         uint64_t seed, uint64_t max_attempts, int64_t *selected,
+                         uint64_t *gains, sia_sas_info *info, void *hip_stream);
+
 /*
  * Measuring hook (not part of the method): the device's random-gather
  * ceiling.  Fills a device array of array_bytes (1 MiB .. 16 GiB) and times

@@ -42,6 +42,19 @@ class Stats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class SasInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("t", C.c_int32), ("n_t", C.c_uint64),
+                ("attempts_r", C.c_uint64), ("attempts_rp", C.c_uint64), ("cov_r", C.c_uint64),
+                ("cov_rp", C.c_uint64), ("attempts_sampled", C.c_uint64), ("eps_t", C.c_double),
+                ("lambda_", C.c_double), ("lambda1", C.c_double), ("n_max", C.c_double),
+                ("t_max", C.c_int32), ("reserved", C.c_int32), ("spread_est", C.c_double),
+                ("suspension_est", C.c_double), ("suspension_nodes_est", C.c_double),
+                ("ms_total", C.c_float), ("reserved2", C.c_float)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("reserved")}
+
+
 class Query(C.Structure):
     _fields_ = [("mode", C.c_int32), ("reserved", C.c_int32), ("sources", C.c_void_p),
                 ("n_sources", C.c_int64), ("k", C.c_int64), ("n_attempts", C.c_uint64),
@@ -124,12 +137,14 @@ def lib():
         L.sia_batch_cancel.argtypes = [p, u64]
         L.sia_batch_stats_get.argtypes = [p, C.POINTER(BatchStats)]
         L.sia_batch_tune.argtypes = [p, C.POINTER(Query), C.c_double, C.POINTER(BatchConfig)]
+        L.sia_sas_solve.argtypes = [p, i32, p, i64, i64, C.c_double, C.c_double, u64, u64, p, p,
+                                    C.POINTER(SasInfo), p]
         L.sia_probe_gather.argtypes = [u64, C.c_uint32, i32, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), p]
         for name in ("sia_check_query", "sia_graph_create", "sia_graph_destroy", "sia_graph_info",
                      "sia_graph_thresholds", "sia_graph_arc_bytes", "sia_quantize", "sia_sample",
                      "sia_greedy",
-                     "sia_solve", "sia_probe_gather") + BATCH_SYMBOLS:
+                     "sia_solve", "sia_sas_solve", "sia_probe_gather") + BATCH_SYMBOLS:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -273,6 +288,22 @@ def solve(graph: Graph, sources, mode, k, n_attempts, attempt_offset=0, seed=201
                            attempt_offset, seed, _hptr(sel), _hptr(gains), C.byref(st),
                            1 if timing else 0, _stream(stream)))
     return dict(selected=sel, gains=gains, stats=st.as_dict())
+
+
+def sas_solve(graph: Graph, sources, mode, k, eps=0.1, delta=None, seed=2017,
+              max_attempts=(1 << 32) - 1, stream=None):
+    """eSIA / nSIA with the sample count chosen by Stop-and-Stare (see
+    sia_sas_solve in include/sia.h); delta defaults to 1/n."""
+    src = _host(sources, np.int32)
+    if delta is None:
+        delta = 1.0 / graph.n
+    sel = np.zeros(k, dtype=np.int64)
+    gains = np.zeros(k, dtype=np.uint64)
+    info = SasInfo()
+    _check(lib().sia_sas_solve(graph.handle, MODES[mode], _hptr(src), src.shape[0], k, float(eps),
+                               float(delta), seed, max_attempts, _hptr(sel), _hptr(gains),
+                               C.byref(info), _stream(stream)))
+    return dict(selected=sel, gains=gains, info=info.as_dict())
 
 
 def _query(sources, mode, k, n_attempts, attempt_offset, seed):

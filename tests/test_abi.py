@@ -130,3 +130,13 @@ def test_probe_gather_rejects_bad_arguments(L):
     assert L.sia_probe_gather(0, 512, 0, C.byref(rate), C.byref(ms), None) == -1
     assert L.sia_probe_gather(1 << 30, 7, 0, C.byref(rate), C.byref(ms), None) == -1
     assert L.sia_probe_gather(1 << 30, 512, 0, None, None, None) == -1
+
+
+def test_sas_solve_rejects_null_graph_on_host(L):
+    info = sia.SasInfo()
+    sel = np.zeros(4, np.int64)
+    gains = np.zeros(4, np.uint64)
+    src = np.array([1, 2], np.int32)
+    rc = L.sia_sas_solve(None, 0, src.ctypes.data, 2, 4, 0.1, 1e-3, 1, 1000, sel.ctypes.data,
+                         gains.ctypes.data, C.byref(info), None)
+    assert rc == -1 and L.sia_last_error().decode() != ""
