@@ -582,16 +582,32 @@ __global__ __launch_bounds__(T) void k_bin_count(const GreedyJob *jobs)
 template <int T>
 __global__ __launch_bounds__(T) void k_hist(const GreedyJob *jobs)
 {
+    constexpr int U = 8;              // loads in flight per lane
+    constexpr uint32_t kBallot = 4;   // counts below this are tallied by wave ballots
     __shared__ uint32_t h[kBins];
     const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J)) return;  // uniform per block
     for (uint32_t i = threadIdx.x; i < kBins; i += blockDim.x) h[i] = 0;
     __syncthreads();
-    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (; i < J.S; i += stride) {
-        const uint32_t c = J.cnt[i];
-        if (c != kSelected) atomicAdd(&h[count_bin(c)], 1u);
+    const int lane = threadIdx.x & (kWave - 1);
+    // whole-block tiles of U*T counts, so every lane of a wave takes part in each ballot
+    for (uint64_t base = blockIdx.x * static_cast<uint64_t>(U * T); base < J.S;
+         base += static_cast<uint64_t>(gridDim.x) * U * T) {
+        uint32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + u * T + threadIdx.x;
+            c[u] = i < J.S ? J.cnt[i] : kSelected;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (uint32_t v = 0; v < kBallot; ++v) {
+                const uint64_t m = __ballot(c[u] == v);
+                if (lane == 0 && m) atomicAdd(&h[v], static_cast<uint32_t>(__popcll(m)));
+            }
+            if (c[u] != kSelected && c[u] >= kBallot) atomicAdd(&h[count_bin(c[u])], 1u);
+        }
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < kBins; b += blockDim.x)
@@ -680,17 +696,25 @@ __global__ __launch_bounds__(T) void k_plan(const GreedyJob *jobs)
 }
 
 // Pool += every unselected id with cnt >= c_min.
-__global__ void k_collect(const GreedyJob *jobs)
+__global__ __launch_bounds__(256) void k_collect(const GreedyJob *jobs)
 {
+    constexpr int U = 8;  // loads in flight per lane
     const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J)) return;
     const uint32_t c_min = J.st->c_min;
     if (c_min == 0) return;
-    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (; i < J.S; i += stride) {
-        const uint32_t c = J.cnt[i];
-        if (c != kSelected && c >= c_min) J.pool[g_add(&J.st->pool_n, 1u)] = static_cast<uint32_t>(i);
+    for (uint64_t base = blockIdx.x * static_cast<uint64_t>(U * blockDim.x); base < J.S;
+         base += static_cast<uint64_t>(gridDim.x) * U * blockDim.x) {
+        uint32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + u * blockDim.x + threadIdx.x;
+            c[u] = i < J.S ? J.cnt[i] : kSelected;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] != kSelected && c[u] >= c_min)
+                J.pool[g_add(&J.st->pool_n, 1u)] = static_cast<uint32_t>(base + u * blockDim.x + threadIdx.x);
     }
 }
 
@@ -811,24 +835,59 @@ __global__ __launch_bounds__(1024) void k_pool_mark(const GreedyJob *jobs)
 // pool skip the bitmap).
 __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
 {
+    constexpr int T = 256, U = 8;  // U id loads in flight per lane
     __shared__ uint32_t filt[kFilterWords];
+    __shared__ uint32_t start[T];  // a batch of walks: first position in the batch
+    __shared__ uint64_t woff[T];   //                   and offset into ids
+    __shared__ uint32_t wid[T];
+    __shared__ uint32_t sh[T / kWave];
     const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J) || J.st->plist_total == 0) return;  // uniform per block
     filter_build(filt, J.pool, pool_size(J.st));
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
-    for (uint64_t w = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave;
-         w < J.n_walks; w += waves) {
-        if (J.covered[w]) continue;  // uniform per wave
-        const uint64_t o = J.walk_off[w];
-        const uint32_t L = J.walk_len[w];
-        for (uint32_t e = lane; e < L; e += kWave) {
-            const uint32_t x = J.ids[o + e];
-            if (filter_has(filt, x) && (J.bitmap[x >> 5] & (1u << (x & 31)))) {
-                const uint32_t i = J.pidx[x];
-                J.plist[J.pstart[i] + g_add(&J.pfill[i], 1u)] = static_cast<uint32_t>(w);
+    // batches of T walks; the ids of a batch's uncovered walks are laid end
+    // to end and every thread takes positions, finding each one's walk by
+    // binary search, so all of a thread's id loads are independent
+    for (uint64_t w0 = blockIdx.x * static_cast<uint64_t>(T); w0 < J.n_walks;
+         w0 += static_cast<uint64_t>(gridDim.x) * T) {
+        const uint64_t w = w0 + threadIdx.x;
+        uint32_t len = 0;
+        uint64_t off = 0;
+        if (w < J.n_walks) {
+            const uint64_t o = J.walk_off[w];
+            const uint32_t l = J.walk_len[w];
+            if (!J.covered[w]) {
+                off = o;
+                len = l;
             }
         }
+        uint32_t total;
+        const uint32_t ex = block_excl_scan<T>(len, sh, total);  // ends with a barrier
+        start[threadIdx.x] = ex;
+        woff[threadIdx.x] = off;
+        wid[threadIdx.x] = static_cast<uint32_t>(w);
+        __syncthreads();
+        for (uint32_t f0 = threadIdx.x; f0 < total; f0 += U * T) {
+            uint32_t x[U], k[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t f = f0 + u * T;
+                x[u] = 0u;
+                k[u] = 0u;
+                if (f < total) {
+                    k[u] = last_le(start, T, f);  // empty (covered) walks share their start
+                    x[u] = J.ids[woff[k[u]] + (f - start[k[u]])];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (f0 + u * T < total && filter_has(filt, x[u]) &&
+                    (J.bitmap[x[u] >> 5] & (1u << (x[u] & 31)))) {
+                    const uint32_t i = J.pidx[x[u]];
+                    J.plist[J.pstart[i] + g_add(&J.pfill[i], 1u)] = wid[k[u]];
+                }
+            }
+        }
+        __syncthreads();  // the batch tables are rewritten next
     }
 }
 
@@ -1304,9 +1363,9 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     // shared out when several jobs run
     const unsigned base = hist_base ? hist_base : cus;
     const unsigned hist_blocks =
-        std::min(grid_for(max_S, T, base), std::max(1u, base / std::min<unsigned>(Q, 8)));
-    const unsigned collect_blocks = grid_for(max_S, 256, cus * 4);
-    const unsigned fill_blocks = grid_for(max_walks * kWave, 256, cus * 16);
+        std::min(grid_for(max_S, T * 8, base), std::max(1u, base / std::min<unsigned>(Q, 8)));
+    const unsigned collect_blocks = grid_for(max_S, 256 * 8, cus * 4);
+    const unsigned fill_blocks = grid_for(max_walks, 256, cus * 8);
     std::vector<GreedyState> hs(Q);
     for (int group = 1;; group = std::min(group * 2, 8)) {
         for (int gen = 0; gen < group; ++gen) {
