@@ -197,6 +197,32 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def sas_bench(args, sia, wl, g, mode, k, ingest_ms):
+    """Stop-and-Stare driver (eSIA Algorithm 6 / nSIA Algorithm 9): wall time of
+    whole runs with eps = args.eps and delta = 1/n; the sample count is the
+    driver's own."""
+    runs = []
+    for i in range(args.warmup + args.steps):
+        t0 = time.perf_counter()
+        r = sia.sas_solve(g, wl.sources, mode, k, args.eps, None, wl.seed)
+        dt = time.perf_counter() - t0
+        print(f"[bench] sas run {i + 1}/{args.warmup + args.steps}: {dt * 1e3:.1f} ms", file=sys.stderr,
+              flush=True)
+        if i >= args.warmup:
+            runs.append((dt, r))
+    ms = sum(d for d, _ in runs) / len(runs) * 1e3
+    info = runs[-1][1]["info"]
+    out = {"metric": "Stop-and-Stare runs/s (eSIA/nSIA to (1-1/e-eps) with delta = 1/n)",
+           "value": 1e3 / ms, "unit": "runs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"{wl.name}: {wl.desc['kind']} n={wl.n} m={wl.m}", "mode": mode, "k": k,
+                      "eps": args.eps, "delta": 1.0 / wl.n, "sources": len(wl.sources), "seed": wl.seed},
+           "ingest_ms": ingest_ms, "info": info,
+           "attempts_per_s": info["attempts_sampled"] / (ms * 1e-3)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +246,9 @@ def main():
     ap.add_argument("--greedy-cus", type=int, default=0, help="CUs reserved for the greedy (--serve)")
     ap.add_argument("--greedy-batch", type=int, default=0, help="queries per greedy launch (--serve)")
     ap.add_argument("--skip-plain", action="store_true", help="batched side only (--serve, profiling)")
+    ap.add_argument("--sas", action="store_true",
+                    help="time the Stop-and-Stare driver (eSIA / nSIA) on the workload instead")
+    ap.add_argument("--eps", type=float, default=0.1, help="epsilon of the Stop-and-Stare driver (--sas)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -249,6 +278,10 @@ def main():
     g = sia.Graph(wl.col_off, wl.row_idx, wl.w)
     torch.cuda.synchronize()
     ingest_ms = (time.perf_counter() - t0) * 1e3
+
+    if args.sas:
+        sas_bench(args, sia, wl, g, mode, k, ingest_ms)
+        return
 
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
