@@ -65,6 +65,7 @@ constexpr uint32_t kCoarseLog = 8;          // first level: at most 256 coarse b
 constexpr uint32_t kCoarseMax = 1u << kCoarseLog;
 constexpr uint32_t kFineMax = 1u << (kCountBinsLog - kCoarseLog);  // fine bins per coarse bin
 constexpr uint32_t kChunk = 8192;           // second level: ids sorted per LDS chunk
+static_assert(kCoarseMax * kFineMax == kCountBins, "two levels span every fine bin");
 constexpr uint32_t kFilterWords = (1u << kFilterBits) / 32;
 static_assert(kHash >= 2 * kPoolMax, "pool hash load factor");
 

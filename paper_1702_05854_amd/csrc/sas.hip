@@ -1,13 +1,15 @@
 // Stop-and-Stare driver: eSIA (Algorithm 6) / nSIA (Algorithm 9) with Check
 // (Algorithm 5 / 8) over the single-query path.
 //
-// The HSAW stream R_1, R_2, ... is the kept walks in attempt-id order.  A
-// walk is a function of (seed, attempt id), so the driver never stores or
-// sorts walks: it probes attempt ranges, keeping only the attempt ids of the
-// kept walks, finds by bisection the attempt bounds A (R_t = the kept walks
-// of [0, A)) and A' (R'_t = those of [A, A')), and samples both ranges
-// afresh: the greedy runs on R_t, and the coverage of its picks is counted
-// on R'_t by a kernel.  The scalar steps of Check run on the host.
+// The HSAW stream R_1, R_2, ... is the kept walks in attempt-id order.  The
+// driver samples attempt ranges [0, end) in chunks (sized from the hit rate
+// seen so far) and appends each chunk's kept walks to a device store, in
+// sampling order (unordered within a chunk).  A walk is a function of (seed,
+// attempt id), so R_t is exactly the stored walks with attempt id below a
+// bound A and R'_t those in [A, A'): the bounds are found by bisection over
+// the stored attempt ids, R_t is compacted into the greedy's input, and the
+// coverage of the picks is counted over the store's walks in [A, A').  The
+// scalar steps of Check run on the host.
 #include "common.hpp"
 
 #include <chrono>
@@ -44,11 +46,14 @@ __global__ __launch_bounds__(256) void k_mark_selected(const int64_t *sel, int64
     __hip_atomic_fetch_or(gp(bits) + (x >> 5), 1u << (x & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// n_out += number of walks holding a marked id; one wave per walk
-__global__ __launch_bounds__(256) void k_cover_walks(const uint64_t *walk_off, const uint32_t *walk_len,
-                                                     const uint32_t *ids, uint64_t n_walks,
+// n_out += number of walks with attempt id in [lo, hi) holding a marked id;
+// one wave per walk
+__global__ __launch_bounds__(256) void k_cover_walks(const uint64_t *walk_att, const uint64_t *walk_off,
+                                                     const uint32_t *walk_len, const uint32_t *ids,
+                                                     uint64_t n_walks, uint64_t lo, uint64_t hi,
                                                      const uint32_t *bits, unsigned long long *n_out)
 {
+    const GLOBAL uint64_t *att = gp(walk_att);
     const GLOBAL uint64_t *off = gp(walk_off);
     const GLOBAL uint32_t *len = gp(walk_len);
     const GLOBAL uint32_t *id = gp(ids);
@@ -58,6 +63,8 @@ __global__ __launch_bounds__(256) void k_cover_walks(const uint64_t *walk_off, c
     uint32_t covered = 0;
     for (uint64_t w = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave; w < n_walks;
          w += waves) {  // uniform per wave
+        const uint64_t a = att[w];
+        if (a < lo || a >= hi) continue;
         const uint64_t o = off[w];
         const uint32_t L = len[w];
         bool hit = false;
@@ -70,6 +77,109 @@ __global__ __launch_bounds__(256) void k_cover_walks(const uint64_t *walk_off, c
     if (lane == 0 && covered)
         __hip_atomic_fetch_add(gp(n_out), static_cast<unsigned long long>(covered), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// store offsets of an appended chunk: dst[i] = src[i] + base
+__global__ __launch_bounds__(256) void k_add_base(uint64_t *dst, const uint64_t *src, uint64_t n, uint64_t base)
+{
+    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (; i < n; i += stride) gp(dst)[i] = gp(src)[i] + base;
+}
+
+// ------------------------------------------------ compaction of a stream prefix
+constexpr int kSelT = 1024;  // walks per compaction block
+
+// exclusive scan of one value per thread over a kSelT-thread block (sh: kSelT/64 words)
+__device__ __forceinline__ uint32_t sel_block_scan(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(x, d, kWave);
+        if (lane >= d) x += o;
+    }
+    if (lane == kWave - 1) sh[wid] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    total = 0;
+    for (int k = 0; k < kSelT / kWave; ++k) {
+        if (k < wid) before += sh[k];
+        total += sh[k];
+    }
+    __syncthreads();
+    return before + x - v;
+}
+
+// per block of kSelT stored walks: how many have attempt id < bound, and their ids
+__global__ __launch_bounds__(kSelT) void k_sel_count(const uint64_t *walk_att, const uint32_t *walk_len,
+                                                   uint64_t n, uint64_t bound, uint32_t *blk)
+{
+    __shared__ uint32_t sh[kSelT / kWave];
+    const uint64_t i = blockIdx.x * static_cast<uint64_t>(kSelT) + threadIdx.x;
+    const bool sel = i < n && gp(walk_att)[i] < bound;
+    uint32_t tw, ti;
+    sel_block_scan(sel ? 1u : 0u, sh, tw);
+    sel_block_scan(sel ? gp(walk_len)[i] : 0u, sh, ti);
+    if (threadIdx.x == 0) {
+        gp(blk)[2 * blockIdx.x] = tw;
+        gp(blk)[2 * blockIdx.x + 1] = ti;
+    }
+}
+
+// exclusive scan of the nb (walks, ids) pairs in place; totals at [2 nb], [2 nb + 1]
+__global__ __launch_bounds__(kSelT) void k_sel_scan(uint32_t *blk, uint64_t nb)
+{
+    __shared__ uint32_t sh[kSelT / kWave];
+    uint32_t cw = 0, ci = 0;
+    for (uint64_t b0 = 0; b0 < nb; b0 += kSelT) {
+        const uint64_t b = b0 + threadIdx.x;
+        const uint32_t w = b < nb ? gp(blk)[2 * b] : 0u, d = b < nb ? gp(blk)[2 * b + 1] : 0u;
+        uint32_t tw, ti;
+        const uint32_t ew = sel_block_scan(w, sh, tw);
+        const uint32_t ei = sel_block_scan(d, sh, ti);
+        if (b < nb) {
+            gp(blk)[2 * b] = cw + ew;
+            gp(blk)[2 * b + 1] = ci + ei;
+        }
+        cw += tw;
+        ci += ti;
+    }
+    if (threadIdx.x == 0) {
+        gp(blk)[2 * nb] = cw;
+        gp(blk)[2 * nb + 1] = ci;
+    }
+}
+
+// write the selected walks (attempt id < bound) as a CSR set: offsets, lengths, ids
+__global__ __launch_bounds__(kSelT) void k_sel_emit(const uint64_t *walk_att, const uint64_t *walk_off,
+                                                  const uint32_t *walk_len, const uint32_t *ids, uint64_t n,
+                                                  uint64_t bound, const uint32_t *blk, uint64_t *out_off,
+                                                  uint32_t *out_len, uint32_t *out_ids)
+{
+    __shared__ uint32_t sh[kSelT / kWave];
+    __shared__ uint64_t src[kSelT];
+    __shared__ uint32_t dst[kSelT], cnt[kSelT];
+    const uint64_t i = blockIdx.x * static_cast<uint64_t>(kSelT) + threadIdx.x;
+    const bool sel = i < n && gp(walk_att)[i] < bound;
+    const uint32_t L = sel ? gp(walk_len)[i] : 0u;
+    uint32_t tw, ti;
+    const uint32_t rw = sel_block_scan(sel ? 1u : 0u, sh, tw);
+    const uint32_t ri = sel_block_scan(L, sh, ti);
+    const uint32_t pw = gp(blk)[2 * blockIdx.x] + rw, pi = gp(blk)[2 * blockIdx.x + 1] + ri;
+    if (sel) {
+        gp(out_off)[pw] = pi;
+        gp(out_len)[pw] = L;
+        src[rw] = gp(walk_off)[i];
+        dst[rw] = pi;
+        cnt[rw] = L;
+    }
+    __syncthreads();
+    // copy the ids, one wave per selected walk of the block
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (uint32_t w = wid; w < tw; w += kSelT / kWave)
+        for (uint32_t e = lane; e < cnt[w]; e += kWave) gp(out_ids)[dst[w] + e] = gp(ids)[src[w] + e];
 }
 
 unsigned grid_of(uint64_t items, unsigned block, unsigned cap)
@@ -160,12 +270,16 @@ sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, 
         I.t_max = P.t_max;
         I.eps_t = std::numeric_limits<double>::quiet_NaN();
 
-        DevBuf acc, scalar, bits, dsel;  // stream attempt ids, one counter, marks, picks
+        // the store: kept walks of attempts [0, end) in sampling order
+        DevBuf s_att, s_off, s_len, s_ids;
+        uint64_t s_n = 0, s_ni = 0;
+        DevBuf scalar, bits, dsel, blk;  // one counter, marks, picks, compaction block sums
         scalar.ensure(sizeof(unsigned long long));
         bits.ensure(4 * ((static_cast<uint64_t>(S) + 31) / 32));
         dsel.ensure(sizeof(int64_t) * static_cast<uint64_t>(k));
         const unsigned cus = static_cast<unsigned>(device_cu_count());
-        uint64_t end = 0, n_acc = 0, chunk = uint64_t(1) << 16;
+        uint64_t end = 0, chunk = uint64_t(1) << 16;
+        Workspace &ws = g->ws;
 
         auto read_counter = [&]() {
             unsigned long long v = 0;
@@ -175,8 +289,8 @@ sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, 
         };
         auto count_below = [&](uint64_t x) {
             SIA_HIP(hipMemsetAsync(scalar.ptr, 0, sizeof(unsigned long long), s));
-            hipLaunchKernelGGL(k_count_below, dim3(grid_of(n_acc, 256, cus * 4)), dim3(256), 0, s,
-                               acc.as<uint64_t>(), n_acc, x, scalar.as<unsigned long long>());
+            hipLaunchKernelGGL(k_count_below, dim3(grid_of(s_n, 256, cus * 4)), dim3(256), 0, s,
+                               s_att.as<uint64_t>(), s_n, x, scalar.as<unsigned long long>());
             SIA_HIP(hipGetLastError());
             return read_counter();
         };
@@ -197,45 +311,79 @@ sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, 
             const uint64_t n_t = static_cast<uint64_t>(nt_real);
             I.t = t;
             I.n_t = n_t;
-            // probe until the stream holds 2 N_t walks
-            while (n_acc < 2 * n_t && end < max_attempts) {
-                const uint64_t c = std::min(chunk, max_attempts - end);
+            // sample until the store holds 2 N_t walks; after the first walks,
+            // chunks aim at the walks still missing at the hit rate seen so far
+            while (s_n < 2 * n_t && end < max_attempts) {
+                uint64_t c = chunk;
+                if (s_n > 0) {
+                    const double rate = static_cast<double>(s_n) / static_cast<double>(end);
+                    const double want = 1.05 * static_cast<double>(2 * n_t - s_n) / rate + 65536.0;
+                    c = static_cast<uint64_t>(std::min(want, static_cast<double>(uint64_t(1) << 30)));
+                }
+                c = std::min(c, max_attempts - end);
                 const SampleResult r = run_sampler(g, mode, st, c, end, seed, s, false);
-                grow_keep(acc, 8 * n_acc, 8 * (n_acc + r.walks), s);
-                if (r.walks)
-                    SIA_HIP(hipMemcpyAsync(acc.as<uint64_t>() + n_acc, g->ws.walk_attempt.ptr, 8 * r.walks,
+                grow_keep(s_att, 8 * s_n, 8 * (s_n + r.walks), s);
+                grow_keep(s_off, 8 * s_n, 8 * (s_n + r.walks), s);
+                grow_keep(s_len, 4 * s_n, 4 * (s_n + r.walks), s);
+                grow_keep(s_ids, 4 * s_ni, 4 * (s_ni + r.ids), s);
+                if (r.walks) {
+                    SIA_HIP(hipMemcpyAsync(s_att.as<uint64_t>() + s_n, ws.walk_attempt.ptr, 8 * r.walks,
                                            hipMemcpyDeviceToDevice, s));
-                n_acc += r.walks;
+                    SIA_HIP(hipMemcpyAsync(s_len.as<uint32_t>() + s_n, ws.walk_len.ptr, 4 * r.walks,
+                                           hipMemcpyDeviceToDevice, s));
+                    hipLaunchKernelGGL(k_add_base, dim3(grid_of(r.walks, 256, cus * 4)), dim3(256), 0, s,
+                                       s_off.as<uint64_t>() + s_n, ws.walk_off.as<uint64_t>(), r.walks, s_ni);
+                    SIA_HIP(hipGetLastError());
+                }
+                if (r.ids)
+                    SIA_HIP(hipMemcpyAsync(s_ids.as<uint32_t>() + s_ni, ws.ids.ptr, 4 * r.ids,
+                                           hipMemcpyDeviceToDevice, s));
+                s_n += r.walks;
+                s_ni += r.ids;
                 end += c;
-                I.attempts_sampled += c;
                 chunk = std::min<uint64_t>(2 * chunk, uint64_t(1) << 30);
             }
-            if (n_acc < 2 * n_t) {
+            I.attempts_sampled = end;
+            if (s_n < 2 * n_t) {
                 I.status = -1;
                 break;
             }
+            SIA_REQUIRE(s_n < 0xFFFFFFFFull && s_ni < 0xFFFFFFFFull, SIA_EINVAL,
+                        "the stream outgrew 32-bit walk and id positions");
             const uint64_t a_r = bound(n_t), a_rp = bound(2 * n_t);
-            // R_t: greedy
+            // R_t: compact the store's walks below a_r into the greedy's input
+            const uint64_t nb = (s_n + kSelT - 1) / kSelT;
+            blk.ensure(4 * (2 * nb + 2));
+            hipLaunchKernelGGL(k_sel_count, dim3(static_cast<unsigned>(nb)), dim3(kSelT), 0, s,
+                               s_att.as<uint64_t>(), s_len.as<uint32_t>(), s_n, a_r, blk.as<uint32_t>());
+            hipLaunchKernelGGL(k_sel_scan, dim3(1), dim3(kSelT), 0, s, blk.as<uint32_t>(), nb);
+            SIA_HIP(hipGetLastError());
+            uint32_t tot[2] = {0, 0};
+            SIA_HIP(hipMemcpyAsync(tot, blk.as<uint32_t>() + 2 * nb, sizeof(tot), hipMemcpyDeviceToHost, s));
+            SIA_HIP(hipStreamSynchronize(s));
+            SIA_REQUIRE(tot[0] == n_t, SIA_EDEVICE, "stream prefix does not hold N_t walks");
+            ws.walk_off.ensure(8 * std::max<uint64_t>(n_t, 1));
+            ws.walk_len.ensure(4 * std::max<uint64_t>(n_t, 1));
+            ws.ids.ensure(4 * std::max<uint64_t>(tot[1], 1));
+            hipLaunchKernelGGL(k_sel_emit, dim3(static_cast<unsigned>(nb)), dim3(kSelT), 0, s,
+                               s_att.as<uint64_t>(), s_off.as<uint64_t>(), s_len.as<uint32_t>(),
+                               s_ids.as<uint32_t>(), s_n, a_r, blk.as<uint32_t>(), ws.walk_off.as<uint64_t>(),
+                               ws.walk_len.as<uint32_t>(), ws.ids.as<uint32_t>());
+            SIA_HIP(hipGetLastError());
             std::vector<int64_t> sel(static_cast<size_t>(k));
             std::vector<uint64_t> gain(static_cast<size_t>(k));
-            const SampleResult r1 = run_sampler(g, mode, st, a_r, 0, seed, s, false);
-            I.attempts_sampled += a_r;
-            SIA_REQUIRE(r1.walks == n_t, SIA_EDEVICE, "stream prefix does not hold N_t walks");
-            run_greedy(g->ws, S, r1.walks, r1.ids, k, sel.data(), gain.data(), s, false);
+            run_greedy(ws, S, n_t, tot[1], k, sel.data(), gain.data(), s, false);
             uint64_t cov_r = 0;
             for (uint64_t x : gain) cov_r += x;
-            // R'_t: coverage of the picks
-            const SampleResult r2 = run_sampler(g, mode, st, a_rp - a_r, a_r, seed, s, false);
-            I.attempts_sampled += a_rp - a_r;
-            SIA_REQUIRE(r2.walks == n_t, SIA_EDEVICE, "stream window does not hold N_t walks");
+            // R'_t: coverage of the picks over the store's walks in [a_r, a_rp)
             SIA_HIP(hipMemsetAsync(bits.ptr, 0, bits.bytes, s));
             SIA_HIP(hipMemcpyAsync(dsel.ptr, sel.data(), sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
             SIA_HIP(hipMemsetAsync(scalar.ptr, 0, sizeof(unsigned long long), s));
             hipLaunchKernelGGL(k_mark_selected, dim3(grid_of(static_cast<uint64_t>(k), 256, 1u << 20)), dim3(256),
                                0, s, dsel.as<int64_t>(), k, bits.as<uint32_t>());
-            hipLaunchKernelGGL(k_cover_walks, dim3(grid_of(r2.walks * kWave, 256, cus * 16)), dim3(256), 0, s,
-                               g->ws.walk_off.as<uint64_t>(), g->ws.walk_len.as<uint32_t>(),
-                               g->ws.ids.as<uint32_t>(), r2.walks, bits.as<uint32_t>(),
+            hipLaunchKernelGGL(k_cover_walks, dim3(grid_of(s_n * kWave, 256, cus * 16)), dim3(256), 0, s,
+                               s_att.as<uint64_t>(), s_off.as<uint64_t>(), s_len.as<uint32_t>(),
+                               s_ids.as<uint32_t>(), s_n, a_r, a_rp, bits.as<uint32_t>(),
                                scalar.as<unsigned long long>());
             SIA_HIP(hipGetLastError());
             const uint64_t cov_rp = read_counter();
