@@ -53,19 +53,18 @@ constexpr uint32_t kHashBits = 14;         // id -> pool position hash, load <= 
 constexpr uint32_t kHash = 1u << kHashBits;
 constexpr uint32_t kFilterBits = 17;       // LDS bit filter of pool ids (false positives <= 1/16)
 // Coverage counting by id ranges (k_bin_sort .. k_bin_count): fine bins of
-// 2^rbits ids, at most kCountBins of them; up to kCountTilesMax tiles of the
-// walk ids.
-constexpr uint32_t kCountBinsLog = 14;
-constexpr uint32_t kCountBins = 1u << kCountBinsLog;
+// 2^kCountSpanLog ids (the LDS counters of one workgroup); up to
+// kCountTilesMax tiles of the walk ids.
 constexpr uint32_t kCountSpanLog = 14;  // LDS counters of one counting pass
 constexpr uint32_t kCountSpan = 1u << kCountSpanLog;
 constexpr uint32_t kCountTilesMax = 512;
 constexpr uint64_t kCountTileMin = 32768;
 constexpr uint32_t kCoarseLog = 8;          // first level: at most 256 coarse bins
 constexpr uint32_t kCoarseMax = 1u << kCoarseLog;
-constexpr uint32_t kFineMax = 1u << (kCountBinsLog - kCoarseLog);  // fine bins per coarse bin
+constexpr uint32_t kFineLog = 10;           // fine bins per coarse bin: id spaces up to 2^32
+constexpr uint32_t kFineMax = 1u << kFineLog;
 constexpr uint32_t kChunk = 8192;           // second level: ids sorted per LDS chunk
-static_assert(kCoarseMax * kFineMax == kCountBins, "two levels span every fine bin");
+static_assert(kCountSpanLog + kCoarseLog + kFineLog >= 32, "two levels span a 32-bit id space");
 constexpr uint32_t kFilterWords = (1u << kFilterBits) / 32;
 static_assert(kHash >= 2 * kPoolMax, "pool hash load factor");
 
@@ -335,8 +334,8 @@ __global__ void k_init(const GreedyJob *jobs)
 // cnt[id] = number of kept walks holding id (the initial Cov of each id),
 // taken without global atomics: random atomics over an id space of 10^8 ids
 // and more miss every cache.  The id space is cut into fine bins of 2^rbits
-// ids (at most kCountBins), grouped into at most kCoarseMax coarse bins of
-// 2^fbits fine bins.  The ids are partitioned in two levels, each narrow
+// ids (one LDS pass each for id spaces up to 2^32), grouped into at most
+// kCoarseMax coarse bins of 2^fbits fine bins.  The ids are partitioned in two levels, each narrow
 // enough that the lines being written stay in L2 until they are whole (a
 // single 2^14-way scatter wrote every 4-byte id as a separate partial line):
 //   k_bin_sort   each tile of the walk ids is split by coarse bin into plist
@@ -452,7 +451,7 @@ template <int T>
 __global__ __launch_bounds__(T) void k_bin_sort2(const GreedyJob *jobs)
 {
     constexpr int U = kChunk / T;  // every load of the chunk in flight at once
-    static_assert(kChunk % T == 0 && kFineMax <= T, "chunk and fine bins per thread");
+    static_assert(kChunk % T == 0 && kFineMax % T == 0, "chunk and fine bins per thread");
     __shared__ uint32_t vpre[kCountTilesMax], vphys[kCountTilesMax];
     __shared__ uint32_t base[kCoarseMax + 1];
     __shared__ uint32_t fh[kFineMax];
@@ -463,7 +462,7 @@ __global__ __launch_bounds__(T) void k_bin_sort2(const GreedyJob *jobs)
     if (g >= J.c_chunks_max) return;  // uniform per block
     const uint32_t C = J.c_coarse, nt = J.c_tiles, F = 1u << J.c_fbits;
     for (uint32_t t = threadIdx.x; t <= C; t += T) base[t] = J.cchunk[t];
-    if (threadIdx.x < kFineMax) fh[threadIdx.x] = 0;
+    for (uint32_t f = threadIdx.x; f < kFineMax; f += T) fh[f] = 0;
     __syncthreads();
     if (g >= base[C]) return;  // uniform: past the last chunk
     const uint32_t c = last_le(base, C + 1, g);  // coarse bin of chunk g
@@ -498,13 +497,24 @@ __global__ __launch_bounds__(T) void k_bin_sort2(const GreedyJob *jobs)
     for (int u = 0; u < U; ++u)
         if (threadIdx.x + u * T < n) atomicAdd(&fh[(x[u] >> rb) & (F - 1)], 1u);
     __syncthreads();
-    const uint32_t mine = threadIdx.x < F ? fh[threadIdx.x] : 0u;
+    // exclusive scan of fh[0 .. F); thread t holds fine bins [t*kPer, (t+1)*kPer)
+    constexpr uint32_t kPer = kFineMax / T;
+    const uint32_t f0 = threadIdx.x * kPer;
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < kPer; ++r) mine += f0 + r < F ? fh[f0 + r] : 0u;
     uint32_t total;
-    const uint32_t ex = block_excl_scan<T>(mine, sh, total);  // ends with a barrier
+    uint32_t run = block_excl_scan<T>(mine, sh, total);  // ends with a barrier
     GLOBAL uint32_t *offs = J.coffs2 + static_cast<uint64_t>(g) * (F + 1);
-    if (threadIdx.x < F) {
-        fh[threadIdx.x] = ex;
-        offs[threadIdx.x] = ex;
+#pragma unroll
+    for (uint32_t r = 0; r < kPer; ++r) {
+        const uint32_t f = f0 + r;
+        if (f < F) {
+            const uint32_t c = fh[f];
+            fh[f] = run;
+            offs[f] = run;
+            run += c;
+        }
     }
     if (threadIdx.x == 0) offs[F] = n;
     __syncthreads();
@@ -1192,10 +1202,11 @@ unsigned grid_for(uint64_t items, unsigned block, unsigned cap)
 
 uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
 
-// Counting plan of a job: fine bins of 2^rbits ids (rbits >= kCountSpanLog,
-// at most kCountBins of them) in at most kCoarseMax coarse bins, tiles of at
-// least kCountTileMin walk ids, and, when there are fewer than kCountBinsFull
-// fine bins, several workgroups per fine bin.
+// Counting plan of a job: fine bins of 2^rbits ids (rbits = kCountSpanLog,
+// so each is one LDS pass) in at most kCoarseMax coarse bins of at most
+// kFineMax fine bins, tiles of at least kCountTileMin walk ids, and, when
+// there are fewer than kCountBinsFull fine bins, several workgroups per fine
+// bin.
 constexpr uint32_t kCountBinsFull = 256;
 struct CountPlan {
     uint32_t rbits, bins, fbits, coarse, tiles, parts, chunks_max;
@@ -1211,9 +1222,8 @@ uint32_t ceil_log2(uint64_t x)
 }
 CountPlan count_plan(uint64_t S, uint64_t n_ids)
 {
-    const uint32_t L = ceil_log2(S);
     CountPlan P;
-    P.rbits = std::max(kCountSpanLog, L > kCountBinsLog ? L - kCountBinsLog : 0u);
+    P.rbits = kCountSpanLog;
     P.bins = static_cast<uint32_t>((S + (uint64_t(1) << P.rbits) - 1) >> P.rbits);
     const uint32_t Lb = ceil_log2(P.bins);
     P.fbits = Lb > kCoarseLog ? Lb - kCoarseLog : 0u;

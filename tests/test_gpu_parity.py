@@ -351,20 +351,20 @@ def test_greedy_empty_and_exhaustive(sia):
     assert sel.tolist() == [1, 3, 0, 2, 4, 5] and gains.tolist() == [1, 1, 0, 0, 0, 0]
 
 
-@pytest.mark.parametrize("case", ["few_bins", "sub_passes", "many_tiles"])
+@pytest.mark.parametrize("case", ["few_bins", "wide", "many_tiles"])
 def test_greedy_counts_exact(sia, case):
     """Walks of one id each: covering an id then lowers no other id's count,
     so the greedy takes ids by count (ties by ascending id, then the lowest
     ids of count 0) and each gain is the id's count -- the counting pass is
     checked id by id.  few_bins: 300 ids, 3*10^6 walks (each range of ids is
-    counted by several workgroups); sub_passes: an id space above 2^30 (ranges
-    wider than one LDS pass), both ends of it used; many_tiles: 2*10^7 walks
+    counted by several workgroups); wide: an id space above 2^30 (512 fine
+    ranges per coarse range), both ends of it used; many_tiles: 2*10^7 walks
     over 2^24 + 3 ids (the most tiles)."""
-    rng = np.random.default_rng({"few_bins": 11, "sub_passes": 12, "many_tiles": 13}[case])
+    rng = np.random.default_rng({"few_bins": 11, "wide": 12, "many_tiles": 13}[case])
     if case == "few_bins":
         S, k = 300, 300
         ids = np.minimum(rng.zipf(1.3, 3_000_000) - 1, S - 1)
-    elif case == "sub_passes":
+    elif case == "wide":
         S, k = (1 << 30) + 5, 3000
         hot = rng.integers(0, S, 2000)
         ids = np.concatenate([rng.integers(0, S, 1_000_000), hot[rng.integers(0, 2000, 1_000_000)],
