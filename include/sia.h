@@ -206,6 +206,24 @@ sia_status sia_solve(const sia_graph *g, int mode, const int32_t *sources,
                      uint64_t attempt_offset, uint64_t seed, int64_t *selected,
                      uint64_t *gains, sia_stats *stats, int timing, void *hip_stream);
 
+/*
+ * sia_solve with a candidate set C (Definitions "edge_remove" /
+ * "node_remove": the k ids are chosen from C within E or V; Algorithm 4 / 7
+ * take the argmax over C minus the ids already chosen).  Coverage and the
+ * estimates are as in sia_solve; ties go to the lowest candidate id, and
+ * once every gain is zero the lowest unselected candidates follow.
+ *   candidates  host int64[n_candidates]: distinct ids in [0, m) (edges) or
+ *               [0, n) (nodes), any order; k <= n_candidates
+ * Errors as sia_solve (SIA_EINVAL for a NULL, repeated or out-of-range
+ * candidate, or fewer candidates than k).
+ */
+sia_status sia_solve_candidates(const sia_graph *g, int mode, const int32_t *sources,
+                                int64_t n_sources, const int64_t *candidates,
+                                int64_t n_candidates, int64_t k, uint64_t n_attempts,
+                                uint64_t attempt_offset, uint64_t seed, int64_t *selected,
+                                uint64_t *gains, sia_stats *stats, int timing,
+                                void *hip_stream);
+
 /* Figures of a Stop-and-Stare run (sia_sas_solve). */
 typedef struct {
     int32_t status;        /* 1: Check passed at iteration t; 0: |R_t| reached

@@ -311,10 +311,11 @@ sia_status sia_greedy(int64_t id_space, const uint64_t *walk_off, const uint32_t
     });
 }
 
-sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
-                     int64_t k, uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
-                     int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
-                     void *hip_stream)
+static sia_status solve_impl(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
+                             const int64_t *candidates, int64_t n_candidates, int64_t k,
+                             uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
+                             int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
+                             void *hip_stream)
 {
     return guarded([&] {
         SIA_REQUIRE(cg != nullptr && selected != nullptr && gains != nullptr, SIA_EINVAL,
@@ -322,6 +323,19 @@ sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int6
         sia_graph *g = const_cast<sia_graph *>(cg);
         check_query(g->n, g->m, mode, sources, n_sources, k, n_attempts, attempt_offset);
         SIA_REQUIRE(k >= 1, SIA_EINVAL, "k must be >= 1");
+        const int64_t id_space_c = mode == SIA_EDGES ? cg->m : cg->n;
+        std::vector<uint32_t> cand_bits;
+        if (candidates) {
+            SIA_REQUIRE(n_candidates >= k, SIA_EINVAL, "fewer candidates than k");
+            cand_bits.assign(static_cast<size_t>((id_space_c + 31) / 32), 0u);
+            for (int64_t i = 0; i < n_candidates; ++i) {
+                const int64_t x = candidates[i];
+                SIA_REQUIRE(x >= 0 && x < id_space_c, SIA_EINVAL, "a candidate is outside the id space");
+                uint32_t &w = cand_bits[static_cast<size_t>(x >> 5)];
+                SIA_REQUIRE(!((w >> (x & 31)) & 1u), SIA_EINVAL, "candidates must be distinct");
+                w |= 1u << (x & 31);
+            }
+        }
         std::lock_guard<std::mutex> lock(g->mu);
         DeviceScope ds(g->device);
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -337,8 +351,13 @@ sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int6
         // with its gathers)
         const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, timing != 0);
         const int64_t id_space = mode == SIA_EDGES ? g->m : g->n;
+        DevBuf d_cand;
+        if (candidates) {
+            d_cand.ensure(4 * cand_bits.size());
+            SIA_HIP(hipMemcpyAsync(d_cand.ptr, cand_bits.data(), 4 * cand_bits.size(), hipMemcpyHostToDevice, s));
+        }
         const GreedyResult gr = run_greedy(g->ws, id_space, r.walks, r.ids, k, selected, gains, s,
-                                           timing != 0);
+                                           timing != 0, candidates ? d_cand.as<uint32_t>() : nullptr);
         float ms_total = 0.f;
         if (timing) {
             SIA_HIP(hipEventRecord(e1, s));
@@ -363,6 +382,29 @@ sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int6
             *stats = S;
         }
     });
+}
+
+sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
+                     int64_t k, uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
+                     int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
+                     void *hip_stream)
+{
+    return solve_impl(cg, mode, sources, n_sources, nullptr, 0, k, n_attempts, attempt_offset, seed,
+                      selected, gains, stats, timing, hip_stream);
+}
+
+sia_status sia_solve_candidates(const sia_graph *cg, int mode, const int32_t *sources,
+                                int64_t n_sources, const int64_t *candidates, int64_t n_candidates,
+                                int64_t k, uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
+                                int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
+                                void *hip_stream)
+{
+    if (!candidates) {
+        sia::set_error("candidates is NULL");
+        return SIA_EINVAL;
+    }
+    return solve_impl(cg, mode, sources, n_sources, candidates, n_candidates, k, n_attempts,
+                      attempt_offset, seed, selected, gains, stats, timing, hip_stream);
 }
 
 }  // extern "C"

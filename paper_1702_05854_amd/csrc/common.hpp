@@ -187,6 +187,7 @@ struct GreedyInput {
     uint64_t id_space = 0, n_walks = 0, n_ids = 0;
     int64_t k = 0;
     uint32_t *cnt = nullptr;    // id_space coverage counts (device), written here
+    const uint32_t *cand = nullptr;  // candidate bitmap over [0, id_space) (device); NULL: every id
     void *scratch = nullptr;
     int64_t *selected = nullptr;  // k entries each; host memory
     uint64_t *gains = nullptr;
@@ -204,10 +205,11 @@ void run_greedy_jobs(std::vector<GreedyInput> &jobs, void *d_job_table, hipStrea
                      GreedyResult *res, unsigned hist_base = 0);
 
 // A single job over the walks held in ws (walk_off / walk_len / ids, n_walks
-// walks, n_ids ids); the counts go to ws.cnt.
+// walks, n_ids ids); the counts go to ws.cnt.  cand: candidate bitmap
+// (device, NULL: every id); the caller guarantees at least k candidates.
 GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
                         int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s,
-                        bool timing);
+                        bool timing, const uint32_t *cand = nullptr);
 
 // Ingest: host structure checks (no device needed) and the device kernels.
 void host_check_structure(int64_t n, int64_t m, const int64_t *col_off, const int32_t *row_idx);

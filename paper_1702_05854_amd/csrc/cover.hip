@@ -122,6 +122,7 @@ struct GreedyJob {
     uint32_t *cchunk;   // c_coarse + 1: first chunk of each coarse bin
     uint32_t *coffs2;   // c_chunks_max x (2^c_fbits + 1): fine-bin starts in a chunk
     uint32_t *cbuf;     // c_chunks_max x kChunk: chunks sorted by fine bin
+    const uint32_t *cand;  // candidate bitmap over [0, S) (NULL: every id)
     int64_t *sel;       // k
     uint64_t *gain;     // k
     uint32_t *hist;     // kBins
@@ -154,6 +155,7 @@ struct GJob {
     GLOBAL uint32_t *cchunk;
     GLOBAL uint32_t *coffs2;
     GLOBAL uint32_t *cbuf;
+    const GLOBAL uint32_t *cand;
     GLOBAL int64_t *sel;
     GLOBAL uint64_t *gain;
     GLOBAL uint32_t *hist;
@@ -194,6 +196,7 @@ __device__ __forceinline__ GJob view(const GreedyJob &j)
     J.cchunk = gp(j.cchunk);
     J.coffs2 = gp(j.coffs2);
     J.cbuf = gp(j.cbuf);
+    J.cand = j.cand ? gp(j.cand) : nullptr;
     J.sel = gp(j.sel);
     J.gain = gp(j.gain);
     J.hist = gp(j.hist);
@@ -587,6 +590,19 @@ __global__ __launch_bounds__(T) void k_bin_count(const GreedyJob *jobs)
         }
         __syncthreads();
     }
+}
+
+// Candidate sets (C within E or V, Definitions "edge_remove" / "node_remove"):
+// an id outside C is marked selected once counted, so no pool, histogram or
+// tie plan ever holds it and the greedy picks only from C.
+__global__ __launch_bounds__(256) void k_apply_cand(const GreedyJob *jobs)
+{
+    const GJob J = view(jobs[blockIdx.y]);
+    if (!J.cand) return;  // uniform per block
+    uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (; i < J.S; i += stride)
+        if (!((J.cand[i >> 5] >> (i & 31)) & 1u)) J.cnt[i] = kSelected;
 }
 
 // ---------------------------------------------------------------- pool rebuild
@@ -1174,7 +1190,15 @@ __global__ __launch_bounds__(256) void k_uncover(const GreedyJob *jobs)
         const uint32_t w = J.claimed[c];
         const uint64_t o = J.walk_off[w];
         const uint32_t L = J.walk_len[w];
-        for (uint32_t e = lane; e < L; e += kWave) g_add(&J.cnt[J.ids[o + e]], 0xFFFFFFFFu);
+        if (J.cand) {
+            // ids outside the candidate set are marked selected: leave them so
+            for (uint32_t e = lane; e < L; e += kWave) {
+                const uint32_t x = J.ids[o + e];
+                if (J.cnt[x] != kSelected) g_add(&J.cnt[x], 0xFFFFFFFFu);
+            }
+        } else {
+            for (uint32_t e = lane; e < L; e += kWave) g_add(&J.cnt[J.ids[o + e]], 0xFFFFFFFFu);
+        }
     }
 }
 
@@ -1282,6 +1306,7 @@ GreedyJob carve(const GreedyInput &g)
     J.c_chunks_max = P.chunks_max;
     J.c_tile_len = P.tile_len;
     J.cnt = g.cnt;
+    J.cand = g.cand;
     J.walk_off = g.walk_off;
     J.walk_len = g.walk_len;
     J.ids = g.ids;
@@ -1365,6 +1390,10 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     hipLaunchKernelGGL(k_bin_bases<256>, dim3(1, Q), dim3(256), 0, s, d_jobs);
     hipLaunchKernelGGL(k_bin_sort2<256>, dim3(max_chunks, Q), dim3(256), 0, s, d_jobs);
     hipLaunchKernelGGL(k_bin_count<1024>, dim3(max_bins, Q), dim3(1024), 0, s, d_jobs);
+    bool any_cand = false;
+    for (uint32_t q = 0; q < Q; ++q) any_cand = any_cand || in[q].cand != nullptr;
+    if (any_cand)
+        hipLaunchKernelGGL(k_apply_cand, dim3(grid_for(max_S, 256, cus * 8), Q), dim3(256), 0, s, d_jobs);
     SIA_HIP(hipGetLastError());
     if (timing) SIA_HIP(hipEventRecord(ev[1], s));
 
@@ -1425,7 +1454,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
 }
 
 GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint64_t n_ids,
-                        int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s, bool timing)
+                        int64_t k, int64_t *selected, uint64_t *gains, hipStream_t s, bool timing,
+                        const uint32_t *cand)
 {
     const uint64_t S = static_cast<uint64_t>(id_space);
     ws.greedy.ensure(greedy_scratch_bytes(S, n_walks, n_ids, k));
@@ -1442,6 +1472,7 @@ GreedyResult run_greedy(Workspace &ws, int64_t id_space, uint64_t n_walks, uint6
     g.k = k;
     g.cnt = ws.cnt.as<uint32_t>();
     g.scratch = ws.greedy.ptr;
+    g.cand = cand;
     g.selected = selected;
     g.gains = gains;
     GreedyResult res;

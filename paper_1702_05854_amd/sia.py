@@ -137,6 +137,8 @@ def lib():
         L.sia_batch_cancel.argtypes = [p, u64]
         L.sia_batch_stats_get.argtypes = [p, C.POINTER(BatchStats)]
         L.sia_batch_tune.argtypes = [p, C.POINTER(Query), C.c_double, C.POINTER(BatchConfig)]
+        L.sia_solve_candidates.argtypes = [p, i32, p, i64, p, i64, i64, u64, u64, u64, p, p,
+                                           C.POINTER(Stats), i32, p]
         L.sia_sas_solve.argtypes = [p, i32, p, i64, i64, C.c_double, C.c_double, u64, u64, p, p,
                                     C.POINTER(SasInfo), p]
         L.sia_probe_gather.argtypes = [u64, C.c_uint32, i32, C.POINTER(C.c_double),
@@ -144,7 +146,8 @@ def lib():
         for name in ("sia_check_query", "sia_graph_create", "sia_graph_destroy", "sia_graph_info",
                      "sia_graph_thresholds", "sia_graph_arc_bytes", "sia_quantize", "sia_sample",
                      "sia_greedy",
-                     "sia_solve", "sia_sas_solve", "sia_probe_gather") + BATCH_SYMBOLS:
+                     "sia_solve", "sia_solve_candidates", "sia_sas_solve",
+                     "sia_probe_gather") + BATCH_SYMBOLS:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -279,14 +282,23 @@ def greedy(id_space, walk_off, ids, k, stream=None):
 
 
 def solve(graph: Graph, sources, mode, k, n_attempts, attempt_offset=0, seed=2017, timing=False,
-          stream=None):
+          stream=None, candidates=None):
+    """The whole path for one query; candidates (ids the picks are drawn
+    from) calls sia_solve_candidates."""
     src = _host(sources, np.int32)
     sel = np.zeros(k, dtype=np.int64)
     gains = np.zeros(k, dtype=np.uint64)
     st = Stats()
-    _check(lib().sia_solve(graph.handle, MODES[mode], _hptr(src), src.shape[0], k, n_attempts,
-                           attempt_offset, seed, _hptr(sel), _hptr(gains), C.byref(st),
-                           1 if timing else 0, _stream(stream)))
+    if candidates is None:
+        _check(lib().sia_solve(graph.handle, MODES[mode], _hptr(src), src.shape[0], k, n_attempts,
+                               attempt_offset, seed, _hptr(sel), _hptr(gains), C.byref(st),
+                               1 if timing else 0, _stream(stream)))
+    else:
+        cand = _host(candidates, np.int64)
+        _check(lib().sia_solve_candidates(graph.handle, MODES[mode], _hptr(src), src.shape[0],
+                                          _hptr(cand), cand.shape[0], k, n_attempts, attempt_offset,
+                                          seed, _hptr(sel), _hptr(gains), C.byref(st),
+                                          1 if timing else 0, _stream(stream)))
     return dict(selected=sel, gains=gains, stats=st.as_dict())
 
 
