@@ -274,6 +274,23 @@ sia_status sia_sas_solve(const sia_graph *g, int mode, const int32_t *sources,
                          uint64_t *gains, sia_sas_info *info, void *hip_stream);
 
 /*
+ * Evaluate a chosen set on its own sample (the out-of-sample estimate the
+ * experiments use to score solutions, Section 6.1, here from HSAWs instead
+ * of the external estimator the paper cites): sample attempts
+ * [attempt_offset, attempt_offset + n_attempts) of seed as sia_sample and
+ * count the kept walks holding at least one selected id.
+ *   selected  host int64[k] ids in [0, m) (edges) or [0, n) (nodes)
+ *   stats     host (out): the sampler's counters, covered = walks hit by the
+ *             set, and the estimates of sia_solve (suspension_est =
+ *             |V\X| * covered / N); times are 0
+ * Errors as sia_solve.
+ */
+sia_status sia_evaluate(const sia_graph *g, int mode, const int32_t *sources,
+                        int64_t n_sources, const int64_t *selected, int64_t k,
+                        uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
+                        sia_stats *stats, void *hip_stream);
+
+/*
  * Measuring hook (not part of the method): the device's random-gather
  * ceiling.  Fills a device array of array_bytes (1 MiB .. 16 GiB) and times
  * one launch, at full occupancy, in which every lane makes loads_per_lane

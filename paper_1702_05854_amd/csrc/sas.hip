@@ -416,4 +416,60 @@ sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, 
     });
 }
 
+sia_status sia_evaluate(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
+                        const int64_t *selected, int64_t k, uint64_t n_attempts, uint64_t attempt_offset,
+                        uint64_t seed, sia_stats *stats, void *hip_stream)
+{
+    return guarded([&] {
+        SIA_REQUIRE(cg != nullptr && selected != nullptr && stats != nullptr, SIA_EINVAL, "NULL argument");
+        sia_graph *g = const_cast<sia_graph *>(cg);
+        check_query(g->n, g->m, mode, sources, n_sources, k, n_attempts, attempt_offset);
+        SIA_REQUIRE(k >= 1, SIA_EINVAL, "k must be >= 1");
+        const int64_t S = mode == SIA_EDGES ? g->m : g->n;
+        for (int64_t i = 0; i < k; ++i)
+            SIA_REQUIRE(selected[i] >= 0 && selected[i] < S, SIA_EINVAL, "a selected id is outside the id space");
+        std::lock_guard<std::mutex> lock(g->mu);
+        DeviceScope ds(g->device);
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        const SourceTables st = build_source_tables(g->n, sources, n_sources);
+        const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, false);
+        DevBuf scalar, bits, dsel;
+        scalar.ensure(sizeof(unsigned long long));
+        bits.ensure(4 * ((static_cast<uint64_t>(S) + 31) / 32));
+        dsel.ensure(sizeof(int64_t) * static_cast<uint64_t>(k));
+        SIA_HIP(hipMemsetAsync(bits.ptr, 0, bits.bytes, s));
+        SIA_HIP(hipMemsetAsync(scalar.ptr, 0, sizeof(unsigned long long), s));
+        SIA_HIP(hipMemcpyAsync(dsel.ptr, selected, sizeof(int64_t) * k, hipMemcpyHostToDevice, s));
+        const unsigned cus = static_cast<unsigned>(device_cu_count());
+        hipLaunchKernelGGL(k_mark_selected, dim3(grid_of(static_cast<uint64_t>(k), 256, 1u << 20)), dim3(256), 0,
+                           s, dsel.as<int64_t>(), k, bits.as<uint32_t>());
+        hipLaunchKernelGGL(k_cover_walks, dim3(grid_of(r.walks * kWave, 256, cus * 16)), dim3(256), 0, s,
+                           g->ws.walk_attempt.as<uint64_t>(), g->ws.walk_off.as<uint64_t>(),
+                           g->ws.walk_len.as<uint32_t>(), g->ws.ids.as<uint32_t>(), r.walks, uint64_t(0),
+                           ~uint64_t(0), bits.as<uint32_t>(), scalar.as<unsigned long long>());
+        SIA_HIP(hipGetLastError());
+        unsigned long long covered = 0;
+        SIA_HIP(hipMemcpyAsync(&covered, scalar.ptr, sizeof(covered), hipMemcpyDeviceToHost, s));
+        SIA_HIP(hipStreamSynchronize(s));
+        sia_stats R{};
+        R.attempts = n_attempts;
+        R.hits = r.hits;
+        R.dead_ends = r.dead;
+        R.cycles = r.cycles;
+        R.steps = r.steps;
+        R.evaluations = r.evals;
+        R.walk_ids = r.ids;
+        R.covered = covered;
+        const double n_ns = static_cast<double>(g->n - n_sources);
+        R.spread_est = static_cast<double>(n_sources) + n_ns * static_cast<double>(r.hits) / n_attempts;
+        R.suspension_est = n_ns * static_cast<double>(covered) / n_attempts;
+        uint64_t in_x = 0;
+        if (mode == SIA_NODES)
+            for (int64_t i = 0; i < k; ++i)
+                in_x += std::binary_search(st.sorted.begin(), st.sorted.end(), static_cast<int32_t>(selected[i]));
+        R.suspension_nodes_est = R.suspension_est + static_cast<double>(in_x);
+        *stats = R;
+    });
+}
+
 }  // extern "C"

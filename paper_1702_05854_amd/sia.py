@@ -139,6 +139,7 @@ def lib():
         L.sia_batch_tune.argtypes = [p, C.POINTER(Query), C.c_double, C.POINTER(BatchConfig)]
         L.sia_solve_candidates.argtypes = [p, i32, p, i64, p, i64, i64, u64, u64, u64, p, p,
                                            C.POINTER(Stats), i32, p]
+        L.sia_evaluate.argtypes = [p, i32, p, i64, p, i64, u64, u64, u64, C.POINTER(Stats), p]
         L.sia_sas_solve.argtypes = [p, i32, p, i64, i64, C.c_double, C.c_double, u64, u64, p, p,
                                     C.POINTER(SasInfo), p]
         L.sia_probe_gather.argtypes = [u64, C.c_uint32, i32, C.POINTER(C.c_double),
@@ -146,7 +147,7 @@ def lib():
         for name in ("sia_check_query", "sia_graph_create", "sia_graph_destroy", "sia_graph_info",
                      "sia_graph_thresholds", "sia_graph_arc_bytes", "sia_quantize", "sia_sample",
                      "sia_greedy",
-                     "sia_solve", "sia_solve_candidates", "sia_sas_solve",
+                     "sia_solve", "sia_solve_candidates", "sia_sas_solve", "sia_evaluate",
                      "sia_probe_gather") + BATCH_SYMBOLS:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -300,6 +301,17 @@ def solve(graph: Graph, sources, mode, k, n_attempts, attempt_offset=0, seed=201
                                           seed, _hptr(sel), _hptr(gains), C.byref(st),
                                           1 if timing else 0, _stream(stream)))
     return dict(selected=sel, gains=gains, stats=st.as_dict())
+
+
+def evaluate(graph: Graph, sources, mode, selected, n_attempts, attempt_offset=0, seed=2017,
+             stream=None):
+    """Counters and estimates of a chosen set on its own sample (sia_evaluate)."""
+    src = _host(sources, np.int32)
+    sel = _host(selected, np.int64)
+    st = Stats()
+    _check(lib().sia_evaluate(graph.handle, MODES[mode], _hptr(src), src.shape[0], _hptr(sel), sel.shape[0],
+                              n_attempts, attempt_offset, seed, C.byref(st), _stream(stream)))
+    return st.as_dict()
 
 
 def sas_solve(graph: Graph, sources, mode, k, eps=0.1, delta=None, seed=2017,

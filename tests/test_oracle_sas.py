@@ -97,3 +97,19 @@ def test_driver_follows_the_stream(er1k, mode):
             assert ok == (r["status"] == "passed")
             assert np.array_equal(sel, r["selected"]) and np.array_equal(gains, r["gains"])
             assert covp == r["cov_rp"] and int(gains.sum()) == r["cov_r"]
+
+
+@pytest.mark.parametrize("mode", [cpu.MODE_EDGES, cpu.MODE_NODES])
+def test_evaluation_on_the_greedy_sample_is_its_coverage(er1k, mode):
+    """Evaluated on the very sample the greedy chose from, a set covers
+    exactly the sum of its marginal gains (Algorithm 4 / 7); on a second seed
+    the estimate agrees with the first within sampling error."""
+    from oracle import evaluate
+    wl, g = er1k
+    r = cpu.solve(g, wl.sources, mode, wl.k, 50_000, 0, wl.seed)
+    same = evaluate.evaluate(g, wl.sources, mode, r["selected"], 50_000, 0, wl.seed)
+    assert same["covered"] == int(r["gains"].sum()) and same["walks"].hits == r["walks"].hits
+    other = evaluate.evaluate(g, wl.sources, mode, r["selected"], 200_000, 0, wl.seed + 1)
+    p = other["covered"] / 200_000
+    sd = math.sqrt(p * (1 - p) / 200_000) + math.sqrt(p * (1 - p) / 50_000)
+    assert abs(same["covered"] / 50_000 - p) < 6 * sd + 1e-9
