@@ -223,6 +223,49 @@ def sas_bench(args, sia, wl, g, mode, k, ingest_ms):
     print(json.dumps(out), flush=True)
 
 
+def sweep_bench(args):
+    """Scalability sweep (the shape of the paper's scalability experiment,
+    Section 6.3): uniform random graphs with n from 10^4 up to --sweep-max
+    nodes and m/n in {5, 10, 15}, w = 1/d_in, n/1000 sources (at least 10),
+    k = 100 edges, 10^7 attempts per point (fewer where the kept walks would
+    hold more than 2^30 ids); whole-path attempts/s."""
+    import torch
+    from paper_1702_05854_amd import sia, workloads
+
+    torch.cuda.set_device(0)
+    rows = []
+    n = 10_000
+    while n <= args.sweep_max:
+        for ratio in (5, 10, 15):
+            wl = workloads.load("er1k", device="cuda", n=n, m=n * ratio, n_src=max(10, n // 1000), k=100,
+                                gseed=11 + ratio, sseed=211)
+            g = sia.Graph(wl.col_off, wl.row_idx, wl.w)
+            # pilot (also the warm-up): walks on these graphs can be long, so the
+            # attempts are capped to keep the kept walks' ids within 2^30
+            pilot = sia.solve(g, wl.sources, "edges", 100, 100_000, 0, wl.seed)["stats"]
+            ids_per_attempt = max(pilot["walk_ids"], 1) / 100_000
+            N = int(min(10_000_000, max(100_000, (1 << 30) / ids_per_attempt)))
+            sia.solve(g, wl.sources, "edges", 100, N, 0, wl.seed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sia.solve(g, wl.sources, "edges", 100, N, 0, wl.seed, timing=True)
+            dt = time.perf_counter() - t0
+            st = r["stats"]
+            rows.append({"n": n, "m": wl.m, "m_over_n": ratio, "attempts": N, "ms": dt * 1e3,
+                         "attempts_per_s": N / dt, "hits": st["hits"], "steps": st["steps"],
+                         "ms_sample": st["ms_sample"], "ms_count": st["ms_count"], "ms_greedy": st["ms_greedy"]})
+            print(f"[bench] sweep n={n} m={wl.m}: {N / dt / 1e6:.1f}M attempts/s", file=sys.stderr, flush=True)
+            g.close()
+            del wl, g
+            torch.cuda.empty_cache()
+        n *= 10
+    out = {"metric": "HSAW attempts/s across graph sizes (scalability sweep, whole path, edges)",
+           "unit": "attempts/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "uniform random graphs, w = 1/d_in, up to 10^7 attempts, k = 100"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +292,9 @@ def main():
     ap.add_argument("--sas", action="store_true",
                     help="time the Stop-and-Stare driver (eSIA / nSIA) on the workload instead")
     ap.add_argument("--eps", type=float, default=0.1, help="epsilon of the Stop-and-Stare driver (--sas)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="scalability sweep: attempts/s on random graphs, n = 10^4 .. --sweep-max, m/n = 5, 10, 15")
+    ap.add_argument("--sweep-max", type=int, default=10_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -256,6 +302,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_bench(args)
+        return
+    if args.sweep:
+        sweep_bench(args)
         return
 
     import torch
