@@ -338,9 +338,10 @@ __global__ void k_init(const GreedyJob *jobs)
 // taken without global atomics: random atomics over an id space of 10^8 ids
 // and more miss every cache.  The id space is cut into fine bins of 2^rbits
 // ids (one LDS pass each for id spaces up to 2^32), grouped into at most
-// kCoarseMax coarse bins of 2^fbits fine bins.  The ids are partitioned in two levels, each narrow
-// enough that the lines being written stay in L2 until they are whole (a
-// single 2^14-way scatter wrote every 4-byte id as a separate partial line):
+// kCoarseMax coarse bins of 2^fbits fine bins.  The ids are partitioned in
+// two levels, each narrow enough that the lines being written stay in L2
+// until they are whole (a single 2^14-way scatter wrote every 4-byte id as a
+// separate partial line):
 //   k_bin_sort   each tile of the walk ids is split by coarse bin into plist
 //                (unused until the first pool is filled); coffs records where
 //                each of the tile's coarse bins starts;

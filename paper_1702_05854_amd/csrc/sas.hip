@@ -6,7 +6,7 @@
 // seen so far) and appends each chunk's kept walks to a device store, in
 // sampling order (unordered within a chunk).  A walk is a function of (seed,
 // attempt id), so R_t is exactly the stored walks with attempt id below a
-// bound A and R'_t those in [A, A'): the bounds are found by bisection over
+// bound A and R'_t those in [A, A'): the bounds are read off histograms of
 // the stored attempt ids, R_t is compacted into the greedy's input, and the
 // coverage of the picks is counted over the store's walks in [A, A').  The
 // scalar steps of Check run on the host.
@@ -21,20 +21,20 @@ namespace {
 
 constexpr int kWave = 64;
 
-// n_out += #{i : att[i] < x}
-__global__ __launch_bounds__(256) void k_count_below(const uint64_t *att, uint64_t n, uint64_t x,
-                                                     unsigned long long *n_out)
+// h[(att[i] >> shift) - base] += 1 for the stored attempt ids with
+// att[i] >> high == top (all of them when high >= 64), for indices below nbins
+__global__ __launch_bounds__(256) void k_att_hist(const uint64_t *att, uint64_t n, uint32_t high, uint64_t top,
+                                                  uint32_t shift, uint64_t base, uint32_t nbins, uint32_t *h)
 {
     const GLOBAL uint64_t *a = gp(att);
     uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    uint32_t c = 0;
-    for (; i < n; i += stride) c += a[i] < x ? 1u : 0u;
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) c += __shfl_xor(c, d, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0 && c)
-        __hip_atomic_fetch_add(gp(n_out), static_cast<unsigned long long>(c), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    for (; i < n; i += stride) {
+        const uint64_t x = a[i];
+        if (high < 64 && (x >> high) != top) continue;
+        const uint64_t b = (x >> shift) - base;
+        if (b < nbins) __hip_atomic_fetch_add(gp(h) + b, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // set bit id of every selected id (bits cleared beforehand)
@@ -287,22 +287,40 @@ sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, 
             SIA_HIP(hipStreamSynchronize(s));
             return static_cast<uint64_t>(v);
         };
-        auto count_below = [&](uint64_t x) {
-            SIA_HIP(hipMemsetAsync(scalar.ptr, 0, sizeof(unsigned long long), s));
-            hipLaunchKernelGGL(k_count_below, dim3(grid_of(s_n, 256, cus * 4)), dim3(256), 0, s,
-                               s_att.as<uint64_t>(), s_n, x, scalar.as<unsigned long long>());
+        // smallest A with N stream walks among attempts [0, A): the N-th
+        // smallest stored attempt id plus one, by a two-level histogram of
+        // the ids (high bits, then the low bits within the chosen bin)
+        DevBuf hist;
+        constexpr uint32_t kHistBits = 16;
+        hist.ensure(sizeof(uint32_t) << kHistBits);
+        std::vector<uint32_t> hh(size_t(1) << kHistBits);
+        auto histogram = [&](uint32_t high, uint64_t top, uint32_t shift, uint64_t base, uint32_t nbins) {
+            SIA_HIP(hipMemsetAsync(hist.ptr, 0, sizeof(uint32_t) * nbins, s));
+            hipLaunchKernelGGL(k_att_hist, dim3(grid_of(s_n, 256, cus * 4)), dim3(256), 0, s, s_att.as<uint64_t>(),
+                               s_n, high, top, shift, base, nbins, hist.as<uint32_t>());
             SIA_HIP(hipGetLastError());
-            return read_counter();
+            SIA_HIP(hipMemcpyAsync(hh.data(), hist.ptr, sizeof(uint32_t) * nbins, hipMemcpyDeviceToHost, s));
+            SIA_HIP(hipStreamSynchronize(s));
         };
-        // smallest A with N stream walks among attempts [0, A)
-        auto bound = [&](uint64_t N) {
-            uint64_t lo = 0, hi = end;  // #below(lo) < N <= #below(hi)
-            while (hi - lo > 1) {
-                const uint64_t mid = lo + (hi - lo) / 2;
-                if (count_below(mid) >= N) hi = mid;
-                else lo = mid;
+        auto bounds = [&](uint64_t N1, uint64_t N2, uint64_t *A1, uint64_t *A2) {
+            uint32_t L = 0;  // attempt ids are below end <= 2^L
+            while ((uint64_t(1) << L) < end) ++L;
+            const uint32_t lo_bits = L > kHistBits ? L - kHistBits : 0;
+            histogram(64, 0, lo_bits, 0, 1u << kHistBits);
+            const std::vector<uint32_t> top = hh;
+            for (int q = 0; q < 2; ++q) {
+                const uint64_t N = q == 0 ? N1 : N2;
+                uint64_t acc = 0, b = 0;
+                while (acc + top[b] < N) acc += top[b++];  // bin of the N-th smallest
+                uint64_t v = b << lo_bits;
+                if (lo_bits) {
+                    histogram(lo_bits, b, 0, b << lo_bits, 1u << lo_bits);
+                    uint64_t r = 0;
+                    while (acc + hh[r] < N) acc += hh[r++];
+                    v += r;
+                }
+                *(q == 0 ? A1 : A2) = v + 1;
             }
-            return hi;
         };
 
         for (int t = 1;; ++t) {
@@ -350,7 +368,8 @@ sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, 
             }
             SIA_REQUIRE(s_n < 0xFFFFFFFFull && s_ni < 0xFFFFFFFFull, SIA_EINVAL,
                         "the stream outgrew 32-bit walk and id positions");
-            const uint64_t a_r = bound(n_t), a_rp = bound(2 * n_t);
+            uint64_t a_r = 0, a_rp = 0;
+            bounds(n_t, 2 * n_t, &a_r, &a_rp);
             // R_t: compact the store's walks below a_r into the greedy's input
             const uint64_t nb = (s_n + kSelT - 1) / kSelT;
             blk.ensure(4 * (2 * nb + 2));
