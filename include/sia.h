@@ -85,7 +85,7 @@ typedef struct {
 typedef struct {
     uint64_t n_walks;  /* kept HSAWs */
     uint64_t n_ids;
-    uint64_t *attempt; /* [n_walks] attempt id of each kept walk (unordered) */
+    uint64_t *attempt; /* [n_walks] attempt id of each kept walk, ascending */
     uint64_t *off;     /* [n_walks+1] offsets into ids */
     uint32_t *ids;     /* [n_ids] edges: CSC positions j_1..j_{l-1} (walk
                           order from the start); nodes: v_1..v_l */
@@ -257,8 +257,13 @@ typedef struct {
  * the next N_t as R'_t, picks k ids by the greedy on R_t and verifies them
  * on R'_t with Check (Algorithm 5 / 8); it stops when Check passes or
  * N_t >= N_max.  t_max reads the iteration lemma's Upsilon(eps, delta/3)
- * (the displayed formula takes the logarithm of delta/3).  Every iteration
- * samples R_t and R'_t afresh (a walk is a function of its attempt id).
+ * (the displayed formula takes the logarithm of delta/3); the parameters
+ * and Check are those of sia_sas_params and sia_sas_check.  The driver
+ * samples the attempts [0, end) once, in growing chunks, into a device
+ * store of kept walks; a walk is a function of its attempt id, so R_t is
+ * the stored walks with attempt id below a bound A and R'_t those in
+ * [A, A'), the bounds being the N_t-th and 2 N_t-th smallest stored
+ * attempt ids plus one.  Walks are never sampled twice.
  *   eps        in (0, 1 - 1/e); delta in (0, 1) (the paper uses 1/n)
  *   max_attempts  in [1, 2^32): the attempts the stream may use
  *   selected   host int64[k] (out), gains host uint64[k] (out): the last
@@ -272,6 +277,39 @@ sia_status sia_sas_solve(const sia_graph *g, int mode, const int32_t *sources,
                          int64_t n_sources, int64_t k, double eps, double delta,
                          uint64_t seed, uint64_t max_attempts, int64_t *selected,
                          uint64_t *gains, sia_sas_info *info, void *hip_stream);
+
+/*
+ * The parameters sia_sas_solve uses, for id space S = id_space (m for
+ * edges, equation "guard"; n for nodes, equation "nguard"), budget k,
+ * eps in (0, 1 - 1/e) and delta in (0, 1):
+ *   n_max   = (2 - 1/e)^2 (2 + 2eps/3) S (ln(6/delta) + ln C(S,k)) / (k eps^2)
+ *   t_max   = ceil(log2(2 n_max / Upsilon)), Upsilon = (2 + 2eps/3) ln(3/delta) / eps^2
+ *             (the lemma bounding the iterations), at least 1
+ *   lambda  = (2 + 2eps/3) ln(3 t_max / delta) / eps^2        (equation "lambda")
+ *   lambda1 = 1 + (1 + eps) lambda                            (equation "lambda_1")
+ * ln C(S,k) is taken through lgamma in double precision.  Host arithmetic
+ * only (no device work); every output pointer may be NULL.  Errors:
+ * SIA_EINVAL (k outside [1, id_space], eps or delta out of range).
+ */
+sia_status sia_sas_params(int64_t id_space, int64_t k, double eps, double delta, double *lambda,
+                          double *lambda1, double *n_max, int32_t *t_max);
+
+/*
+ * Check (Algorithm 5 / 8) as sia_sas_solve evaluates it at iteration t:
+ * with Cov' = cov_rp the coverage on R'_t, |R'_t| = n_rp, Cov = cov_r the
+ * coverage on R_t and s = n_rp (1 + eps) / (2^(t-1) Cov'):
+ *   eps_1 = Cov / Cov' - 1,  eps_2 = eps sqrt(s),
+ *   eps_3 = eps sqrt(s (1 - 1/e - eps) / (1 + eps/3)),
+ *   eps_t = (eps_1 + eps_2 + eps_1 eps_2)(1 - 1/e - eps) + (1 - 1/e) eps_3.
+ *   terms   host double[4] (out): eps_1, eps_2, eps_3, eps_t; all NaN when
+ *           Cov' < lambda1 (Check then fails without forming them)
+ *   passed  host (out): 1 when Cov' >= lambda1 and eps_t <= eps, else 0
+ * Host arithmetic only.  Errors: SIA_EINVAL (NULL output, t outside
+ * [1, 1024), cov_rp or n_rp not positive, cov_r negative, eps out of
+ * range).
+ */
+sia_status sia_sas_check(double cov_r, double cov_rp, double n_rp, int32_t t, double eps, double lambda1,
+                         double *terms, int32_t *passed);
 
 /*
  * Evaluate a chosen set on its own sample (the out-of-sample estimate the

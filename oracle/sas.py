@@ -47,18 +47,27 @@ def params(id_space, k, eps, delta):
     return dict(lam=lam, lam1=lam1, n_max=n_max, t_max=t_max, upsilon=upsilon, e1=e1)
 
 
-def check(cov_r, cov_rp, n_rp, t, eps, lam1):
-    """Check (Algorithm 5 / 8): (passed, eps_t); eps_t is None when the
-    coverage on R'_t is below Lambda_1."""
+def check_terms(cov_r, cov_rp, n_rp, t, eps, lam1):
+    """The quantities Check (Algorithm 5 / 8) forms: None below the Lambda_1
+    cut-off (Cov_{R'_t} < Lambda_1), else (eps_1, eps_2, eps_3, eps_t)."""
     if cov_rp < lam1:
-        return False, None
+        return None
     e = 1.0 - 1.0 / math.e
     scale = n_rp * (1.0 + eps) / (2.0 ** (t - 1) * cov_rp)
     eps1 = cov_r / cov_rp - 1.0
     eps2 = eps * math.sqrt(scale)
     eps3 = eps * math.sqrt(scale * (e - eps) / (1.0 + eps / 3.0))
     eps_t = (eps1 + eps2 + eps1 * eps2) * (e - eps) + e * eps3
-    return eps_t <= eps, eps_t
+    return eps1, eps2, eps3, eps_t
+
+
+def check(cov_r, cov_rp, n_rp, t, eps, lam1):
+    """Check (Algorithm 5 / 8): (passed, eps_t); eps_t is None when the
+    coverage on R'_t is below Lambda_1."""
+    terms = check_terms(cov_r, cov_rp, n_rp, t, eps, lam1)
+    if terms is None:
+        return False, None
+    return terms[3] <= eps, terms[3]
 
 
 def coverage(off, ids, chosen, id_space):

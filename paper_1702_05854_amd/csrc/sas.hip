@@ -211,18 +211,23 @@ SasParams sas_params(double S, double k, double eps, double delta)
     return P;
 }
 
-// Check (Algorithm 5 / 8): passes when eps_t <= eps; eps_t is NaN below Lambda_1.
-bool sas_check(double cov_r, double cov_rp, double n_rp, int t, double eps, double lambda1, double *eps_t)
+// Check (Algorithm 5 / 8): passes when eps_t <= eps.  terms[0..3] receive
+// eps_1, eps_2, eps_3 and eps_t, all NaN below the Lambda_1 cut-off (where
+// Check returns false without forming them).
+bool sas_check(double cov_r, double cov_rp, double n_rp, int t, double eps, double lambda1, double terms[4])
 {
-    *eps_t = std::numeric_limits<double>::quiet_NaN();
+    for (int i = 0; i < 4; ++i) terms[i] = std::numeric_limits<double>::quiet_NaN();
     if (cov_rp < lambda1) return false;
     const double e = 1.0 - 1.0 / M_E;
     const double scale = n_rp * (1.0 + eps) / (std::ldexp(1.0, t - 1) * cov_rp);
     const double e1 = cov_r / cov_rp - 1.0;
     const double e2 = eps * std::sqrt(scale);
     const double e3 = eps * std::sqrt(scale * (e - eps) / (1.0 + eps / 3.0));
-    *eps_t = (e1 + e2 + e1 * e2) * (e - eps) + e * e3;
-    return *eps_t <= eps;
+    terms[0] = e1;
+    terms[1] = e2;
+    terms[2] = e3;
+    terms[3] = (e1 + e2 + e1 * e2) * (e - eps) + e * e3;
+    return terms[3] <= eps;
 }
 
 // grow a device buffer keeping its first keep bytes
@@ -406,16 +411,16 @@ sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, 
                                scalar.as<unsigned long long>());
             SIA_HIP(hipGetLastError());
             const uint64_t cov_rp = read_counter();
-            double eps_t;
+            double terms[4];
             const bool passed = sas_check(static_cast<double>(cov_r), static_cast<double>(cov_rp),
-                                          static_cast<double>(n_t), t, eps, P.lambda1, &eps_t);
+                                          static_cast<double>(n_t), t, eps, P.lambda1, terms);
             if (passed || static_cast<double>(n_t) >= P.n_max) {
                 I.status = passed ? 1 : 0;
                 I.attempts_r = a_r;
                 I.attempts_rp = a_rp;
                 I.cov_r = cov_r;
                 I.cov_rp = cov_rp;
-                I.eps_t = eps_t;
+                I.eps_t = terms[3];
                 const double n_ns = static_cast<double>(g->n - n_sources);
                 I.spread_est = static_cast<double>(n_sources) + n_ns * static_cast<double>(n_t) / a_r;
                 I.suspension_est = n_ns * static_cast<double>(cov_r) / a_r;
@@ -488,6 +493,33 @@ sia_status sia_evaluate(const sia_graph *cg, int mode, const int32_t *sources, i
                 in_x += std::binary_search(st.sorted.begin(), st.sorted.end(), static_cast<int32_t>(selected[i]));
         R.suspension_nodes_est = R.suspension_est + static_cast<double>(in_x);
         *stats = R;
+    });
+}
+
+sia_status sia_sas_params(int64_t id_space, int64_t k, double eps, double delta, double *lambda,
+                          double *lambda1, double *n_max, int32_t *t_max)
+{
+    return guarded([&] {
+        SIA_REQUIRE(id_space >= 1 && k >= 1 && k <= id_space, SIA_EINVAL, "need 1 <= k <= id_space");
+        SIA_REQUIRE(eps > 0.0 && eps < 1.0 - 1.0 / M_E, SIA_EINVAL, "eps must be in (0, 1 - 1/e)");
+        SIA_REQUIRE(delta > 0.0 && delta < 1.0, SIA_EINVAL, "delta must be in (0, 1)");
+        const SasParams P = sas_params(static_cast<double>(id_space), static_cast<double>(k), eps, delta);
+        if (lambda) *lambda = P.lambda;
+        if (lambda1) *lambda1 = P.lambda1;
+        if (n_max) *n_max = P.n_max;
+        if (t_max) *t_max = P.t_max;
+    });
+}
+
+sia_status sia_sas_check(double cov_r, double cov_rp, double n_rp, int32_t t, double eps, double lambda1,
+                         double *terms, int32_t *passed)
+{
+    return guarded([&] {
+        SIA_REQUIRE(terms != nullptr && passed != nullptr, SIA_EINVAL, "NULL argument");
+        SIA_REQUIRE(t >= 1 && t < 1024, SIA_EINVAL, "t must be in [1, 1024)");
+        SIA_REQUIRE(cov_rp > 0.0 && n_rp > 0.0 && cov_r >= 0.0, SIA_EINVAL, "need cov_rp > 0, n_rp > 0, cov_r >= 0");
+        SIA_REQUIRE(eps > 0.0 && eps < 1.0 - 1.0 / M_E, SIA_EINVAL, "eps must be in (0, 1 - 1/e)");
+        *passed = sas_check(cov_r, cov_rp, n_rp, t, eps, lambda1, terms) ? 1 : 0;
     });
 }
 

@@ -142,13 +142,17 @@ def lib():
         L.sia_evaluate.argtypes = [p, i32, p, i64, p, i64, u64, u64, u64, C.POINTER(Stats), p]
         L.sia_sas_solve.argtypes = [p, i32, p, i64, i64, C.c_double, C.c_double, u64, u64, p, p,
                                     C.POINTER(SasInfo), p]
+        L.sia_sas_params.argtypes = [i64, i64, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.sia_sas_check.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.sia_probe_gather.argtypes = [u64, C.c_uint32, i32, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), p]
         for name in ("sia_check_query", "sia_graph_create", "sia_graph_destroy", "sia_graph_info",
                      "sia_graph_thresholds", "sia_graph_arc_bytes", "sia_quantize", "sia_sample",
                      "sia_greedy",
                      "sia_solve", "sia_solve_candidates", "sia_sas_solve", "sia_evaluate",
-                     "sia_probe_gather") + BATCH_SYMBOLS:
+                     "sia_sas_params", "sia_sas_check", "sia_probe_gather") + BATCH_SYMBOLS:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -328,6 +332,25 @@ def sas_solve(graph: Graph, sources, mode, k, eps=0.1, delta=None, seed=2017,
                                float(delta), seed, max_attempts, _hptr(sel), _hptr(gains),
                                C.byref(info), _stream(stream)))
     return dict(selected=sel, gains=gains, info=info.as_dict())
+
+
+def sas_params(id_space, k, eps, delta):
+    """Lambda, Lambda_1, N_max and t_max of the Stop-and-Stare driver
+    (sia_sas_params; host arithmetic)."""
+    lam, lam1, n_max, t_max = C.c_double(), C.c_double(), C.c_double(), C.c_int32()
+    _check(lib().sia_sas_params(id_space, k, float(eps), float(delta), C.byref(lam), C.byref(lam1),
+                                C.byref(n_max), C.byref(t_max)))
+    return dict(lam=lam.value, lam1=lam1.value, n_max=n_max.value, t_max=t_max.value)
+
+
+def sas_check(cov_r, cov_rp, n_rp, t, eps, lam1):
+    """Check as the driver evaluates it (sia_sas_check): (passed, terms)
+    with terms = (eps_1, eps_2, eps_3, eps_t), all NaN below Lambda_1."""
+    terms = (C.c_double * 4)()
+    passed = C.c_int32()
+    _check(lib().sia_sas_check(float(cov_r), float(cov_rp), float(n_rp), t, float(eps), float(lam1), terms,
+                               C.byref(passed)))
+    return bool(passed.value), tuple(terms)
 
 
 def _query(sources, mode, k, n_attempts, attempt_offset, seed):

@@ -106,3 +106,24 @@ def test_sas_attempt_cap_and_arguments(sia, er1k):
     for kw in (dict(eps=0.0), dict(eps=0.7), dict(delta=0.0), dict(delta=1.0)):
         with pytest.raises(sia.SiaError):
             sia.sas_solve(g, wl.sources, "edges", wl.k, **{**dict(eps=0.1, delta=1e-3), **kw})
+
+
+@pytest.mark.parametrize("mode,eps,name", [("nodes", 0.5, "er1k_nodes"), ("edges", 0.1, "er1k_edges")])
+def test_sas_driver_parameters_match_hand_derivation(sia, er1k, mode, eps, name):
+    """The driver's Lambda, Lambda_1, N_max and t_max on the 1000-node graph
+    (delta = 1/n, k = 10) equal the hand-derived values of
+    tests/golden/sas_check.json (equations "lambda", "lambda_1", "nguard" /
+    "guard", iteration lemma), and its N_t is ceil(Lambda 2^(t-1))."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sas_check.json")) as f:
+        P = {p["name"]: p for p in json.load(f)["params"]}[name]
+    wl, g, og = er1k
+    assert (P["S"], P["k"]) == ((g.n if mode == "nodes" else g.m), 10) and wl.k == 10
+    say("golden params", name)
+    I = sia.sas_solve(g, wl.sources, mode, 10, eps, None, wl.seed)["info"]
+    assert I["t_max"] == P["t_max"]
+    assert I["n_max"] == pytest.approx(float(P["n_max"]), rel=1e-9)
+    assert I["lambda_"] == pytest.approx(float(P["lam"]), rel=1e-13)
+    assert I["lambda1"] == pytest.approx(float(P["lam1"]), rel=1e-13)
+    assert I["n_t"] == math.ceil(float(P["lam"]) * 2 ** (I["t"] - 1))
