@@ -148,6 +148,19 @@ class Graph:
         rc, self.thr = thresholds(self.col_off, self.w)
         _check(rc, "thresholds")
 
+    @classmethod
+    def from_tables(cls, col_off, row_idx, thr):
+        """A graph whose threshold table was computed by this oracle before
+        (the arrays may be read-only memory maps; they are not copied)."""
+        g = cls.__new__(cls)
+        g.col_off = np.ascontiguousarray(col_off, dtype=np.int64)
+        g.row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
+        g.thr = np.ascontiguousarray(thr, dtype=np.uint32)
+        g.w = None
+        g.n = g.col_off.shape[0] - 1
+        g.m = g.row_idx.shape[0]
+        return g
+
     def _sample(self, sources, mode, seed, attempts=None, n_attempts=0, offset=0):
         src = np.ascontiguousarray(sources, dtype=np.int32)
         s = _Walks()

@@ -143,6 +143,62 @@ def test_rmat24_solve_properties(sia, rmat24):
     assert int(hit.sum()) == st["covered"]
 
 
+def _digest(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{name}_digest.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _sha(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def compare_with_digest(sia, g, wl, D):
+    """The whole query against the oracle's digest (tests/golden/*_digest.json,
+    written by tests/golden/make_fullsize_digest.py from the oracle alone, run
+    over disjoint attempt ranges in several processes and merged in attempt
+    order): the graph, the counters, the attempt-ordered kept walks, the
+    coverage counts, and the k picks and gains of the full solve."""
+    assert (g.n, g.m, wl.seed) == (D["n"], D["m"], D["seed"])
+    assert _sha(np.asarray(wl.sources, np.int32)) == D["sources_sha256"]
+    col_off, row_idx, w = wl.host()
+    assert _sha(col_off.astype("<i8")) == D["sha256"]["col_off"]
+    assert _sha(row_idx.astype("<i4")) == D["sha256"]["row_idx"]
+    assert _sha(w.astype("<f4")) == D["sha256"]["w"]
+    N, k = D["n_attempts"], D["k"]
+    say("gpu sample", N)
+    got = sia.sample(g, wl.sources, D["mode"], N, D["attempt_offset"], wl.seed)
+    st = got.stats
+    C = D["counters"]
+    assert (st["attempts"], st["hits"], st["dead_ends"], st["cycles"], st["steps"], st["walk_ids"]) == (
+        C["attempts"], C["hits"], C["dead_ends"], C["cycles"], C["steps"], C["walk_ids"])
+    say("stream digests")
+    assert _sha(got.attempt.astype("<u8")) == D["sha256"]["attempt"]
+    assert _sha(got.off.astype("<u8")) == D["sha256"]["off"]
+    assert _sha(got.ids.astype("<u4")) == D["sha256"]["ids"]
+    space = g.m if D["mode"] == "edges" else g.n
+    cnt = np.bincount(got.ids, minlength=space).astype("<u4")
+    assert _sha(cnt) == D["sha256"]["counts"]
+    del got, cnt
+    say("gpu solve k =", k)
+    res = sia.solve(g, wl.sources, D["mode"], k, N, D["attempt_offset"], wl.seed)
+    assert res["selected"].tolist() == D["selected"]
+    assert res["gains"].tolist() == D["gains"]
+    assert res["stats"]["covered"] == D["covered"]
+    assert res["stats"]["hits"] == C["hits"] and res["stats"]["steps"] == C["steps"]
+
+
+def test_rmat24_whole_query_matches_oracle_digest(sia, rmat24):
+    """The bench's query (R-MAT scale 24, 10^4 sources, N = 10^8, k = 1000)
+    equal to the oracle as a whole: every counter, the digest of every kept
+    walk in attempt order, the counts, all 1000 picks and gains."""
+    wl, g, og, host = rmat24
+    compare_with_digest(sia, g, wl, _digest("rmat24"))
+
+
 # ---------------------------------------------------------------- billion-edge graph
 @pytest.fixture(scope="module")
 def rmat26(sia):
