@@ -68,12 +68,16 @@ static_assert(kCountSpanLog + kCoarseLog + kFineLog >= 32, "two levels span a 32
 constexpr uint32_t kFilterWords = (1u << kFilterBits) / 32;
 static_assert(kHash >= 2 * kPoolMax, "pool hash load factor");
 
-enum PlanKind : uint32_t { PLAN_COLLECT = 0, PLAN_TIES = 1 };
+enum PlanKind : uint32_t { PLAN_COLLECT = 0, PLAN_TIES = 1, PLAN_REFINE = 2 };
+// An overfull wide bin (one above the exact counts) is split by one or two
+// further histograms of its own counts, kRefineBins sub-bins each.
+constexpr uint32_t kRefineLog = 13;
+constexpr uint32_t kRefineBins = 1u << kRefineLog;
 
 // Per-job state, written by the plan / collect / lazy kernels.
 struct GreedyState {
     uint32_t rounds;    // rounds completed so far
-    uint32_t error;     // 2: more tied high counts than the pool holds
+    uint32_t error;     // nonzero: the job stopped (no valid input sets it)
     uint32_t plan;      // PlanKind of the current pool
     uint32_t c_min;     // pool holds every unselected id with cnt >= c_min (0: none)
     uint32_t pool_n;    // ids collected that way
@@ -86,6 +90,10 @@ struct GreedyState {
     uint32_t n_claimed;     // walks covered so far (entries of the claimed list)
     uint32_t claimed_done;  // of them, already taken off the global counts
     uint32_t marked;        // rounds whose picks are marked selected in the global counts
+    uint32_t r_lo;          // PLAN_REFINE: lowest count of the range being split
+    uint32_t r_shift;       //   sub-bins of 2^r_shift counts
+    uint32_t r_nbins;       //   sub-bins covering the range (<= kRefineBins)
+    uint32_t r_above;       //   unselected ids with a count above the range
     uint32_t pad;
 };
 
@@ -642,12 +650,53 @@ __global__ __launch_bounds__(T) void k_hist(const GreedyJob *jobs)
         if (h[b]) g_add(&J.hist[b], h[b]);
 }
 
+// The plan for a pool once the crossing bin is known: ab unselected ids lie
+// above it, h_b in it, its counts are [c_lo, c_lo + 2^shift).  If ab + h_b
+// fit the pool (and the bin is not count 0), the pool is every id with cnt
+// >= c_lo.  A single count c = c_lo gives a tie plan: every id above c plus
+// the lowest-id ones at c, up to kPoolTarget.  A wider bin that overfills
+// the pool is split by a histogram of its own counts (PLAN_REFINE).
+__device__ void set_plan(GLOBAL GreedyState *st, uint64_t c_lo, uint32_t shift, uint32_t ab, uint32_t h_b)
+{
+    const uint64_t ge = static_cast<uint64_t>(ab) + h_b;
+    st->pool_n = 0;
+    st->next_id = 0;
+    if (ge <= kPoolMax && c_lo > 0) {
+        st->plan = PLAN_COLLECT;
+        st->c_min = static_cast<uint32_t>(c_lo);
+        st->n_tie = 0;
+        st->leftover = 0;
+        st->tau = (c_lo << 32) | 0xFFFFFFFFull;  // bound for every count <= c_lo - 1
+    } else if (shift == 0) {
+        const uint32_t c = static_cast<uint32_t>(c_lo);
+        const uint32_t R = static_cast<uint32_t>(std::min<uint64_t>(kPoolTarget, ge) - ab);
+        st->plan = PLAN_TIES;
+        st->c_min = ab ? c + 1 : 0;
+        st->c_tie = c;
+        st->n_tie = R;
+        st->leftover = ge > static_cast<uint64_t>(ab) + R;
+        st->tau = c ? (static_cast<uint64_t>(c) << 32) | 0xFFFFFFFFull : 0ull;
+    } else {
+        const uint32_t sub = shift > kRefineLog ? shift - kRefineLog : 0u;
+        st->plan = PLAN_REFINE;
+        st->r_lo = static_cast<uint32_t>(c_lo);
+        st->r_shift = sub;
+        st->r_nbins = 1u << (shift - sub);
+        st->r_above = ab;
+        st->n_tie = 0;
+    }
+}
+
+// log2 of the width of histogram bin b (0 for the exact counts)
+__device__ __forceinline__ uint32_t bin_shift(uint32_t b)
+{
+    return b < kExact ? 0u : (b - kExact) / kPerOctave + 3u;
+}
+
 // Choose the next pool from the histogram (and clear it for the next
 // rebuild).  b* = the highest bin with at least kPoolTarget unselected ids at
-// or above it (bin 0 if there are fewer).  If those ids fit the pool and b* >
-// 0, the pool is every id with cnt >= the lowest count of b*.  Otherwise b*
-// is an exact count c (else: error) and the pool is every id above c plus the
-// lowest-id ones at c, up to kPoolTarget.  One workgroup per job.
+// or above it (bin 0 if there are fewer); set_plan turns it into a pool.
+// One workgroup per job.
 template <int T>
 __global__ __launch_bounds__(T) void k_plan(const GreedyJob *jobs)
 {
@@ -698,29 +747,94 @@ __global__ __launch_bounds__(T) void k_plan(const GreedyJob *jobs)
         b = bstar;
         ab = ab_sh;
     }
-    const uint64_t ge = static_cast<uint64_t>(ab) + h[b];
-    GLOBAL GreedyState *st = J.st;
-    st->pool_n = 0;
-    st->next_id = 0;
-    if (ge <= kPoolMax && b > 0) {
-        const uint64_t c_lo = bin_lo(b);
-        st->plan = PLAN_COLLECT;
-        st->c_min = static_cast<uint32_t>(c_lo);
-        st->n_tie = 0;
-        st->leftover = 0;
-        st->tau = (c_lo << 32) | 0xFFFFFFFFull;  // bound for every count <= c_lo - 1
-    } else if (b < kExact) {
-        const uint32_t c = b;
-        const uint32_t R = static_cast<uint32_t>(std::min<uint64_t>(kPoolTarget, ge) - ab);
-        st->plan = PLAN_TIES;
-        st->c_min = ab ? c + 1 : 0;
-        st->c_tie = c;
-        st->n_tie = R;
-        st->leftover = ge > static_cast<uint64_t>(ab) + R;
-        st->tau = c ? (static_cast<uint64_t>(c) << 32) | 0xFFFFFFFFull : 0ull;
-    } else {
-        st->error = 2;
+    set_plan(J.st, bin_lo(b), bin_shift(b), ab, h[b]);
+}
+
+// PLAN_REFINE: histogram of the unselected counts in [r_lo, r_lo +
+// r_nbins 2^r_shift), sub-bin (c - r_lo) >> r_shift, into the job's histogram
+// array (cleared by the plan kernels).
+template <int T>
+__global__ __launch_bounds__(T) void k_refine_hist(const GreedyJob *jobs)
+{
+    constexpr int U = 8;  // loads in flight per lane
+    __shared__ uint32_t h[kRefineBins];
+    const GJob J = view(jobs[blockIdx.y]);
+    if (job_done(J) || J.st->plan != PLAN_REFINE) return;  // uniform per block
+    const uint32_t lo = J.st->r_lo, shift = J.st->r_shift, nb = J.st->r_nbins;
+    for (uint32_t i = threadIdx.x; i < nb; i += T) h[i] = 0;
+    __syncthreads();
+    for (uint64_t base = blockIdx.x * static_cast<uint64_t>(U * T); base < J.S;
+         base += static_cast<uint64_t>(gridDim.x) * U * T) {
+        uint32_t c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = base + u * T + threadIdx.x;
+            c[u] = i < J.S ? J.cnt[i] : kSelected;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (c[u] == kSelected || c[u] < lo) continue;
+            const uint32_t sb = (c[u] - lo) >> shift;
+            if (sb < nb) atomicAdd(&h[sb], 1u);
+        }
     }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += T)
+        if (h[b]) g_add(&J.hist[b], h[b]);
+}
+
+// PLAN_REFINE: the sub-bin where the count of ids at or above it (with the
+// r_above ids above the range) reaches kPoolTarget -- it exists, since the
+// range's bin crossed it -- then set_plan.  One workgroup per job.
+template <int T>
+__global__ __launch_bounds__(T) void k_refine_plan(const GreedyJob *jobs)
+{
+    constexpr uint32_t kPer = kRefineBins / T;
+    constexpr int kWaves = T / kWave;
+    static_assert(kRefineBins % T == 0, "sub-bins per thread");
+    __shared__ uint32_t h[kRefineBins];
+    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t bstar, ab_sh;
+    const GJob J = view(jobs[blockIdx.x]);
+    if (job_done(J) || J.st->plan != PLAN_REFINE) return;  // uniform per block
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const uint32_t nb = J.st->r_nbins;
+    for (uint32_t b = threadIdx.x; b < kRefineBins; b += T) {
+        h[b] = b < nb ? J.hist[b] : 0u;
+        if (b < nb) J.hist[b] = 0;
+    }
+    if (threadIdx.x == 0) {
+        bstar = 0;
+        ab_sh = J.st->r_above;
+    }
+    __syncthreads();
+    const uint32_t b0 = threadIdx.x * kPer;
+    uint32_t mine = 0;
+    for (uint32_t i = 0; i < kPer; ++i) mine += h[b0 + i];
+    uint32_t x = mine;  // inclusive suffix sum within the wave
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_down(x, d, kWave);
+        if (lane + d < kWave) x += o;
+    }
+    if (lane == 0) wsum[wid] = x;
+    __syncthreads();
+    uint32_t above = J.st->r_above + x - mine;
+    for (int w = wid + 1; w < kWaves; ++w) above += wsum[w];
+    for (int i = static_cast<int>(kPer) - 1; i >= 0; --i) {
+        const uint32_t b = b0 + i;
+        if (above < kPoolTarget && above + h[b] >= kPoolTarget) {
+            bstar = b;
+            ab_sh = above;
+        }
+        above += h[b];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    GLOBAL GreedyState *st = J.st;
+    const uint32_t shift = st->r_shift;
+    set_plan(st, static_cast<uint64_t>(st->r_lo) + (static_cast<uint64_t>(bstar) << shift), shift, ab_sh,
+             h[bstar]);
 }
 
 // Pool += every unselected id with cnt >= c_min.
@@ -1412,6 +1526,10 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
         for (int gen = 0; gen < group; ++gen) {
             hipLaunchKernelGGL(k_hist<T>, dim3(hist_blocks, Q), dim3(T), 0, s, d_jobs);
             hipLaunchKernelGGL(k_plan<T>, dim3(Q), dim3(T), 0, s, d_jobs);
+            for (int level = 0; level < 2; ++level) {  // bins of up to 2^22 counts: two splits at most
+                hipLaunchKernelGGL(k_refine_hist<T>, dim3(hist_blocks, Q), dim3(T), 0, s, d_jobs);
+                hipLaunchKernelGGL(k_refine_plan<T>, dim3(Q), dim3(T), 0, s, d_jobs);
+            }
             hipLaunchKernelGGL(k_collect, dim3(collect_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_tie_count, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_tie_scan, dim3(1, Q), dim3(256), 0, s, d_jobs);
@@ -1427,8 +1545,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
         SIA_HIP(hipStreamSynchronize(s));
         bool all = true;
         for (uint32_t q = 0; q < Q; ++q) {
-            SIA_REQUIRE(hs[q].error == 0, SIA_EDEVICE,
-                        "greedy pool: more tied high counts than the pool holds");
+            SIA_REQUIRE(hs[q].error == 0 && hs[q].plan != PLAN_REFINE, SIA_EDEVICE,
+                        "greedy pool plan left unresolved");
             const bool finished = static_cast<int64_t>(hs[q].rounds) >= in[q].k;
             // every rebuild certifies at least one pick, so an unfinished job
             // always advances

@@ -387,6 +387,58 @@ def test_greedy_counts_exact(sia, case):
     assert np.array_equal(gains, exp_gain)
 
 
+@pytest.mark.parametrize("case", ["width8", "width16"])
+def test_greedy_overfull_high_count_bin(sia, case):
+    """Algorithm 4 / 7 return k picks for any input.  9000 ids whose counts
+    all fall in one wide bin of the count histogram (above the exact counts:
+    4096..4103, a bin of 8 counts; or 8192..8207, a bin of 16), more ids than
+    the lazy pool holds, with 1000 (500) ids in the bin above: the pool is
+    planned from a second histogram of that bin's own counts.  Single-id
+    walks, so the picks are the ids by count (ties by ascending id) and each
+    gain is the id's count; k runs past the hot ids into a tail of low
+    counts."""
+    rng = np.random.default_rng({"width8": 41, "width16": 42}[case])
+    lo, width, n_hot, n_above = (4096, 8, 9000, 1000) if case == "width8" else (8192, 16, 9000, 500)
+    S = 50_000
+    hot = rng.choice(S, n_hot + n_above, replace=False)
+    cnt = np.concatenate([rng.integers(lo, lo + width, n_hot), rng.integers(lo + width, lo + 2 * width, n_above)])
+    cold = rng.integers(0, S, 200_000)
+    ids = rng.permutation(np.concatenate([np.repeat(hot, cnt), cold])).astype(np.uint32)
+    off = np.arange(ids.shape[0] + 1, dtype=np.uint64)
+    k = n_hot + n_above + 500
+    print("[parity] overfull bin", case, ids.shape[0], "walks", flush=True)
+    sel, gains = sia.greedy(S, off, ids, k)
+    u, c = np.unique(ids, return_counts=True)
+    order = np.lexsort((u, -c))
+    assert np.array_equal(sel, u[order][:k].astype(np.int64))
+    assert np.array_equal(gains, c[order][:k].astype(np.uint64))
+
+
+def test_greedy_overfull_high_count_bin_multi_id_walks(sia):
+    """The same shape with walks of four distinct ids (covering a walk lowers
+    the counts of its other ids), against the oracle's greedy.  4100 rounds,
+    each a random permutation of 9000 ids cut into walks of four, give every
+    id the count 4100; 3000 more random walks lift some by a few, so more
+    than 8192 ids have counts in 4100..4103 (one wide bin) and a few hundred
+    lie in the bin above."""
+    rng = np.random.default_rng(43)
+    S, n_hot, R = 30_000, 9000, 4100
+    hot = rng.choice(S, n_hot, replace=False).astype(np.uint32)
+    rounds = rng.permuted(np.tile(np.arange(n_hot, dtype=np.uint32), (R, 1)), axis=1).reshape(-1)
+    extra = np.stack([rng.choice(n_hot, 4, replace=False) for _ in range(3000)]).reshape(-1).astype(np.uint32)
+    walks = np.concatenate([rounds, extra]).reshape(-1, 4)
+    walks = walks[rng.permutation(walks.shape[0])]
+    ids = hot[walks.reshape(-1)]
+    off = np.arange(0, ids.shape[0] + 1, 4, dtype=np.uint64)
+    cnt = np.bincount(ids, minlength=S)[hot]
+    assert cnt.min() >= 4100 and cnt.max() < 4112 and (cnt < 4104).sum() > 8192
+    k = 150
+    print("[parity] overfull bin, multi-id walks", off.shape[0] - 1, flush=True)
+    a = sia.greedy(S, off, ids, k)
+    b = cpu.greedy_csr(S, off, ids, k)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
 # ------------------------------------------------------------------ solve
 @pytest.mark.parametrize("mode", ["edges", "nodes"])
 def test_solve_er1k_matches_oracle(sia, mode):
@@ -490,3 +542,4 @@ def test_probe_gather_measures(sia):
     ind, ms_i = sia.probe_gather(64 << 20, 64, dependent=False)
     dep, ms_d = sia.probe_gather(64 << 20, 64, dependent=True)
     assert ind > 0 and dep > 0 and ms_i > 0 and ms_d > 0
+
