@@ -98,6 +98,12 @@ const char *sia_version(void);
 /* Message for the last failed call on this thread ("" if none). */
 const char *sia_last_error(void);
 
+/* Test hook (fault injection on the host): the nth device allocation the
+ * library makes from now on fails as if the device were out of memory
+ * (SIA_ENOMEM from the call making it); 0 disables.  Allocations that reuse
+ * a buffer large enough do not count.  Process-wide. */
+void sia_test_fail_alloc(uint32_t nth);
+
 /*
  * Check the query arguments of sia_solve / sia_sample on the host without
  * touching the GPU (also done inside those calls).

@@ -3,6 +3,7 @@
 #include "common.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cstddef>
 #include <cstring>
 #include <memory>
@@ -39,12 +40,25 @@ void finish_stats(sia_stats &S, const SourceTables &st, int mode, uint64_t n_att
 }
 void clear_error() { g_last_error.clear(); }
 
+namespace {
+// Test hook: when nonzero, the allocation that brings it to zero fails.
+std::atomic<uint32_t> g_fail_alloc{0};
+}  // namespace
+
 void DevBuf::ensure(size_t want)
 {
     if (want == 0) want = 1;
     if (ptr && bytes >= want) return;
     release();
-    SIA_HIP(hipMalloc(&ptr, want));
+    uint32_t c = g_fail_alloc.load();
+    while (c && !g_fail_alloc.compare_exchange_weak(c, c - 1)) {
+    }
+    if (c == 1) throw Error{SIA_ENOMEM, "device allocation failed (injected by sia_test_fail_alloc)"};
+    if (hipMalloc(&ptr, want) != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        throw Error{SIA_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed"};
+    }
     bytes = want;
 }
 
@@ -114,6 +128,8 @@ using namespace sia;
 extern "C" {
 
 const char *sia_version(void) { return "sia 0.1 (gfx950)"; }
+
+void sia_test_fail_alloc(uint32_t nth) { g_fail_alloc.store(nth); }
 
 const char *sia_last_error(void) { return g_last_error.c_str(); }
 

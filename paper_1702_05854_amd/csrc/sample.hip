@@ -670,6 +670,34 @@ void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
     SIA_HIP(hipGetLastError());
 }
 
+namespace {
+// Clears a query's source-tag bit on every exit from the sampler, thrown
+// errors included: a tag left set would make later queries on the graph
+// treat those nodes as sources.
+struct SourceTagScope {
+    const sia_graph *g;
+    const int32_t *d_src;
+    uint32_t n_src, mask;
+    hipStream_t s;
+    SourceTagScope(const sia_graph *g_, const int32_t *d_src_, uint32_t n_src_, uint32_t mask_, hipStream_t s_)
+        : g(g_), d_src(d_src_), n_src(n_src_), mask(mask_), s(s_)
+    {
+        tag_sources(g, d_src, n_src, mask, true, s);
+    }
+    ~SourceTagScope()
+    {
+        try {
+            tag_sources(g, d_src, n_src, mask, false, s);
+            (void)hipStreamSynchronize(s);
+        } catch (...) {
+            // the device already failed; nothing more can be undone here
+        }
+    }
+    SourceTagScope(const SourceTagScope &) = delete;
+    SourceTagScope &operator=(const SourceTagScope &) = delete;
+};
+}  // namespace
+
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
                          uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing)
 {
@@ -687,13 +715,18 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
                            hipMemcpyHostToDevice, s));
     SIA_HIP(hipMemcpyAsync(ws.bucket.ptr, st.bucket.data(), sizeof(uint32_t) * st.bucket.size(),
                            hipMemcpyHostToDevice, s));
-    tag_sources(g, ws.src_sorted.as<int32_t>(), n_src, mask, true, s);
+    const SourceTagScope tags(g, ws.src_sorted.as<int32_t>(), n_src, mask, s);
     char *cbase = ws.counters.as<char>();
     uint64_t *d_counters = reinterpret_cast<uint64_t *>(cbase);
     SlotDev *d_slot = reinterpret_cast<SlotDev *>(cbase + sizeof(uint64_t) * ST_COUNT);
     WaveTable *d_table = reinterpret_cast<WaveTable *>(
         cbase + ((sizeof(uint64_t) * ST_COUNT + sizeof(SlotDev) + 255) / 256) * 256);
 
+    // The first call on a graph sizes the walk buffers from a pilot of this
+    // query's first attempts (its output is discarded), so a cold query does
+    // not run the full launch twice.
+    const uint64_t kPilot = uint64_t(1) << 16;
+    bool pilot = !ws.walk_cap && n_attempts > kPilot;
     if (!ws.walk_cap) {
         ws.walk_cap = std::min<uint64_t>(n_attempts, std::max<uint64_t>(1u << 20, n_attempts / 16));
         ws.id_cap = std::max<uint64_t>(1u << 24, ws.walk_cap * 32);
@@ -702,6 +735,7 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
     SampleResult res;
     bool ok = false;
     for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
+        const uint64_t launch_attempts = pilot ? kPilot : n_attempts;
         ws.walk_attempt.ensure(sizeof(uint64_t) * ws.walk_cap);
         ws.walk_off.ensure(sizeof(uint64_t) * ws.walk_cap);
         ws.walk_len.ensure(sizeof(uint32_t) * ws.walk_cap);
@@ -726,7 +760,7 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
         S.id_cap = ws.id_cap;
         S.counters = d_counters;
         SIA_HIP(hipMemcpyAsync(d_slot, &S, sizeof(S), hipMemcpyHostToDevice, s));
-        const WaveItem item{0u, 0u, n_attempts};
+        const WaveItem item{0u, 0u, launch_attempts};
         WaveTable table;
         fill_wave_table(table, &item, 1, 1);
         SIA_HIP(hipMemcpyAsync(d_table, &table, sizeof(table), hipMemcpyHostToDevice, s));
@@ -748,9 +782,16 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
             SIA_HIP(hipEventDestroy(e0));
             SIA_HIP(hipEventDestroy(e1));
         }
-        if (h[ST_FAULTS]) {
-            tag_sources(g, ws.src_sorted.as<int32_t>(), n_src, mask, false, s);
-            throw Error{SIA_EDEVICE, "sampler consistency check failed"};
+        if (h[ST_FAULTS]) throw Error{SIA_EDEVICE, "sampler consistency check failed"};
+        if (pilot) {
+            // room for the whole query at the pilot's rates, plus 25% and slack
+            const double scale = 1.25 * static_cast<double>(n_attempts) / static_cast<double>(kPilot);
+            ws.walk_cap = std::max<uint64_t>(ws.walk_cap, static_cast<uint64_t>(scale * h[ST_WALKS]) + 4096);
+            ws.id_cap = std::max<uint64_t>(ws.id_cap, static_cast<uint64_t>(scale * h[ST_IDS]) + 65536);
+            ws.walk_cap = std::min<uint64_t>(ws.walk_cap, n_attempts);
+            pilot = false;
+            --attempt;  // the pilot is not one of the tries
+            continue;
         }
         res.walks = h[ST_WALKS];
         res.ids = h[ST_IDS];
@@ -765,7 +806,6 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
             ws.id_cap = std::max(ws.id_cap, h[ST_IDS] + 1);
         }
     }
-    tag_sources(g, ws.src_sorted.as<int32_t>(), n_src, mask, false, s);
     SIA_REQUIRE(ok, SIA_EDEVICE, "sampler output did not fit after resizing");
     return res;
 }

@@ -142,6 +142,8 @@ def lib():
         L.sia_evaluate.argtypes = [p, i32, p, i64, p, i64, u64, u64, u64, C.POINTER(Stats), p]
         L.sia_sas_solve.argtypes = [p, i32, p, i64, i64, C.c_double, C.c_double, u64, u64, p, p,
                                     C.POINTER(SasInfo), p]
+        L.sia_test_fail_alloc.argtypes = [C.c_uint32]
+        L.sia_test_fail_alloc.restype = None
         L.sia_sas_params.argtypes = [i64, i64, C.c_double, C.c_double, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.sia_sas_check.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_double, C.c_double,
@@ -332,6 +334,12 @@ def sas_solve(graph: Graph, sources, mode, k, eps=0.1, delta=None, seed=2017,
                                float(delta), seed, max_attempts, _hptr(sel), _hptr(gains),
                                C.byref(info), _stream(stream)))
     return dict(selected=sel, gains=gains, info=info.as_dict())
+
+
+def inject_alloc_failure(nth):
+    """Fault injection (sia_test_fail_alloc): the nth device allocation from
+    now fails with SIA_ENOMEM; 0 disables."""
+    lib().sia_test_fail_alloc(int(nth))
 
 
 def sas_params(id_space, k, eps, delta):

@@ -543,3 +543,31 @@ def test_probe_gather_measures(sia):
     dep, ms_d = sia.probe_gather(64 << 20, 64, dependent=True)
     assert ind > 0 and dep > 0 and ms_i > 0 and ms_d > 0
 
+
+def test_failed_call_leaves_graph_clean(sia):
+    """A call that fails part-way (an injected device-allocation failure at
+    each allocation site in turn, including those after the query's sources
+    are tagged in the graph) leaves the graph as it was: the next solve on it
+    equals the oracle's."""
+    from paper_1702_05854_amd import workloads
+    wl = workloads.load("er1k")
+    col, row, w = wl.host()
+    og = cpu.Graph(col, row, w)
+    ref = cpu.solve(og, wl.sources, cpu.MODE_EDGES, wl.k, 50_000, 0, wl.seed)
+    failures = 0
+    for nth in range(1, 16):
+        g = sia.Graph(col, row, w)
+        sia.inject_alloc_failure(nth)
+        try:
+            sia.solve(g, wl.sources, "edges", wl.k, 50_000, 0, wl.seed)
+        except sia.SiaError as e:
+            assert e.status == -3, (nth, e)  # SIA_ENOMEM
+            failures += 1
+        finally:
+            sia.inject_alloc_failure(0)
+        got = sia.solve(g, wl.sources, "edges", wl.k, 50_000, 0, wl.seed)
+        assert np.array_equal(got["selected"], ref["selected"]), nth
+        assert np.array_equal(got["gains"], ref["gains"]), nth
+        assert got["stats"]["hits"] == ref["walks"].hits, nth
+        g.close()
+    assert failures >= 5
