@@ -11,8 +11,13 @@ attempts, k = 1000, edges.  Inputs are synthetic (seeded) and generated on
 the GPU; they stand in for the paper's Twitter-scale graph.
 
 The JSON line carries ``roofline`` for the sampling kernel (algorithmic bytes
-/ its HIP-event time) and ``cpu_baseline`` (the single-threaded oracle on a
-bounded prefix of the same attempts).
+/ its HIP-event time), ``serve`` (the other half of the metric: 512 mixed
+queries on R-MAT scale 22, batched closed-loop queries/s against one query
+per call with every plain answer checked equal to the batched one, and
+p50/p99 latency at an open-loop load of the batched rate) and
+``cpu_baseline`` (the oracle on bounded prefixes of the same attempts: one
+host core, and P processes on disjoint attempt ranges merged exactly, with
+the host's CPU model and core counts).
 """
 import argparse
 import hashlib
@@ -62,13 +67,46 @@ def load_traffic():
     return t.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(wl, mode, k, budget_s):
-    """The oracle as it stands, single-threaded, on attempts [0, n_s)."""
+def host_cpu():
+    """CPU model, logical CPUs this process may use, physical cores."""
+    model, cores = "", set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name" and not model:
+                    model = val
+                elif key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    core = val
+                elif not key and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+    except OSError:
+        pass
+    if phys is not None:
+        cores.add((phys, core))
+    try:
+        logical = len(os.sched_getaffinity(0))
+    except AttributeError:
+        logical = os.cpu_count() or 1
+    return model, logical, len(cores) or logical
+
+
+def cpu_baseline(wl, mode, k, budget_s, max_procs=16):
+    """The oracle as it stands: single-threaded on attempts [0, n_s), then P
+    oracle processes on disjoint attempt ranges of a larger prefix, merged in
+    attempt order (exact), counted and greedily solved by one process -- the
+    one-core and multi-core columns of the paper's CPU/GPU comparison."""
     import numpy as np
-    from oracle import cpu
+    from oracle import cpu, shards
     col_off, row_idx, w = wl.host()
     og = cpu.Graph(col_off, row_idx, w)
     om = cpu.MODE_EDGES if mode == "edges" else cpu.MODE_NODES
+    model, logical, physical = host_cpu()
     # size the sample from a short probe so the timed run takes ~budget_s
     probe = 20_000
     t0 = time.perf_counter()
@@ -78,10 +116,30 @@ def cpu_baseline(wl, mode, k, budget_s):
     t0 = time.perf_counter()
     res = cpu.solve(og, wl.sources, om, k, n_s, 0, wl.seed)
     dt = time.perf_counter() - t0
-    return {"value": n_s / dt, "unit": "HSAW attempts/s", "cores": 1, "kind": "oracle",
-            "sample": f"attempts [0, {n_s}) of the same query (sample + count + greedy k={k}), "
-                      f"{dt:.1f} s on one host core",
-            "hsaw_per_s": res["walks"].hits / dt, "steps_per_s": res["walks"].steps / dt}
+    out = {"value": n_s / dt, "unit": "HSAW attempts/s", "cores": 1, "kind": "oracle",
+           "sample": f"attempts [0, {n_s}) of the same query (sample + count + greedy k={k}), "
+                     f"{dt:.1f} s on one host core",
+           "hsaw_per_s": res["walks"].hits / dt, "steps_per_s": res["walks"].steps / dt,
+           "host_cpu": model, "host_logical_cpus": logical, "host_physical_cores": physical}
+    # multi-process: P workers on disjoint ranges of P times the sample
+    P = max(1, min(max_procs, logical, physical))
+    n_p = int(min(wl.n_attempts, n_s * P))
+    print(f"[bench] cpu baseline: {P} oracle processes on {n_p} attempts", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    walks = shards.sample(og, wl.sources, om, n_p, 0, wl.seed, procs=P)
+    t_sample = time.perf_counter() - t0
+    id_space = og.m if om == cpu.MODE_EDGES else og.n
+    t1 = time.perf_counter()
+    sel, gains = cpu.greedy_csr(id_space, walks.off, walks.ids, k)
+    t_greedy = time.perf_counter() - t1
+    dt_p = time.perf_counter() - t0
+    out["multi"] = {"value": n_p / dt_p, "unit": "HSAW attempts/s", "cores": P, "processes": P,
+                    "sample": f"attempts [0, {n_p}) of the same query: {P} processes on disjoint "
+                              f"ranges merged in attempt order, then one count + greedy k={k}",
+                    "seconds": {"sample": t_sample, "count_greedy": t_greedy, "total": dt_p},
+                    "hsaw_per_s": walks.hits / dt_p, "steps_per_s": walks.steps / dt_p,
+                    "speedup_vs_one_core": (n_p / dt_p) / (n_s / dt)}
+    return out
 
 
 def percentile(xs, q):
@@ -89,7 +147,7 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
 
-def serve_bench(args):
+def serve_measure(args, name, n_queries, loads, skip_plain=False):
     """Batched / served queries vs the plain path (one query per call, FIFO).
 
     Closed loop: every query of the mix is submitted at t=0; queries/s =
@@ -104,12 +162,11 @@ def serve_bench(args):
     from paper_1702_05854_amd import sia, workloads
 
     torch.cuda.set_device(0)
-    name = args.workload if args.workload != "rmat24" else "rmat22"
     print(f"[serve] generating {name}", file=sys.stderr, flush=True)
     wl = workloads.load(name, device="cuda")
     g = sia.Graph(wl.col_off, wl.row_idx, wl.w)
     torch.cuda.synchronize()
-    qs = workloads.query_mix(wl.n, args.queries, seed=5)
+    qs = workloads.query_mix(wl.n, n_queries, seed=5)
     total_att = sum(q["n_attempts"] for q in qs)
     print(f"[serve] n={wl.n} m={wl.m}: {len(qs)} queries, {total_att} attempts", file=sys.stderr,
           flush=True)
@@ -143,7 +200,7 @@ def serve_bench(args):
 
         # plain: one query per call, in order; the answers must agree
         service = []
-        for i, q in enumerate(qs if not args.skip_plain else []):
+        for i, q in enumerate(qs if not skip_plain else []):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             r = sia.solve(g, q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"])
@@ -158,7 +215,7 @@ def serve_bench(args):
 
         open_loop = []
         rng = np.random.default_rng(6)
-        for frac in args.loads:
+        for frac in loads:
             lam = frac * rate_b
             arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(qs)))
             ts, lat = [], []
@@ -181,18 +238,29 @@ def serve_bench(args):
                               "plain_p99_s": percentile(plain_lat, 99)})
             print(f"[serve] open loop {frac}: {open_loop[-1]}", file=sys.stderr, flush=True)
     g.close()
-    out = {
-        "metric": "queries/s (mixed interdiction queries, batched and served)",
-        "value": rate_b, "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": makespan * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"{name}: R-MAT s{wl.desc.get('scale')} ef{wl.desc.get('ef')}, "
-                               f"{len(qs)} mixed queries", "n": wl.n, "m": wl.m,
-                   "queries": len(qs), "attempts_total": total_att},
+    return {
+        "workload": f"{name}: R-MAT s{wl.desc.get('scale')} ef{wl.desc.get('ef')}, {len(qs)} mixed queries",
+        "n": wl.n, "m": wl.m, "queries": len(qs), "attempts_total": total_att,
+        "batched_queries_per_s": rate_b, "makespan_s": makespan,
         "plain_queries_per_s": rate_p, "speedup_vs_plain": rate_b / rate_p if rate_p else None,
+        "plain_answers_checked": len(service),
         "closed_loop_p50_s": percentile(closed_lat, 50), "closed_loop_p99_s": percentile(closed_lat, 99),
         "attempts_per_s_batched": total_att / makespan,
         "open_loop": open_loop, "batch_stats": bstats,
+    }
+
+
+def serve_bench(args):
+    name = args.workload if args.workload != "rmat24" else "rmat22"
+    r = serve_measure(args, name, args.queries, args.loads, args.skip_plain)
+    out = {
+        "metric": "queries/s (mixed interdiction queries, batched and served)",
+        "value": r["batched_queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": r["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": r["workload"], "n": r["n"], "m": r["m"], "queries": r["queries"],
+                   "attempts_total": r["attempts_total"]},
+        **{k: v for k, v in r.items() if k not in ("workload", "n", "m", "queries", "attempts_total")},
     }
     print(json.dumps(out), flush=True)
 
@@ -275,6 +343,8 @@ def main():
     ap.add_argument("--mode", default=None)
     ap.add_argument("--attempts", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the batched-vs-plain block (mixed queries on R-MAT s22) of the default run")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
@@ -405,6 +475,11 @@ def main():
         "sampler_lines_per_s": samp_lines,
         "sampler_frac_of_independent": samp_lines / ceil_ind if samp_lines else None,
         "sampler_frac_of_dependent": samp_lines / ceil_dep if samp_lines else None}
+    del g
+    torch.cuda.empty_cache()
+    if not args.no_serve:
+        # the other half of the metric: batched vs plain queries/s on the mixed workload
+        out["serve"] = serve_measure(args, "rmat22", args.queries, [1.0])
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, mode, k, args.cpu_budget)
