@@ -55,6 +55,13 @@ def lib():
         L.orc_sample_list.argtypes = [C.c_int64, p, p, p, p, C.c_int64, C.c_int,
                                       p, C.c_uint64, C.c_uint64, C.POINTER(_Walks)]
         L.orc_walks_free.argtypes = [C.POINTER(_Walks)]
+        L.orc_draw_node_word.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32]
+        L.orc_draw_node_word.restype = C.c_uint64
+        L.orc_coin_thresholds.argtypes = [p, C.c_int64, p]
+        L.orc_sample_suspects_range.argtypes = [C.c_int64, p, p, p, p, p, C.c_int64, C.c_int,
+                                                C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(_Walks)]
+        L.orc_sample_suspects_list.argtypes = [C.c_int64, p, p, p, p, p, C.c_int64, C.c_int,
+                                               p, C.c_uint64, C.c_uint64, C.POINTER(_Walks)]
         L.orc_count.argtypes = [C.c_int64, C.c_uint64, p, p, p]
         L.orc_greedy.argtypes = [C.c_int64, C.c_uint64, p, p, C.c_int64, p, p]
         L.orc_estimates.argtypes = [C.c_int64, C.c_int64, C.c_uint64, C.c_uint64, C.c_uint64,
@@ -87,6 +94,20 @@ def draw_node(seed, attempt, node):
 
 def draw_start_word(seed, attempt):
     return int(lib().orc_draw_start_word(seed, attempt))
+
+
+def draw_node_word(seed, attempt, node):
+    """Word 0 of the block with counter (node,0,0,0): high half = live-edge
+    draw, low half = seed coin."""
+    return int(lib().orc_draw_node_word(seed, attempt, node))
+
+
+def coin_thresholds(p):
+    """pq = min(round-half-even(p * 2^32), 2^32 - 1) per suspect."""
+    p = np.ascontiguousarray(p, dtype=np.float32)
+    out = np.zeros(p.shape[0], dtype=np.uint32)
+    _check(lib().orc_coin_thresholds(_ptr(p), p.shape[0], _ptr(out)), "coin thresholds")
+    return out
 
 
 def scale_u64(x0, count):
@@ -180,6 +201,35 @@ class Graph:
         finally:
             L.orc_walks_free(C.byref(s))
 
+    def _sample_suspects(self, suspects, p, mode, seed, attempts=None, n_attempts=0, offset=0):
+        sus = np.ascontiguousarray(suspects, dtype=np.int32)
+        pr = np.ascontiguousarray(p, dtype=np.float32)
+        assert sus.shape == pr.shape
+        s = _Walks()
+        L = lib()
+        if attempts is None:
+            rc = L.orc_sample_suspects_range(self.n, _ptr(self.col_off), _ptr(self.row_idx), _ptr(self.thr),
+                                             _ptr(sus), _ptr(pr), sus.shape[0], mode, n_attempts, offset,
+                                             seed, C.byref(s))
+        else:
+            at = np.ascontiguousarray(attempts, dtype=np.uint64)
+            rc = L.orc_sample_suspects_list(self.n, _ptr(self.col_off), _ptr(self.row_idx), _ptr(self.thr),
+                                            _ptr(sus), _ptr(pr), sus.shape[0], mode, _ptr(at), at.shape[0],
+                                            seed, C.byref(s))
+        try:
+            _check(rc, "sample (suspects)")
+            return Walks(s)
+        finally:
+            L.orc_walks_free(C.byref(s))
+
+    def sample_suspects(self, suspects, p, mode, n_attempts, offset=0, seed=0):
+        """Attempts with probabilistic suspects (suspects[i] a seed with
+        probability p[i]); start uniform over V."""
+        return self._sample_suspects(suspects, p, mode, seed, n_attempts=n_attempts, offset=offset)
+
+    def sample_suspects_list(self, suspects, p, mode, attempts, seed=0):
+        return self._sample_suspects(suspects, p, mode, seed, attempts=attempts)
+
     def sample(self, sources, mode, n_attempts, offset=0, seed=0):
         return self._sample(sources, mode, seed, n_attempts=n_attempts, offset=offset)
 
@@ -214,6 +264,18 @@ def estimates(n, n_sources, n_attempts, hits, covered, sources_selected=0):
     lib().orc_estimates(n, n_sources, n_attempts, hits, covered, sources_selected,
                         C.byref(a), C.byref(b), C.byref(c))
     return a.value, b.value, c.value
+
+
+def solve_suspects(graph: Graph, suspects, p, mode, k, n_attempts, offset=0, seed=0):
+    """The whole path with probabilistic suspects: sample (start uniform over
+    V), count, greedy; estimates I(V_I) ~ n hits / N and D(T) ~ n Cov(T) / N
+    (a removed seed's own walk <v_1> is one of the covered walks)."""
+    walks = graph.sample_suspects(suspects, p, mode, n_attempts, offset, seed)
+    id_space = graph.m if mode == MODE_EDGES else graph.n
+    sel, gains = greedy(id_space, walks, k)
+    covered = int(gains.sum())
+    spread, susp, _ = estimates(graph.n, 0, n_attempts, walks.hits, covered, 0)
+    return dict(walks=walks, selected=sel, gains=gains, covered=covered, spread=spread, suspension=susp)
 
 
 def solve(graph: Graph, sources, mode, k, n_attempts, offset=0, seed=0):

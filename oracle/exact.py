@@ -20,6 +20,14 @@ Three independent routes to the quantities the sampler estimates, all in
 Theorem "lem:rr_edge" / "lem:rr_node" say routes 1 and 2 give the same
 suspension; the tests check that they agree exactly.
 
+Probabilistic suspects (Section 2.2: V_I = (V_I, p), seed sets X drawn with
+the probability of equation "prob_src_set") have their own three routes:
+``hsaw_paths_p`` (equation "compute_path_inf" with its factor p(v_l) times
+(1 - p(u)) over the other suspects on the walk), ``live_edge_spread_p``
+(every live-edge graph times every seed set X within V_I, the definitions
+"def:eis" and "sus_nod" written out) and ``walk_tree_p`` (the sampling
+process with a coin per suspect, start uniform over V).
+
 Edge probabilities come in two flavours:
 
 * ``exact_edge_probs``: the real-valued LT weights, as exact rationals;
@@ -282,3 +290,168 @@ def subdivide(col_off, row_idx, w):
             raise ValueError("column weight sum above 1")
         p_none.append(1 - s)
     return TinyGraph(new_off, new_row, p_edge, p_none)
+
+
+# ---------------------------------------------------------------- probabilistic suspects
+def coin_probs_exact(p):
+    """Suspect probabilities as exact rationals of their fp32 values."""
+    return [Fraction(float(np.float32(x))) for x in p]
+
+
+def coin_probs_quantized(p):
+    """The discretised coin the sampler realises: x is a seed when a 32-bit
+    draw is below pq = min(round-half-even(p * 2^32), 2^32 - 1)."""
+    return [Fraction(min(round(Fraction(float(np.float32(x))) * TWO32), TWO32 - 1), TWO32) for x in p]
+
+
+def hsaw_paths_p(g: TinyGraph, suspects, probs):
+    """Route 1 with probabilistic suspects: every HSAW h = <v_1 .. v_l> (any
+    start v_1, distinct nodes, v_l a suspect; l = 1 when v_1 itself is one)
+    with Pr[h] = p(v_l) * prod over the other suspects u on h of (1 - p(u))
+    * prod of its edge probabilities (equation "compute_path_inf").  Returns
+    (start, nodes, edges, probability)."""
+    P = {int(v): q for v, q in zip(suspects, probs)}
+    out = []
+
+    def dfs(start, nodes, edges, prob):
+        x = nodes[-1]
+        if x in P:
+            if P[x] > 0:
+                out.append((start, tuple(nodes), tuple(edges), prob * P[x]))
+            prob = prob * (1 - P[x])  # x is not a seed: the walk goes on
+            if prob == 0:
+                return
+        for j in g.in_edges(x):
+            pj = g.p_edge[j]
+            if pj == 0:
+                continue
+            u = g.row_idx[j]
+            if u in nodes:
+                continue
+            dfs(start, nodes + [u], edges + [j], prob * pj)
+
+    for v in range(g.n):
+        dfs(v, [v], [], Fraction(1))
+    return out
+
+
+def spread_p_from_paths(g: TinyGraph, suspects, probs):
+    """I(V_I) = sum over nodes of Pr[the node is infected] = sum of Pr[h]
+    over all HSAWs (walk uniqueness: the HSAWs from one start are disjoint
+    events)."""
+    return sum((p for (_, _, _, p) in hsaw_paths_p(g, suspects, probs)), Fraction(0))
+
+
+def suspension_p_from_paths(g: TinyGraph, suspects, probs, removed, mode):
+    """D(T) = sum of Pr[h] over the HSAWs T interdicts (Theorems "lem:rr_edge"
+    / "lem:rr_node"); for nodes a walk holds its start and its end."""
+    removed = set(int(x) for x in removed)
+    total = Fraction(0)
+    for (_, nodes, edges, p) in hsaw_paths_p(g, suspects, probs):
+        if removed.intersection(edges if mode == "edges" else nodes):
+            total += p
+    return total
+
+
+def live_edge_spread_p(g: TinyGraph, suspects, probs, removed=(), mode="edges"):
+    """Route 2: I(V_I) in the network after removing the edge set (mode
+    'edges') or node set ('nodes'), by summing over every live-edge graph
+    and every seed set X within V_I (probability of equation
+    "prob_src_set"; a removed node is neither a seed nor counted)."""
+    sus = [int(v) for v in suspects]
+    removed = set(int(x) for x in removed)
+    choices = []
+    for v in range(g.n):
+        opts = [(None, g.p_none[v])] if g.p_none[v] > 0 else []
+        opts += [(j, g.p_edge[j]) for j in g.in_edges(v) if g.p_edge[j] > 0]
+        choices.append(opts)
+    seed_sets = []
+    for bits in product((0, 1), repeat=len(sus)):
+        pr = Fraction(1)
+        X = set()
+        for v, b, q in zip(sus, bits, probs):
+            pr *= q if b else 1 - q
+            if b:
+                X.add(v)
+        if pr:
+            seed_sets.append((X, pr))
+    total = Fraction(0)
+    for combo in product(*choices):
+        prob = Fraction(1)
+        parent = [None] * g.n
+        for v, (j, pj) in enumerate(combo):
+            prob *= pj
+            if j is None:
+                continue
+            u = g.row_idx[j]
+            if mode == "edges" and j in removed:
+                continue
+            if mode == "nodes" and (u in removed or v in removed):
+                continue
+            parent[v] = u
+        # the nodes on each node's backward trace (at most one in-edge each)
+        traces = []
+        for v in range(g.n):
+            if mode == "nodes" and v in removed:
+                continue
+            seen, x, tr = set(), v, []
+            while x is not None and x not in seen:
+                seen.add(x)
+                tr.append(x)
+                x = parent[x]
+            traces.append(tr)
+        for X, px in seed_sets:
+            Xr = X - removed if mode == "nodes" else X
+            infected = sum(1 for tr in traces if any(x in Xr for x in tr))
+            total += prob * px * infected
+    return total
+
+
+def walk_tree_p(g: TinyGraph, suspects, probs):
+    """Route 3: the exact law of one sampler attempt with probabilistic
+    suspects -- start uniform over V; on arriving at a node: a node already
+    on the walk ends it (cycle), a suspect is a seed with its probability
+    (hit), else the live in-edge is drawn (no edge: dead end).  Returns the
+    outcome probabilities, expected draws, and the kept walks' law
+    {(nodes, edges): probability}."""
+    P = {int(v): q for v, q in zip(suspects, probs)}
+    res = dict(hit=Fraction(0), dead_end=Fraction(0), cycle=Fraction(0), steps=Fraction(0))
+    walks = {}
+
+    def arrive(nodes, edges, prob):
+        x = nodes[-1]
+        if x in P and P[x] > 0:
+            q = prob * P[x]
+            res["hit"] += q
+            key = (tuple(nodes), tuple(edges))
+            walks[key] = walks.get(key, Fraction(0)) + q
+            prob = prob * (1 - P[x])
+            if prob == 0:
+                return
+        res["steps"] += prob  # one draw
+        if g.p_none[x] > 0:
+            res["dead_end"] += prob * g.p_none[x]
+        for j in g.in_edges(x):
+            pj = g.p_edge[j]
+            if pj == 0:
+                continue
+            u = g.row_idx[j]
+            if u in nodes:
+                res["cycle"] += prob * pj
+            else:
+                arrive(nodes + [u], edges + [j], prob * pj)
+
+    for v in range(g.n):
+        arrive([v], [], Fraction(1, g.n))
+    res["walks"] = walks
+    return res
+
+
+def id_frequencies_p(g: TinyGraph, suspects, probs, mode):
+    """Exact Pr[id lies on the kept walk of one attempt], suspect coins."""
+    size = g.m if mode == "edges" else g.n
+    freq = [Fraction(0)] * size
+    for (nodes, edges), p in walk_tree_p(g, suspects, probs)["walks"].items():
+        for i in (edges if mode == "edges" else nodes):
+            freq[i] += p
+    return freq

@@ -37,6 +37,22 @@
  *  R5  Greedy ties go to the lowest id; once every marginal gain is zero
  *      the round takes the lowest id not yet selected, so exactly k ids
  *      are always returned.
+ *
+ * Probabilistic suspects (Section 2.2: V_I = (V_I, p), a seed set X drawn
+ * with probability given by equation "prob_src_set"; Algorithm 1's test "u
+ * in V_I and rand() <= p(u)"), in place of R3 and R4:
+ *  R6  p is discretised as the weights are: pq = min(round-half-even(p *
+ *      2^32), 2^32 - 1); node x is a seed in attempt a when the low 32 bits
+ *      of its draw word (word 0 of counter (x,0,0,0), whose high half picks
+ *      its live in-edge) are below pq(x).  One coin per node and attempt, so
+ *      the seeds of an attempt are one draw of X.
+ *  R7  The start is uniform over all of V, floor(x0 * n / 2^64), as
+ *      Algorithm 1 picks it; a start that is a seed gives the walk <v_1>
+ *      (no edge).
+ *  R8  A node is tested when the walk arrives at it: a node already on the
+ *      walk ends it as a cycle (its coin came up "not a seed" on the first
+ *      visit, so the order of the two tests does not matter), else a seed
+ *      ends it as a kept walk, else its live in-edge is drawn.
  */
 #include <math.h>
 #include <stdint.h>
@@ -114,6 +130,17 @@ uint32_t orc_draw_node(uint64_t seed, uint64_t attempt, uint32_t node)
     uint64_t out[4];
     orc_philox4x64_10(ctr, key, out);
     return (uint32_t)(out[0] >> 32);
+}
+
+/* Word 0 of the block with counter (x,0,0,0): high half = live-edge draw
+ * of node x, low half = its seed coin (readings R2, R6). */
+uint64_t orc_draw_node_word(uint64_t seed, uint64_t attempt, uint32_t node)
+{
+    uint64_t key[2] = {seed, attempt};
+    uint64_t ctr[4] = {node, 0, 0, 0};
+    uint64_t out[4];
+    orc_philox4x64_10(ctr, key, out);
+    return out[0];
 }
 
 /* ------------------------------------------------------------------ */
@@ -360,6 +387,152 @@ int orc_sample_list(int64_t n, const int64_t *col_off, const int32_t *row_idx,
     for (uint64_t i = 0; rc == ORC_OK && i < count; ++i)
         rc = sample_one_into(&S, attempt_ids[i], out);
     sampler_free(&S);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Probabilistic suspects (readings R6-R8).                             */
+/* ------------------------------------------------------------------ */
+
+/* pq = min(round-half-even(p * 2^32), 2^32 - 1) for p in [0, 1]. */
+int orc_coin_thresholds(const float *p, int64_t count, uint32_t *pq_out)
+{
+    for (int64_t i = 0; i < count; ++i) {
+        float x = p[i];
+        if (!(x >= 0.0f && x <= 1.0f))
+            return ORC_EINVAL;
+        uint64_t q = (uint64_t)llrint(ldexp((double)x, 32));
+        pq_out[i] = q > 0xFFFFFFFFULL ? 0xFFFFFFFFU : (uint32_t)q;
+    }
+    return ORC_OK;
+}
+
+typedef struct {
+    int64_t n;
+    const int64_t *col_off;
+    const int32_t *row_idx;
+    const uint32_t *thr;
+    int mode;
+    uint64_t seed;
+    uint8_t *is_suspect;   /* [n] */
+    uint32_t *coin_thr;    /* [n] pq of each suspect */
+    uint64_t *stamp;       /* [n] attempt+1 that last put the node on its path */
+    int32_t *path_nodes;   /* [n] */
+    uint32_t *path_edges;  /* [n] */
+} psampler_t;
+
+static void psampler_free(psampler_t *S)
+{
+    free(S->is_suspect); free(S->coin_thr); free(S->stamp);
+    free(S->path_nodes); free(S->path_edges);
+}
+
+static int psampler_setup(psampler_t *S, int64_t n, const int64_t *col_off,
+                          const int32_t *row_idx, const uint32_t *thr,
+                          const int32_t *suspects, const float *p,
+                          int64_t n_suspects, int mode, uint64_t seed)
+{
+    memset(S, 0, sizeof(*S));
+    if (n < 1 || n_suspects < 0 || n_suspects > n) return ORC_EINVAL;
+    if (mode != ORC_MODE_EDGES && mode != ORC_MODE_NODES) return ORC_EINVAL;
+    S->n = n; S->col_off = col_off; S->row_idx = row_idx; S->thr = thr;
+    S->mode = mode; S->seed = seed;
+    S->is_suspect = calloc((size_t)n, 1);
+    S->coin_thr = calloc((size_t)n, sizeof(uint32_t));
+    S->stamp = calloc((size_t)n, sizeof(uint64_t));
+    S->path_nodes = malloc((size_t)n * sizeof(int32_t));
+    S->path_edges = malloc((size_t)n * sizeof(uint32_t));
+    if (!S->is_suspect || !S->coin_thr || !S->stamp || !S->path_nodes || !S->path_edges)
+        return ORC_ENOMEM;
+    for (int64_t i = 0; i < n_suspects; ++i) {
+        int32_t x = suspects[i];
+        if (x < 0 || x >= n || S->is_suspect[x]) return ORC_EINVAL;
+        int rc = orc_coin_thresholds(&p[i], 1, &S->coin_thr[x]);
+        if (rc != ORC_OK) return rc;
+        S->is_suspect[x] = 1;
+    }
+    return ORC_OK;
+}
+
+/* Is x a seed in attempt a (reading R6)? */
+static int is_seed(const psampler_t *S, uint64_t a, int32_t x)
+{
+    if (!S->is_suspect[x]) return 0;
+    uint32_t coin = (uint32_t)orc_draw_node_word(S->seed, a, (uint32_t)x);
+    return coin < S->coin_thr[x];
+}
+
+/* One attempt (Algorithm 1 with suspect coins, readings R6-R8). */
+static int pwalk_one(psampler_t *S, uint64_t a, uint64_t *steps_out, uint64_t *len)
+{
+    uint64_t idx = orc_scale_u64(orc_draw_start_word(S->seed, a), (uint64_t)S->n);
+    int32_t v = (int32_t)idx;
+    uint64_t tag = a + 1;
+    uint64_t n_nodes = 0, n_edges = 0, s = 0;
+    S->path_nodes[n_nodes++] = v;
+    S->stamp[v] = tag;
+    for (;;) {
+        if (is_seed(S, a, v)) {
+            *steps_out = s;
+            *len = (S->mode == ORC_MODE_EDGES) ? n_edges : n_nodes;
+            return ORC_HIT;
+        }
+        uint32_t r = orc_draw_node(S->seed, a, (uint32_t)v);
+        s += 1;
+        int64_t j = orc_select_edge(S->col_off[v], S->col_off[v + 1], S->thr, r);
+        if (j < 0) { *steps_out = s; return ORC_DEAD_END; }
+        int32_t u = S->row_idx[j];
+        S->path_edges[n_edges++] = (uint32_t)j;
+        if (S->stamp[u] == tag) { *steps_out = s; return ORC_CYCLE; }
+        S->stamp[u] = tag;
+        S->path_nodes[n_nodes++] = u;
+        v = u;
+    }
+}
+
+static int psample_one_into(psampler_t *S, uint64_t a, orc_walks *out)
+{
+    uint64_t steps = 0, len = 0;
+    int outcome = pwalk_one(S, a, &steps, &len);
+    out->attempts += 1;
+    out->steps += steps;
+    if (outcome == ORC_DEAD_END) { out->dead_ends += 1; return ORC_OK; }
+    if (outcome == ORC_CYCLE) { out->cycles += 1; return ORC_OK; }
+    out->hits += 1;
+    const uint32_t *ids = (S->mode == ORC_MODE_EDGES)
+                              ? S->path_edges
+                              : (const uint32_t *)S->path_nodes;
+    return walks_push(out, a, ids, len);
+}
+
+/* Attempts attempt_offset .. attempt_offset+n_attempts-1 with suspects
+ * suspects[i] of probability p[i] (distinct ids, any order). */
+int orc_sample_suspects_range(int64_t n, const int64_t *col_off, const int32_t *row_idx,
+                              const uint32_t *thr, const int32_t *suspects, const float *p,
+                              int64_t n_suspects, int mode, uint64_t n_attempts,
+                              uint64_t attempt_offset, uint64_t seed, orc_walks *out)
+{
+    memset(out, 0, sizeof(*out));
+    psampler_t S;
+    int rc = psampler_setup(&S, n, col_off, row_idx, thr, suspects, p, n_suspects, mode, seed);
+    for (uint64_t i = 0; rc == ORC_OK && i < n_attempts; ++i)
+        rc = psample_one_into(&S, attempt_offset + i, out);
+    psampler_free(&S);
+    return rc;
+}
+
+/* The listed attempts, in the given order. */
+int orc_sample_suspects_list(int64_t n, const int64_t *col_off, const int32_t *row_idx,
+                             const uint32_t *thr, const int32_t *suspects, const float *p,
+                             int64_t n_suspects, int mode, const uint64_t *attempt_ids,
+                             uint64_t count, uint64_t seed, orc_walks *out)
+{
+    memset(out, 0, sizeof(*out));
+    psampler_t S;
+    int rc = psampler_setup(&S, n, col_off, row_idx, thr, suspects, p, n_suspects, mode, seed);
+    for (uint64_t i = 0; rc == ORC_OK && i < count; ++i)
+        rc = psample_one_into(&S, attempt_ids[i], out);
+    psampler_free(&S);
     return rc;
 }
 
