@@ -200,6 +200,32 @@ sia_status sia_greedy(int64_t id_space, const uint64_t *walk_off, const uint32_t
                       void *hip_stream);
 
 /*
+ * sia_greedy for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same greedy, the same answer, with every array in device memory and
+ * no hipMalloc / hipFree.  The buffers its kernels need (walk lengths,
+ * coverage counts, the greedy's state, pool, walk lists and counting
+ * partition) come from one static device array of 64 MiB per device,
+ * reserved while the library is loaded and shared by every call on that
+ * device: calls that overlap on one device race and must be serialised by
+ * the caller (each call starts from cleared state).
+ *   id_space   ids are in [0, id_space); 1 <= k <= id_space
+ *   walk_off   device uint64[n_walks+1] (walk_off[0] = 0, non-decreasing);
+ *              ids device uint32[walk_off[n_walks]], each walk holding an id
+ *              at most once
+ *   selected   device int64[k] (out); gains device uint64[k] (out)
+ * Limit: about 8.2 id_space + 8 n_ids + 12 n_walks + 16 k bytes plus 3 MB
+ * of scratch must fit in 64 MiB (for example id_space = 10^6, 3.5 * 10^6
+ * ids in 5 * 10^5 walks); larger inputs are rejected with SIA_EINVAL and a
+ * message giving the bytes needed.  Malformed walks (decreasing offsets, an
+ * id outside the id space): SIA_EINVAL.  Synchronises hip_stream (it reads
+ * the walk count and the greedy's progress back to the host).
+ */
+sia_status sia_greedy_noalloc(int64_t id_space, const uint64_t *walk_off, const uint32_t *ids,
+                              uint64_t n_walks, int64_t k, int64_t *selected, uint64_t *gains,
+                              void *hip_stream);
+
+/*
  * The whole hot path for one query (eSIA / nSIA with a fixed sample count):
  * sample as sia_sample, count coverage, greedy as sia_greedy over the kept
  * walks, and the estimates of Theorem "lem:rr_edge" / "lem:rr_node".

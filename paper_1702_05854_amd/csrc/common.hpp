@@ -189,8 +189,9 @@ struct GreedyInput {
     uint32_t *cnt = nullptr;    // id_space coverage counts (device), written here
     const uint32_t *cand = nullptr;  // candidate bitmap over [0, id_space) (device); NULL: every id
     void *scratch = nullptr;
-    int64_t *selected = nullptr;  // k entries each; host memory
-    uint64_t *gains = nullptr;
+    int64_t *selected = nullptr;  // k entries each; host memory (device memory
+    uint64_t *gains = nullptr;    // when out_on_device: written in place)
+    bool out_on_device = false;
     uint32_t rounds_seen = 0;     // progress bookkeeping
 };
 size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids, int64_t k);

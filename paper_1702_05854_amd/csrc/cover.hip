@@ -1477,6 +1477,10 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
                     "k must be in [1, id space]");
         SIA_REQUIRE(g.cnt && g.scratch && g.selected && g.gains, SIA_EINVAL, "greedy job buffers");
         jobs[q] = carve(g);
+        if (g.out_on_device) {  // the rounds write the caller's device arrays
+            jobs[q].sel = g.selected;
+            jobs[q].gain = g.gains;
+        }
         g.rounds_seen = 0;
         max_S = std::max(max_S, g.id_space);
         max_walks = std::max(max_walks, g.n_walks);
@@ -1559,6 +1563,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     }
     if (timing) SIA_HIP(hipEventRecord(ev[2], s));
     for (uint32_t q = 0; q < Q; ++q) {
+        if (in[q].out_on_device) continue;
         SIA_HIP(hipMemcpyAsync(in[q].selected, jobs[q].sel, sizeof(int64_t) * in[q].k,
                                hipMemcpyDeviceToHost, s));
         SIA_HIP(hipMemcpyAsync(in[q].gains, jobs[q].gain, sizeof(uint64_t) * in[q].k,

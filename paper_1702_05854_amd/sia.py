@@ -142,6 +142,8 @@ def lib():
         L.sia_evaluate.argtypes = [p, i32, p, i64, p, i64, u64, u64, u64, C.POINTER(Stats), p]
         L.sia_sas_solve.argtypes = [p, i32, p, i64, i64, C.c_double, C.c_double, u64, u64, p, p,
                                     C.POINTER(SasInfo), p]
+        L.sia_greedy_noalloc.argtypes = [i64, p, p, u64, i64, p, p, p]
+        L.sia_greedy_noalloc.restype = C.c_int
         L.sia_test_fail_alloc.argtypes = [C.c_uint32]
         L.sia_test_fail_alloc.restype = None
         L.sia_sas_params.argtypes = [i64, i64, C.c_double, C.c_double, C.POINTER(C.c_double),
@@ -285,6 +287,22 @@ def greedy(id_space, walk_off, ids, k, stream=None):
     gains = np.zeros(k, dtype=np.uint64)
     _check(lib().sia_greedy(id_space, _hptr(off), _hptr(ids), off.shape[0] - 1, k, _hptr(sel),
                             _hptr(gains), _stream(stream)))
+    return sel, gains
+
+
+def greedy_noalloc(id_space, walk_off, ids, k, stream=None):
+    """The greedy of ``greedy`` on walks in device memory, through the entry
+    point that allocates no device memory itself (sia_greedy_noalloc).
+    walk_off / ids: device tensors (int64 or uint64 offsets, int32 ids);
+    returns device tensors (selected int64[k], gains int64[k] holding the
+    uint64 gains)."""
+    import torch
+    assert walk_off.is_cuda and ids.is_cuda and walk_off.dtype == torch.int64 and ids.dtype == torch.int32
+    sel = torch.empty(k, dtype=torch.int64, device=walk_off.device)
+    gains = torch.empty(k, dtype=torch.int64, device=walk_off.device)
+    _check(lib().sia_greedy_noalloc(id_space, C.c_void_p(walk_off.data_ptr()), C.c_void_p(ids.data_ptr()),
+                                    walk_off.numel() - 1, k, C.c_void_p(sel.data_ptr()),
+                                    C.c_void_p(gains.data_ptr()), _stream(stream)))
     return sel, gains
 
 
