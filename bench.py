@@ -56,6 +56,15 @@ def algorithmic_bytes(st):
     return 17 * s + 12 * (s - d) + 4 * st["walk_ids"] + 20 * st["hits"]
 
 
+def per_step_bytes(st, n_attempts, step_bytes):
+    """The flat reading of the same launch: step_bytes per plain step (node
+    record, the two bracketing thresholds, the tail id, membership), 4 bytes per
+    attempt for its start, and 4 bytes per id plus 16 per kept walk written.
+    29 bytes per step prices the two column offsets as 64-bit words, 21 as the
+    32-bit words the node records actually hold."""
+    return step_bytes * st["steps"] + 4 * n_attempts + 4 * st["walk_ids"] + 16 * st["hits"]
+
+
 def load_traffic():
     try:
         with open(TRAFFIC_FILE) as f:
@@ -292,11 +301,71 @@ def sas_bench(args, sia, wl, g, mode, k, ingest_ms):
 
 
 def sweep_bench(args):
-    """Scalability sweep (the shape of the paper's scalability experiment,
-    Section 6.3): uniform random graphs with n from 10^4 up to --sweep-max
-    nodes and m/n in {5, 10, 15}, w = 1/d_in, n/1000 sources (at least 10),
-    k = 100 edges, 10^7 attempts per point (fewer where the kept walks would
-    hold more than 2^30 ids); whole-path attempts/s."""
+    """Scalability sweep, as the paper's scalability test runs it (Section
+    6.3, "Scalability Test"): nSIA end to end -- the Stop-and-Stare driver
+    over the sampler, counts and greedy -- on uniform random graphs with n
+    from 10^4 to --sweep-max nodes and m/n in {5, 10, 15}; w = 1/d_in, 1000
+    random suspects with probabilities uniform in (0, 1), k = 100 nodes,
+    eps = 0.1, delta = 1/n (the experiments' settings, Section 6.1).  One
+    untimed run per point, then one timed run (wall time of the call).  At
+    n <= --sweep-check the oracle's driver runs the same point and its
+    iteration, sample sizes, picks and gains must be equal."""
+    import numpy as np
+    import torch
+    from paper_1702_05854_amd import sia, workloads
+
+    torch.cuda.set_device(0)
+    rows = []
+    n = 10_000
+    while n <= args.sweep_max:
+        for ratio in (5, 10, 15):
+            t0 = time.perf_counter()
+            wl = workloads.load("er1k", device="cuda", n=n, m=n * ratio, n_src=10, k=100, gseed=11 + ratio,
+                                sseed=211)
+            torch.cuda.synchronize()
+            gen_s = time.perf_counter() - t0
+            g = sia.Graph(wl.col_off, wl.row_idx, wl.w)
+            rng = np.random.default_rng(1000 + ratio)
+            sus = np.sort(rng.choice(n, 1000, replace=False)).astype(np.int32)
+            p = rng.uniform(0, 1, 1000).astype(np.float32)
+            sia.sas_solve_suspects(g, sus, p, "nodes", 100, 0.1, None, wl.seed)  # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = sia.sas_solve_suspects(g, sus, p, "nodes", 100, 0.1, None, wl.seed)
+            dt = time.perf_counter() - t1
+            I = r["info"]
+            row = {"n": n, "m": wl.m, "m_over_n": ratio, "seconds": dt, "status": I["status"], "t": I["t"],
+                   "n_t": I["n_t"], "attempts_sampled": I["attempts_sampled"], "eps_t": I["eps_t"],
+                   "gen_seconds": gen_s, "oracle_equal": None}
+            if n <= args.sweep_check:
+                from oracle import cpu, sas
+                og = cpu.Graph(*wl.host())
+                ref = sas.stop_and_stare(og, sus, cpu.MODE_NODES, 100, 0.1, None, wl.seed, p=p)
+                row["oracle_equal"] = bool(
+                    ref["status"] == "passed" and I["status"] == 1 and (I["t"], I["n_t"]) == (ref["t"], ref["n_t"])
+                    and np.array_equal(r["selected"], ref["selected"]) and np.array_equal(r["gains"], ref["gains"])
+                    and (I["cov_r"], I["cov_rp"]) == (ref["cov_r"], ref["cov_rp"]))
+                assert row["oracle_equal"], (n, ratio)
+            rows.append(row)
+            print(f"[bench] sweep n={n} m={wl.m}: nSIA {dt:.3f} s (t={I['t']}, N_t={I['n_t']}, "
+                  f"{I['attempts_sampled']} attempts; oracle equal: {row['oracle_equal']})", file=sys.stderr,
+                  flush=True)
+            g.close()
+            del wl, g
+            torch.cuda.empty_cache()
+        n *= 10
+    out = {"metric": "nSIA running time across graph sizes (scalability sweep, Stop-and-Stare end to end)",
+           "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "uniform random graphs, w = 1/d_in, 1000 suspects with p ~ U(0,1), "
+                                  "nSIA k = 100, eps = 0.1, delta = 1/n"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def sweep_fixed_bench(args):
+    """The sweep's graphs with a fixed sample count: eSIA, n/1000 sources, k =
+    100 edges, 10^7 attempts per point (fewer where the kept walks would hold
+    more than 2^30 ids); whole-path attempts/s."""
     import torch
     from paper_1702_05854_amd import sia, workloads
 
@@ -327,7 +396,7 @@ def sweep_bench(args):
             del wl, g
             torch.cuda.empty_cache()
         n *= 10
-    out = {"metric": "HSAW attempts/s across graph sizes (scalability sweep, whole path, edges)",
+    out = {"metric": "HSAW attempts/s across graph sizes (fixed-sample sweep, whole path, edges)",
            "unit": "attempts/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u32", "data": "synthetic",
            "config": {"workload": "uniform random graphs, w = 1/d_in, up to 10^7 attempts, k = 100"},
            "rows": rows}
@@ -363,8 +432,13 @@ def main():
                     help="time the Stop-and-Stare driver (eSIA / nSIA) on the workload instead")
     ap.add_argument("--eps", type=float, default=0.1, help="epsilon of the Stop-and-Stare driver (--sas)")
     ap.add_argument("--sweep", action="store_true",
-                    help="scalability sweep: attempts/s on random graphs, n = 10^4 .. --sweep-max, m/n = 5, 10, 15")
-    ap.add_argument("--sweep-max", type=int, default=10_000_000)
+                    help="scalability sweep: nSIA (Stop-and-Stare) time on random graphs, n = 10^4 .. --sweep-max, "
+                         "m/n = 5, 10, 15")
+    ap.add_argument("--sweep-fixed", action="store_true",
+                    help="the same graphs with a fixed sample count (eSIA attempts/s)")
+    ap.add_argument("--sweep-max", type=int, default=100_000_000)
+    ap.add_argument("--sweep-check", type=int, default=100_000,
+                    help="largest n whose sweep point is also run by the oracle and compared")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -375,6 +449,9 @@ def main():
         return
     if args.sweep:
         sweep_bench(args)
+        return
+    if args.sweep_fixed:
+        sweep_fixed_bench(args)
         return
 
     import torch
@@ -460,7 +537,10 @@ def main():
         "suspension_est": st["suspension_est"],
         "roofline": {"bound": "hbm", "kernel": "k_sample", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_launch": b_alg, "traffic": load_traffic()},
+                     "algorithmic_bytes_per_launch": b_alg, "traffic": load_traffic(),
+                     "frac_other_readings": {
+                         f"{sb} B/step flat": per_step_bytes(st, n_att, sb) / (ms_sample * 1e-3) / 1e9
+                         / HBM_PEAK_GBS for sb in (29, 21)}},
         "cpu_baseline": None,
     }
     g.close()

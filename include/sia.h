@@ -256,6 +256,33 @@ sia_status sia_solve_candidates(const sia_graph *g, int mode, const int32_t *sou
                                 uint64_t *gains, sia_stats *stats, int timing,
                                 void *hip_stream);
 
+/*
+ * Probabilistic suspects (Section 2.2: V_I = (V_I, p); a seed set X is drawn
+ * with probability prod_{u in X} p(u) prod_{v in V_I \ X} (1 - p(v)),
+ * equation "prob_src_set"; Algorithm 1's suspect test makes a suspect u met by
+ * the walk a seed with probability p(u)).
+ * Each attempt draws its own X: suspect x is a seed in attempt a when the
+ * low 32 bits of x's draw word (word 0 of counter (x,0,0,0), whose high half
+ * picks x's live in-edge) are below min(round-half-even(p(x) 2^32), 2^32-1).
+ * The start is uniform over all of V, floor(x0 * n / 2^64); the walk stops
+ * at the first seed it arrives at (the start included: a seed start gives the
+ * walk <v_1> with no edge), at a node already on it, or where no in-edge is
+ * live.  Estimates: I(V_I) ~ n hits / N, D(T) ~ n Cov(T) / N (Theorems
+ * "lem:rr_edge" / "lem:rr_node").
+ *   suspects  host int32[n_suspects], distinct, in [0,n); 1 <= n_suspects <= n
+ *   p         host float[n_suspects] in [0,1] (NaN rejected)
+ * Other arguments and outputs as sia_sample / sia_solve; stats.spread_est,
+ * suspension_est and suspension_nodes_est follow the estimates above.
+ * Errors as sia_sample / sia_solve (SIA_EINVAL for the suspects or p).
+ */
+sia_status sia_sample_suspects(const sia_graph *g, int mode, const int32_t *suspects, const float *p,
+                               int64_t n_suspects, uint64_t n_attempts, uint64_t attempt_offset,
+                               uint64_t seed, sia_walks *out, void *hip_stream);
+sia_status sia_solve_suspects(const sia_graph *g, int mode, const int32_t *suspects, const float *p,
+                              int64_t n_suspects, int64_t k, uint64_t n_attempts, uint64_t attempt_offset,
+                              uint64_t seed, int64_t *selected, uint64_t *gains, sia_stats *stats,
+                              int timing, void *hip_stream);
+
 /* Figures of a Stop-and-Stare run (sia_sas_solve). */
 typedef struct {
     int32_t status;        /* 1: Check passed at iteration t; 0: |R_t| reached
@@ -309,6 +336,15 @@ sia_status sia_sas_solve(const sia_graph *g, int mode, const int32_t *sources,
                          int64_t n_sources, int64_t k, double eps, double delta,
                          uint64_t seed, uint64_t max_attempts, int64_t *selected,
                          uint64_t *gains, sia_sas_info *info, void *hip_stream);
+
+/* sia_sas_solve with probabilistic suspects (suspects and p as in
+ * sia_sample_suspects): the HSAW stream is the kept walks of attempts
+ * 0, 1, 2, ... with a start uniform over V; spread_est = n n_t / attempts_r,
+ * suspension_est = suspension_nodes_est = n cov_r / attempts_r. */
+sia_status sia_sas_solve_suspects(const sia_graph *g, int mode, const int32_t *suspects, const float *p,
+                                  int64_t n_suspects, int64_t k, double eps, double delta, uint64_t seed,
+                                  uint64_t max_attempts, int64_t *selected, uint64_t *gains,
+                                  sia_sas_info *info, void *hip_stream);
 
 /*
  * The parameters sia_sas_solve uses, for id space S = id_space (m for

@@ -87,8 +87,8 @@ def coverage(off, ids, chosen, id_space):
 class _Stream:
     """Accepted walks in attempt-id order, sampled in growing attempt ranges."""
 
-    def __init__(self, graph, sources, mode, seed, chunk):
-        self.g, self.src, self.mode, self.seed = graph, sources, mode, seed
+    def __init__(self, graph, sources, mode, seed, chunk, p=None):
+        self.g, self.src, self.mode, self.seed, self.p = graph, sources, mode, seed, p
         self.chunk = chunk
         self.end = 0  # attempts [0, end) sampled
         self.attempt = np.zeros(0, np.uint64)
@@ -100,7 +100,10 @@ class _Stream:
             if self.end >= max_attempts:
                 return False
             c = min(self.chunk, max_attempts - self.end)
-            w = self.g.sample(self.src, self.mode, c, self.end, self.seed)
+            if self.p is None:
+                w = self.g.sample(self.src, self.mode, c, self.end, self.seed)
+            else:
+                w = self.g.sample_suspects(self.src, self.p, self.mode, c, self.end, self.seed)
             self.attempt = np.concatenate([self.attempt, w.attempt])
             self.lens = np.concatenate([self.lens, np.diff(w.off.astype(np.int64))])
             self.ids = np.concatenate([self.ids, w.ids])
@@ -116,15 +119,17 @@ class _Stream:
 
 
 def stop_and_stare(graph, sources, mode, k, eps=0.1, delta=None, seed=0, max_attempts=1 << 40,
-                   chunk=1 << 16):
+                   chunk=1 << 16, p=None):
     """eSIA (mode = cpu.MODE_EDGES) or nSIA (cpu.MODE_NODES) with a sample
     count chosen by Stop-and-Stare.  Returns the candidate of the last
-    iteration with the iteration's figures."""
+    iteration with the iteration's figures.  With p, sources are suspects
+    with those probabilities (the HSAW stream of the probabilistic
+    sampler)."""
     id_space = graph.m if mode == cpu.MODE_EDGES else graph.n
     if delta is None:
         delta = 1.0 / graph.n
     P = params(id_space, k, eps, delta)
-    st = _Stream(graph, sources, mode, seed, chunk)
+    st = _Stream(graph, sources, mode, seed, chunk, p)
     t = 0
     while True:
         t += 1

@@ -39,8 +39,9 @@
  *      are always returned.
  *
  * Probabilistic suspects (Section 2.2: V_I = (V_I, p), a seed set X drawn
- * with probability given by equation "prob_src_set"; Algorithm 1's test "u
- * in V_I and rand() <= p(u)"), in place of R3 and R4:
+ * with probability given by equation "prob_src_set"; Algorithm 1's suspect
+ * test, a suspect u the walk meets is a seed with probability p(u)), in place
+ * of R3 and R4:
  *  R6  p is discretised as the weights are: pq = min(round-half-even(p *
  *      2^32), 2^32 - 1); node x is a seed in attempt a when the low 32 bits
  *      of its draw word (word 0 of counter (x,0,0,0), whose high half picks

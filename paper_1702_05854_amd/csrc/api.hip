@@ -3,6 +3,7 @@
 #include "common.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstddef>
 #include <cstring>
@@ -34,6 +35,12 @@ void finish_stats(sia_stats &S, const SourceTables &st, int mode, uint64_t n_att
     S.attempts = n_attempts;
     S.covered = covered;
     const double n_ns = static_cast<double>(st.n_ns), N = static_cast<double>(n_attempts);
+    if (st.probabilistic) {  // starts over all of V; a seed's own walk is among the kept ones
+        S.spread_est = n_ns * static_cast<double>(S.hits) / N;
+        S.suspension_est = n_ns * static_cast<double>(covered) / N;
+        S.suspension_nodes_est = S.suspension_est;
+        return;
+    }
     S.spread_est = static_cast<double>(st.sorted.size()) + n_ns * static_cast<double>(S.hits) / N;
     S.suspension_est = n_ns * static_cast<double>(covered) / N;
     S.suspension_nodes_est = S.suspension_est + static_cast<double>(src_selected);
@@ -118,6 +125,34 @@ SourceTables build_source_tables(int64_t n, const int32_t *sources, int64_t n_so
     // whole 16-byte blocks: the sampler reads both tables a block at a time
     st.t.resize((st.t.size() + 3) & ~size_t(3), 0xFFFFFFFFu);
     st.bucket.resize((st.bucket.size() + 3) & ~size_t(3), static_cast<uint32_t>(n_sources));
+    return st;
+}
+
+SourceTables build_suspect_tables(int64_t n, const int32_t *suspects, const float *p, int64_t n_suspects)
+{
+    SIA_REQUIRE(n >= 2 && n < (int64_t(1) << 31), SIA_EINVAL, "n must be in [2, 2^31)");
+    SIA_REQUIRE(n_suspects >= 1 && n_suspects <= n, SIA_EINVAL, "need 1 <= n_suspects <= n");
+    SIA_REQUIRE(suspects != nullptr && p != nullptr, SIA_EINVAL, "suspects / p is NULL");
+    std::vector<std::pair<int32_t, uint32_t>> sp(static_cast<size_t>(n_suspects));
+    for (int64_t i = 0; i < n_suspects; ++i) {
+        SIA_REQUIRE(suspects[i] >= 0 && suspects[i] < n, SIA_EINVAL, "a suspect is outside [0, n)");
+        const float x = p[i];
+        SIA_REQUIRE(x >= 0.0f && x <= 1.0f, SIA_EINVAL, "a suspect probability is outside [0, 1] (or NaN)");
+        // the weights' rounding rule: round-half-even(p 2^32), clamped below 2^32
+        const uint64_t q = static_cast<uint64_t>(std::llrint(std::ldexp(static_cast<double>(x), 32)));
+        sp[static_cast<size_t>(i)] = {suspects[i], static_cast<uint32_t>(std::min<uint64_t>(q, 0xFFFFFFFFull))};
+    }
+    std::sort(sp.begin(), sp.end());
+    SourceTables st;
+    st.probabilistic = true;
+    st.n_ns = static_cast<uint64_t>(n);
+    for (size_t i = 0; i < sp.size(); ++i) {
+        SIA_REQUIRE(i == 0 || sp[i].first != sp[i - 1].first, SIA_EINVAL, "suspects must be distinct");
+        st.sorted.push_back(sp[i].first);
+        st.coin.push_back(sp[i].second);
+    }
+    st.t.assign(4, 0xFFFFFFFFu);  // unused (no rank among sources): one block
+    st.bucket.assign(4, 0u);
     return st;
 }
 
@@ -233,19 +268,10 @@ void sia_walks_free(sia_walks *w)
     w->n_walks = w->n_ids = 0;
 }
 
-sia_status sia_sample(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
-                      uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
-                      sia_walks *out, void *hip_stream)
+static void sample_impl(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
+                        uint64_t attempt_offset, uint64_t seed, sia_walks *out, hipStream_t s)
 {
-    return guarded([&] {
-        SIA_REQUIRE(cg != nullptr && out != nullptr, SIA_EINVAL, "NULL argument");
-        std::memset(out, 0, sizeof(*out));
-        sia_graph *g = const_cast<sia_graph *>(cg);
-        check_query(g->n, g->m, mode, sources, n_sources, 0, n_attempts, attempt_offset);
-        std::lock_guard<std::mutex> lock(g->mu);
-        DeviceScope ds(g->device);
-        hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        const SourceTables st = build_source_tables(g->n, sources, n_sources);
+    {
         const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, false);
 
         std::vector<uint64_t> att(r.walks), off(r.walks);
@@ -289,7 +315,40 @@ sia_status sia_sample(const sia_graph *cg, int mode, const int32_t *sources, int
         S.evaluations = r.evals;
         S.walk_ids = r.ids;
         const double n_ns = static_cast<double>(st.n_ns);
-        S.spread_est = static_cast<double>(n_sources) + n_ns * r.hits / static_cast<double>(n_attempts);
+        S.spread_est = (st.probabilistic ? 0.0 : static_cast<double>(st.sorted.size())) +
+                       n_ns * r.hits / static_cast<double>(n_attempts);
+    }
+}
+
+sia_status sia_sample(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
+                      uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
+                      sia_walks *out, void *hip_stream)
+{
+    return guarded([&] {
+        SIA_REQUIRE(cg != nullptr && out != nullptr, SIA_EINVAL, "NULL argument");
+        std::memset(out, 0, sizeof(*out));
+        sia_graph *g = const_cast<sia_graph *>(cg);
+        check_query(g->n, g->m, mode, sources, n_sources, 0, n_attempts, attempt_offset);
+        std::lock_guard<std::mutex> lock(g->mu);
+        DeviceScope ds(g->device);
+        sample_impl(g, mode, build_source_tables(g->n, sources, n_sources), n_attempts, attempt_offset, seed, out,
+                    static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+sia_status sia_sample_suspects(const sia_graph *cg, int mode, const int32_t *suspects, const float *p,
+                               int64_t n_suspects, uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
+                               sia_walks *out, void *hip_stream)
+{
+    return guarded([&] {
+        SIA_REQUIRE(cg != nullptr && out != nullptr, SIA_EINVAL, "NULL argument");
+        std::memset(out, 0, sizeof(*out));
+        sia_graph *g = const_cast<sia_graph *>(cg);
+        const SourceTables st = build_suspect_tables(g->n, suspects, p, n_suspects);
+        check_query(g->n, g->m, mode, st.sorted.data(), 1, 0, n_attempts, attempt_offset);  // mode, attempts
+        std::lock_guard<std::mutex> lock(g->mu);
+        DeviceScope ds(g->device);
+        sample_impl(g, mode, st, n_attempts, attempt_offset, seed, out, static_cast<hipStream_t>(hip_stream));
     });
 }
 
@@ -327,8 +386,9 @@ sia_status sia_greedy(int64_t id_space, const uint64_t *walk_off, const uint32_t
     });
 }
 
-static sia_status solve_impl(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
-                             const int64_t *candidates, int64_t n_candidates, int64_t k,
+// p != NULL: sources are suspects with these probabilities
+static sia_status solve_impl(const sia_graph *cg, int mode, const int32_t *sources, const float *p,
+                             int64_t n_sources, const int64_t *candidates, int64_t n_candidates, int64_t k,
                              uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
                              int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
                              void *hip_stream)
@@ -337,7 +397,10 @@ static sia_status solve_impl(const sia_graph *cg, int mode, const int32_t *sourc
         SIA_REQUIRE(cg != nullptr && selected != nullptr && gains != nullptr, SIA_EINVAL,
                     "NULL argument");
         sia_graph *g = const_cast<sia_graph *>(cg);
-        check_query(g->n, g->m, mode, sources, n_sources, k, n_attempts, attempt_offset);
+        const SourceTables st = p ? build_suspect_tables(g->n, sources, p, n_sources)
+                                  : (check_query(g->n, g->m, mode, sources, n_sources, k, n_attempts, attempt_offset),
+                                     build_source_tables(g->n, sources, n_sources));
+        if (p) check_query(g->n, g->m, mode, st.sorted.data(), 1, k, n_attempts, attempt_offset);
         SIA_REQUIRE(k >= 1, SIA_EINVAL, "k must be >= 1");
         const int64_t id_space_c = mode == SIA_EDGES ? cg->m : cg->n;
         std::vector<uint32_t> cand_bits;
@@ -361,7 +424,6 @@ static sia_status solve_impl(const sia_graph *cg, int mode, const int32_t *sourc
             SIA_HIP(hipEventCreate(&e1));
             SIA_HIP(hipEventRecord(e0, s));
         }
-        const SourceTables st = build_source_tables(g->n, sources, n_sources);
         // counts are taken by the greedy's counting pass: atomics fused into the
         // sampler's emission cost it 15% on rmat24 (their random lines compete
         // with its gathers)
@@ -405,7 +467,20 @@ sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int6
                      int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
                      void *hip_stream)
 {
-    return solve_impl(cg, mode, sources, n_sources, nullptr, 0, k, n_attempts, attempt_offset, seed,
+    return solve_impl(cg, mode, sources, nullptr, n_sources, nullptr, 0, k, n_attempts, attempt_offset, seed,
+                      selected, gains, stats, timing, hip_stream);
+}
+
+sia_status sia_solve_suspects(const sia_graph *cg, int mode, const int32_t *suspects, const float *p,
+                              int64_t n_suspects, int64_t k, uint64_t n_attempts, uint64_t attempt_offset,
+                              uint64_t seed, int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
+                              void *hip_stream)
+{
+    if (!p) {
+        sia::set_error("p is NULL");
+        return SIA_EINVAL;
+    }
+    return solve_impl(cg, mode, suspects, p, n_suspects, nullptr, 0, k, n_attempts, attempt_offset, seed,
                       selected, gains, stats, timing, hip_stream);
 }
 
@@ -419,7 +494,7 @@ sia_status sia_solve_candidates(const sia_graph *cg, int mode, const int32_t *so
         sia::set_error("candidates is NULL");
         return SIA_EINVAL;
     }
-    return solve_impl(cg, mode, sources, n_sources, candidates, n_candidates, k, n_attempts,
+    return solve_impl(cg, mode, sources, nullptr, n_sources, candidates, n_candidates, k, n_attempts,
                       attempt_offset, seed, selected, gains, stats, timing, hip_stream);
 }
 

@@ -99,6 +99,8 @@ struct Workspace {
     DevBuf src_sorted, src_t, bucket, bitmap;      // per-query source tables
     DevBuf cnt;                                    // coverage counts
     DevBuf greedy, jobs;                           // greedy scratch + job table
+    DevBuf ring;                                   // the sampler's walk ring
+    DevBuf coin_thr, coin_src;                     // suspects' coin thresholds: per node, per suspect
     uint64_t walk_cap = 0, id_cap = 0;
 };
 
@@ -126,10 +128,17 @@ struct SourceTables {
     // (t and bucket are padded to whole 16-byte blocks: 0xFFFFFFFF, |X|)
     uint32_t shift = 0;
     uint64_t n_ns = 0;
+    // probabilistic suspects (sorted holds them): the seed coin threshold of
+    // each, min(round-half-even(p 2^32), 2^32 - 1); start over all of V
+    bool probabilistic = false;
+    std::vector<uint32_t> coin;
 };
 void check_query(int64_t n, int64_t m, int mode, const int32_t *sources, int64_t n_sources,
                  int64_t k, uint64_t n_attempts, uint64_t attempt_offset);
 SourceTables build_source_tables(int64_t n, const int32_t *sources, int64_t n_sources);
+// Suspects with probabilities (checked: distinct ids in [0,n), 1 <= count <= n,
+// every p in [0,1]).
+SourceTables build_suspect_tables(int64_t n, const int32_t *suspects, const float *p, int64_t n_suspects);
 // Fill attempts, covered and the estimates of a finished query into S (whose
 // counters are already set).
 void finish_stats(sia_stats &S, const SourceTables &st, int mode, uint64_t n_attempts,
@@ -157,7 +166,10 @@ int sampler_max_blocks_per_cu(const sia_graph *g);  // for the graph's record fo
 // Sample the wave described by d_table (device) over the n_slots SlotDev
 // entries at d_slots (device).  Asynchronous on stream s.
 void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
-                 const WaveTable *d_table, const SamplerConfig &cfg, hipStream_t s);
+                 const WaveTable *d_table, const SamplerConfig &cfg, uint32_t *ring, hipStream_t s);
+// Bytes of the walk ring a launch on g needs (the largest grid; device memory
+// owned by the caller, contents need no clearing; one ring per concurrent launch).
+size_t sampler_ring_bytes(const sia_graph *g);
 // Set or clear the tag bit `mask` of the given sources (device array).
 void tag_sources(const sia_graph *g, const int32_t *d_src, uint32_t n_src, uint32_t mask, bool set,
                  hipStream_t s);

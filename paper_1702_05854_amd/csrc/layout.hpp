@@ -82,6 +82,11 @@ __device__ __forceinline__ uint64_t inv_indeg_quantum(uint32_t d)
     return quantize_weight(1.0f / static_cast<float>(d));
 }
 
+// Walk ring of the sampler: per wave, kRingRows rows of 64 lanes x 4 bytes;
+// a lane's walk position t (the chosen in-edge position for edges, the node
+// evaluated for nodes) sits in row (it0 + t) mod kRingRows of its column.
+constexpr uint32_t kRingRows = 1024;
+
 // Per-query counters written by the sampler.
 enum StatSlot {
     ST_WALKS = 0, ST_IDS = 1, ST_HITS = 2, ST_DEAD = 3, ST_CYCLE = 4, ST_STEPS = 5,
@@ -109,6 +114,9 @@ struct SlotDev {
     uint64_t walk_cap;
     uint64_t id_cap;
     uint64_t *counters;      // StatSlot entries
+    const uint32_t *coin_thr; // probabilistic suspects: per node, the seed coin's
+                              // threshold (read for tagged nodes only); NULL:
+                              // the tagged nodes are sources, start over V\X
 };
 
 // The work table a sampling launch reads from device memory: the wave's

@@ -14,16 +14,28 @@
 //    plain walk, mu + lambda, follows from a two-pointer pass from the start
 //    (the paper's heuristics had false negatives because its draws depended
 //    on the step, not the node).
-//  * A kept walk is re-walked to emit its ids, so no per-lane path storage
-//    is needed either.  Coverage counts are taken afterwards, in one pass
-//    over the written ids (atomics here would compete with the gathers).
+//  * Each wave keeps a ring of what its lanes evaluated: position t of a
+//    lane's walk goes to row it0 + t (it0: the iteration of its first
+//    evaluation).  A lane evaluates in consecutive iterations, so a row is
+//    mostly the same iteration of all 64 lanes and is written whole.  With
+//    the cycle length lambda known, the entry
+//    mu is the first position i with x_i == x_{i+lambda} -- false before mu,
+//    true from mu on -- found by bisection over the ring (two 4-byte reads
+//    per probe instead of walking the graph again), and a kept walk's ids are
+//    copied from the ring.  Walks longer than the ring fall back to a
+//    two-pointer pass from the start and a re-walk.  Coverage counts are
+//    taken afterwards, in one pass over the written ids (atomics here would
+//    compete with the gathers).
 //
 // One launch samples a wave: attempt ranges of up to 31 queries ("slots",
 // each with its own sources, seed, mode and output buffers) laid end to end.
 // One lane per attempt; persistent waves refill idle lanes from a global
 // counter in chunks and find the slot of each attempt in a small table kept
 // in LDS; kept walks are appended with one pair of atomics per slot per
-// wave.  Every iteration a lane computes one Philox block (its start draw,
+// wave.  A query with probabilistic suspects (a per-node coin threshold
+// array) starts uniformly over V and, at a tagged node, reads its threshold
+// in the next iteration: the node is a seed when the low half of its draw
+// word is below it (a seed start gives a walk without edges).  Every iteration a lane computes one Philox block (its start draw,
 // or the draw of the node it evaluates) and issues at most one 16-byte gather:
 // mostly the in-edge record the draw selects, which says whether the evaluated
 // node is a source and carries the next node's offset and degree -- so a step
@@ -54,8 +66,14 @@ enum Phase : uint32_t {
     PH_MU_A = 3,    // advance the first pointer
     PH_MU_B = 4,    // advance the second pointer, compare
     PH_EMIT = 5,    // kept walk: re-walk and write its ids
-    PH_SRC = 6      // start: the rank of the start among the sources, a 4-entry window at a time
+    PH_SRC = 6,     // start: the rank of the start among the sources, a 4-entry window at a time
+    PH_MU_RING = 7, // cycle found: bisect the ring for the entry mu
+    PH_EMIT_RING = 8  // kept walk: copy its ids from the ring
 };
+
+constexpr uint32_t kRingCells = kRingRows / 4;  // a lane's 16-byte cells: positions 4c .. 4c+3
+constexpr uint32_t kCellMask = kRingCells - 1;
+constexpr uint32_t kEmitPerIter = 4;  // ids a lane copies from the ring per iteration
 
 struct WaveArgs {
     const NodeRec *nodes;
@@ -65,6 +83,7 @@ struct WaveArgs {
     uint32_t chunk;                // attempts taken per refill
     const WaveTable *table;
     uint64_t guard_evals;          // no walk may need more evaluations than this
+    uint32_t *ring;                // kRingRows x 64 words per wave of the grid (NULL: no ring)
 };
 
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
@@ -183,7 +202,7 @@ __device__ __forceinline__ uint32_t settle_arc(const GLOBAL ArcRec *arcs, uint32
 }
 
 template <bool kCompact>
-__global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
+__global__ __launch_bounds__(256, 5) void k_sample(const WaveArgs A)
 {
     __shared__ SlotDev sl[kMaxSlots + 1];
     __shared__ uint64_t ip[kMaxItems + 1];
@@ -203,6 +222,38 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
     __syncthreads();
     const uint64_t total = ip[n_items];
     uint64_t *next = const_cast<uint64_t *>(&A.table->next[0]);
+    // this lane's column of its wave's ring: cells of 4 positions, the 64
+    // lanes' cells of one cell row side by side (1 KB).  Only the 32-byte
+    // record format keeps a ring: with 16-byte records an evaluation is one
+    // line, and the ring's stores cost more time than the evaluations they
+    // save (rmat24: 145 against 136 ms with 19% fewer evaluations; the
+    // billion-edge graph's 32-byte records: 927 against 1192 ms)
+    GLOBAL uint32_t *ring = (!kCompact && A.ring) ? gp(A.ring) + (static_cast<uint64_t>(blockIdx.x) * (blockDim.x / kWave) +
+                                                   threadIdx.x / kWave) * (kRingRows * kWave) + 4 * lane
+                                   : nullptr;
+    // word of virtual position v (= it0 + position) in the ring
+    auto ring_word = [&](uint32_t v) { return ring + static_cast<uint64_t>((v >> 2) & kCellMask) * (4 * kWave) + (v & 3u); };
+    // the cell being filled; written whole when its last position is, or
+    // when the walk needs the ring read back
+    uint32_t rb0 = 0, rb1 = 0, rb2 = 0, rb3 = 0;
+    auto ring_put = [&](uint32_t v, uint32_t val) {
+        const uint32_t c = v & 3u;
+        rb0 = c == 0 ? val : rb0;
+        rb1 = c == 1 ? val : rb1;
+        rb2 = c == 2 ? val : rb2;
+        rb3 = c == 3 ? val : rb3;
+        if (c == 3) {
+            const u32x4 cell = {rb0, rb1, rb2, rb3};
+            *reinterpret_cast<GLOBAL u32x4 *>(ring_word(v & ~3u)) = cell;
+        }
+    };
+    auto ring_flush = [&](uint32_t v_last) {  // the cell holding v_last, unless already written
+        if ((v_last & 3u) != 3u) {
+            const u32x4 cell = {rb0, rb1, rb2, rb3};
+            *reinterpret_cast<GLOBAL u32x4 *>(ring_word(v_last & ~3u)) = cell;
+        }
+    };
+    uint32_t iter = 0;  // wave-uniform iteration count
 
     // wave-uniform work state
     uint64_t chunk_next = 0, chunk_end = 0;
@@ -211,13 +262,16 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
     bool active = false, fetch = false;  // fetch: load cur's node record next iteration
     uint64_t a = 0, out_pos = 0, seed = 0;
     uint32_t slot = 0, mode = SIA_EDGES, tag_mask = 0;
+    bool psus = false;  // the lane's query has probabilistic suspects
+    bool ck = false;    // cur is a suspect: its coin threshold is read with this evaluation
     uint32_t phase = PH_START, x1 = 0, cur = 0, tort = 0, power = 1, lam = 0, t = 0, lambda = 0,
-             cnt = 0, pa = 0, pb = 0, evals = 0, ptort = 0, mbase = 0;
+             cnt = 0, pa = 0, pb = 0, evals = 0, ptort = 0, mbase = 0,
+             it0 = 0;  // iteration of the walk's first evaluation (its ring row)
     // (off, deg, thr_last, compact quantum) of the pointers' nodes: c for cur
     // (and pb in the cycle-entry search), p for pa
     uint32_t c_off = 0, c_deg = 0, c_thr = 0, c_q = 0, p_off = 0, p_deg = 0, p_thr = 0, p_q = 0;
 
-    for (;;) {
+    for (;; ++iter) {
         // ---- refill idle lanes with new attempts (converged section)
         uint64_t idle = __ballot(!active);
         while (idle != 0 && !exhausted) {
@@ -247,6 +301,8 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 seed = S.seed;
                 mode = S.mode;
                 tag_mask = S.tag_mask;
+                psus = S.coin_thr != nullptr;
+                ck = false;
                 phase = PH_START;
                 fetch = false;
                 evals = 0;
@@ -276,24 +332,33 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 do_eval = true;
                 if (phase == PH_DETECT) {
                     y = cur;
-                    if (t > 0) {
+                    if (t > 0 && !ck) {  // (a coin retry evaluates a position already checked)
                         ++lam;
                         if (cur == tort) {  // Brent: cycle of length lam (tort is never a source)
                             // The tortoise sits at positions 2^j - 1 with a window of
                             // 2^j.  If lam fits half the final window, the previous
                             // tortoise (position power/2 - 1) was off the cycle --
-                            // else its window would have found it -- so the search
-                            // for the cycle entry mu starts there, not at x1.
+                            // else its window would have found it -- so the cycle
+                            // entry mu is past it, not anywhere from x1 on.
                             const bool past = lam <= (power >> 1);
                             lambda = lam;
-                            cnt = lam;
-                            mbase = past ? (power >> 1) - 1u : 0u;
-                            pa = past ? ptort : x1;
-                            pb = pa;
-                            phase = PH_MU_POS;
-                            y = pa;
-                            fetch_now = true;  // both pointers start from this record
+                            const uint32_t lo = past ? (power >> 1) : 0u;  // mu in [lo, t - lam]
                             do_eval = false;
+                            if (ring && ((it0 + t - 1u) >> 2) - ((it0 + lo) >> 2) < kRingCells) {
+                                // the cells of positions lo .. t-1 are all in the ring
+                                ring_flush(it0 + t - 1u);
+                                mbase = lo;
+                                cnt = t - lam;  // the tortoise's position: on the cycle
+                                phase = PH_MU_RING;
+                            } else {
+                                cnt = lam;
+                                mbase = past ? (power >> 1) - 1u : 0u;
+                                pa = past ? ptort : x1;
+                                pb = pa;
+                                phase = PH_MU_POS;
+                                y = pa;
+                                fetch_now = true;  // both pointers start from this record
+                            }
                         } else if (lam == power) {
                             ptort = tort;
                             tort = cur;
@@ -305,6 +370,42 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                     y = pa;
                 } else if (phase == PH_EMIT) {
                     y = cur;
+                } else if (phase == PH_MU_RING) {
+                    // bisect [mbase, cnt] for mu, the first position i with
+                    // x_i == x_{i+lambda} (compared as the ring's entries:
+                    // equal chosen in-edges mean equal nodes)
+                    do_eval = false;
+                    if (mbase == cnt) {
+                        atomicAdd(&acc[slot][2], 1ull);
+                        atomicAdd(&acc[slot][3], static_cast<unsigned long long>(mbase) + lambda);
+                        atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
+                        active = false;
+                    } else {
+                        const uint32_t mid = (mbase + cnt) >> 1;  // mid + lambda <= t - 1
+                        const uint32_t va = *ring_word(it0 + mid);
+                        const uint32_t vb = *ring_word(it0 + mid + lambda);
+                        if (va == vb) cnt = mid;
+                        else mbase = mid + 1u;
+                    }
+                } else if (phase == PH_EMIT_RING) {
+                    // copy positions pa .. cnt-1 of the walk, a few per iteration
+                    do_eval = false;
+                    const SlotDev &S = sl[slot];
+                    uint32_t v[kEmitPerIter];
+#pragma unroll
+                    for (uint32_t e = 0; e < kEmitPerIter; ++e)
+                        v[e] = pa + e < cnt ? *ring_word(it0 + pa + e) : 0u;
+#pragma unroll
+                    for (uint32_t e = 0; e < kEmitPerIter; ++e)
+                        if (pa + e < cnt) gp(S.ids)[out_pos + e] = v[e];
+                    const uint32_t n_copied = min(kEmitPerIter, cnt - pa);
+                    out_pos += n_copied;
+                    pa += n_copied;
+                    if (pa == cnt) {
+                        if (mode == SIA_NODES) gp(S.ids)[out_pos++] = cur;  // the source reached
+                        atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
+                        active = false;
+                    }
                 } else {
                     y = pb;
                 }
@@ -334,6 +435,16 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 } else {
                     tag_only = phase == PH_DETECT && t > 0;
                 }
+                if (phase == PH_DETECT) {
+                    if (t == 0) it0 = iter;
+                    // the walk's position t goes to ring row it0 + t, stored beside
+                    // this iteration's gather so the two are in flight together
+                    // (an evaluation this iteration cancels -- a source reached,
+                    // a coin to read first -- leaves a row no position uses, or
+                    // one its retry rewrites with the same value)
+                    if (ring && live && (kCompact || mode == SIA_NODES))
+                        ring_put(it0 + t, mode == SIA_EDGES ? yoff + g : y);
+                }
             }
             // one 16-byte gather instruction per iteration: the node record (a
             // walk's first node, or the tag of a node without a live edge) or
@@ -347,7 +458,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                     src = reinterpret_cast<const GLOBAL u32x4 *>(gp(static_cast<const ArcRec16 *>(A.arcs)) + yoff + g);
                 else
                     src = reinterpret_cast<const GLOBAL u32x4 *>(gp(static_cast<const ArcRec *>(A.arcs)) + yoff + g);
-            } else if (starting) {
+            } else if (starting && !psus) {
                 src = reinterpret_cast<const GLOBAL u32x4 *>(gp(sl[slot].bucket) +
                                                               ((2u * (x1 >> sl[slot].bucket_shift)) & ~3u));
             } else if (in_src) {
@@ -363,6 +474,7 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 if constexpr (kCompact) v = __builtin_nontemporal_load(src);
                 else v = *src;
             }
+            const uint32_t cthr = (do_eval && ck) ? gp(sl[slot].coin_thr)[cur] : 0u;
             if (fetch_now || tag_only) {
                 R = NodeRec{v.x, v.y, v.z, v.w};
             } else if (live) {
@@ -374,9 +486,10 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                 }
             } else if (starting || in_src) {
                 const SlotDev &D = sl[slot];
-                uint32_t c;
+                uint32_t c = 0;
                 bool more = false;  // the next window of t is needed
-                if (starting) {  // the bucket's pair: the count below it, the next t
+                if (psus) {  // uniform over V: the start is idx itself
+                } else if (starting) {  // the bucket's pair: the count below it, the next t
                     const uint32_t k = (2u * (x1 >> D.bucket_shift)) & 3u;
                     c = pick4(v, k);
                     more = c < D.n_src && pick4(v, k + 1u) <= x1;
@@ -400,17 +513,28 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                     fetch = true;
                 }
             }
-            if (do_eval && phase == PH_DETECT && t > 0) {
-                const uint32_t tag = live ? (kCompact ? E16.head_tag : E.head_tag) : R.tag;
-                if (tag & tag_mask) {  // reached a source: kept walk
-                    hit_now = true;
-                    do_eval = false;
-                } else if (t > A.guard_evals) {  // unreachable for a correct walk
-                    atomicAdd(&acc[slot][5], 1ull);
-                    active = false;
-                    do_eval = false;
+            if (do_eval && phase == PH_DETECT) {
+                if (ck) {  // a suspect: a seed when its coin is below the threshold
+                    ck = false;
+                    if (static_cast<uint32_t>(word) < cthr) {
+                        hit_now = true;
+                        do_eval = false;
+                    }
+                } else if (t > 0) {
+                    const uint32_t tag = live ? (kCompact ? E16.head_tag : E.head_tag) : R.tag;
+                    if (tag & tag_mask) {
+                        do_eval = false;
+                        if (psus) ck = true;  // its coin decides, with its threshold, next iteration
+                        else hit_now = true;  // reached a source: kept walk
+                    } else if (t > A.guard_evals) {  // unreachable for a correct walk
+                        atomicAdd(&acc[slot][5], 1ull);
+                        active = false;
+                        do_eval = false;
+                    }
                 }
             }
+            if (fetch_now && psus && phase == PH_DETECT && t == 0 && (R.tag & tag_mask))
+                ck = true;  // the start is a suspect: its coin comes first
             if (fetch_now) {
                 c_off = R.off;
                 c_deg = R.deg;
@@ -458,10 +582,23 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
                     gp(S.walk_len)[widx] = len;
                     out_pos = ioff;
                     if (mode == SIA_NODES) gp(S.ids)[out_pos++] = x1;
-                    phase = PH_EMIT;
-                    cur = x1;
-                    fetch = true;
-                    cnt = t;
+                    if (t == 0) {  // a seed start: the walk <x1>, nothing more to write
+                        atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
+                        active = false;
+                    } else if (ring && ((it0 + t - 1u) >> 2) - (it0 >> 2) < kRingCells) {
+                        // positions 0 .. t-1 sit in the ring: edges copy all
+                        // of them, nodes positions 1 .. t-1 and then the
+                        // source reached (cur)
+                        ring_flush(it0 + t - 1u);
+                        phase = PH_EMIT_RING;
+                        pa = mode == SIA_NODES ? 1u : 0u;
+                        cnt = t;
+                    } else {
+                        phase = PH_EMIT;
+                        cur = x1;
+                        fetch = true;
+                        cnt = t;
+                    }
                 } else {
                     gp(S.counters)[ST_OVERFLOW] = 1;
                     atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
@@ -504,6 +641,9 @@ __global__ __launch_bounds__(256) void k_sample(const WaveArgs A)
             ++evals;
             bool done = false;
             if (phase == PH_DETECT) {
+                if constexpr (!kCompact)  // (the searched in-edge is known only now)
+                    if (ring && live && mode == SIA_EDGES)
+                        ring_put(it0 + t, j);
                 ++t;
                 if (!live) {
                     atomicAdd(&acc[slot][1], 1ull);
@@ -592,6 +732,15 @@ __global__ __launch_bounds__(256) void k_tag_sources(const int32_t *src, uint32_
     }
 }
 
+// coin_thr[ids[i]] = q[i]: the seed thresholds of a query's suspects (the
+// other entries are never read: only tagged nodes look theirs up)
+__global__ __launch_bounds__(256) void k_scatter_coin(const int32_t *ids, const uint32_t *q, uint32_t count,
+                                                      uint32_t *coin_thr)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) gp(coin_thr)[gp(ids)[i]] = gp(q)[i];
+}
+
 int max_blocks_per_cu(bool compact)
 {
     static int per_cu[2] = {0, 0};
@@ -648,8 +797,15 @@ void tag_sources(const sia_graph *g, const int32_t *d_src, uint32_t n_src, uint3
     SIA_HIP(hipGetLastError());
 }
 
+size_t sampler_ring_bytes(const sia_graph *g)
+{
+    if (compact_arcs(g)) return 0;  // (no ring with 16-byte records)
+    const uint64_t waves = static_cast<uint64_t>(max_blocks_per_cu(compact_arcs(g))) * device_cu_count() * (256 / kWave);
+    return static_cast<size_t>(waves * kRingRows * kWave * sizeof(uint32_t));
+}
+
 void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
-                 const WaveTable *d_table, const SamplerConfig &cfg, hipStream_t s)
+                 const WaveTable *d_table, const SamplerConfig &cfg, uint32_t *ring, hipStream_t s)
 {
     SIA_REQUIRE(n_slots >= 1 && n_slots <= kMaxSlots + 1, SIA_EINVAL, "bad wave shape");
     SIA_REQUIRE(cfg.chunk >= 1 && cfg.chunk <= (1u << 20), SIA_EINVAL, "bad refill chunk");
@@ -664,6 +820,7 @@ void launch_wave(const sia_graph *g, const SlotDev *d_slots, uint32_t n_slots,
     A.chunk = cfg.chunk;
     A.table = d_table;
     A.guard_evals = 3 * static_cast<uint64_t>(g->n) + 8;
+    A.ring = ring;  // sized by sampler_ring_bytes for the largest grid
     const int cus = cfg.cus > 0 ? std::min(cfg.cus, device_cu_count()) : device_cu_count();
     if (compact) hipLaunchKernelGGL(k_sample<true>, dim3(per_cu * cus), dim3(256), 0, s, A);
     else hipLaunchKernelGGL(k_sample<false>, dim3(per_cu * cus), dim3(256), 0, s, A);
@@ -709,12 +866,21 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
     ws.src_t.ensure(sizeof(uint32_t) * st.t.size());
     ws.bucket.ensure(sizeof(uint32_t) * st.bucket.size());
     ws.counters.ensure(sizeof(uint64_t) * ST_COUNT + sizeof(SlotDev) + sizeof(WaveTable) + 256);
+    ws.ring.ensure(sampler_ring_bytes(g));
     SIA_HIP(hipMemcpyAsync(ws.src_sorted.ptr, st.sorted.data(), sizeof(int32_t) * n_src,
                            hipMemcpyHostToDevice, s));
     SIA_HIP(hipMemcpyAsync(ws.src_t.ptr, st.t.data(), sizeof(uint32_t) * st.t.size(),
                            hipMemcpyHostToDevice, s));
     SIA_HIP(hipMemcpyAsync(ws.bucket.ptr, st.bucket.data(), sizeof(uint32_t) * st.bucket.size(),
                            hipMemcpyHostToDevice, s));
+    if (st.probabilistic) {
+        ws.coin_thr.ensure(sizeof(uint32_t) * static_cast<uint64_t>(g->n));
+        ws.coin_src.ensure(sizeof(uint32_t) * n_src);
+        SIA_HIP(hipMemcpyAsync(ws.coin_src.ptr, st.coin.data(), sizeof(uint32_t) * n_src, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_scatter_coin, dim3((n_src + 255) / 256), dim3(256), 0, s, ws.src_sorted.as<int32_t>(),
+                           ws.coin_src.as<uint32_t>(), n_src, ws.coin_thr.as<uint32_t>());
+        SIA_HIP(hipGetLastError());
+    }
     const SourceTagScope tags(g, ws.src_sorted.as<int32_t>(), n_src, mask, s);
     char *cbase = ws.counters.as<char>();
     uint64_t *d_counters = reinterpret_cast<uint64_t *>(cbase);
@@ -759,6 +925,7 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
         S.walk_cap = ws.walk_cap;
         S.id_cap = ws.id_cap;
         S.counters = d_counters;
+        S.coin_thr = st.probabilistic ? ws.coin_thr.as<uint32_t>() : nullptr;
         SIA_HIP(hipMemcpyAsync(d_slot, &S, sizeof(S), hipMemcpyHostToDevice, s));
         const WaveItem item{0u, 0u, launch_attempts};
         WaveTable table;
@@ -771,7 +938,7 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
             SIA_HIP(hipEventCreate(&e1));
             SIA_HIP(hipEventRecord(e0, s));
         }
-        launch_wave(g, d_slot, 1, d_table, SamplerConfig{}, s);
+        launch_wave(g, d_slot, 1, d_table, SamplerConfig{}, ws.ring.as<uint32_t>(), s);
         if (timing) SIA_HIP(hipEventRecord(e1, s));
 
         uint64_t h[ST_COUNT];

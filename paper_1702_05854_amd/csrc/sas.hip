@@ -248,25 +248,20 @@ using namespace sia;
 
 extern "C" {
 
-sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
-                         int64_t k, double eps, double delta, uint64_t seed, uint64_t max_attempts,
-                         int64_t *selected, uint64_t *gains, sia_sas_info *info, void *hip_stream)
+// The driver for the query whose sources (or suspects with probabilities) st
+// holds; arguments checked by the callers.
+static void sas_impl(sia_graph *g, int mode, const SourceTables &st, int64_t k, double eps, double delta,
+                     uint64_t seed, uint64_t max_attempts, int64_t *selected, uint64_t *gains, sia_sas_info *info,
+                     void *hip_stream)
 {
-    return guarded([&] {
+    {
         const auto t0 = std::chrono::steady_clock::now();
-        SIA_REQUIRE(cg != nullptr && selected != nullptr && gains != nullptr && info != nullptr, SIA_EINVAL,
-                    "NULL argument");
-        SIA_REQUIRE(eps > 0.0 && eps < 1.0 - 1.0 / M_E, SIA_EINVAL, "eps must be in (0, 1 - 1/e)");
-        SIA_REQUIRE(delta > 0.0 && delta < 1.0, SIA_EINVAL, "delta must be in (0, 1)");
-        sia_graph *g = const_cast<sia_graph *>(cg);
-        check_query(g->n, g->m, mode, sources, n_sources, k, max_attempts, 0);
-        SIA_REQUIRE(k >= 1, SIA_EINVAL, "k must be >= 1");
+        const int64_t n_sources = st.probabilistic ? 0 : static_cast<int64_t>(st.sorted.size());
         std::lock_guard<std::mutex> lock(g->mu);
         DeviceScope ds(g->device);
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
         const int64_t S = mode == SIA_EDGES ? g->m : g->n;
         const SasParams P = sas_params(static_cast<double>(S), static_cast<double>(k), eps, delta);
-        const SourceTables st = build_source_tables(g->n, sources, n_sources);
 
         sia_sas_info I{};
         I.lambda = P.lambda;
@@ -425,7 +420,7 @@ sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, 
                 I.spread_est = static_cast<double>(n_sources) + n_ns * static_cast<double>(n_t) / a_r;
                 I.suspension_est = n_ns * static_cast<double>(cov_r) / a_r;
                 uint64_t in_x = 0;
-                if (mode == SIA_NODES)
+                if (mode == SIA_NODES && !st.probabilistic)  // (suspects: a seed's own walk is sampled)
                     for (int64_t v : sel)
                         in_x += std::binary_search(st.sorted.begin(), st.sorted.end(), static_cast<int32_t>(v));
                 I.suspension_nodes_est = I.suspension_est + static_cast<double>(in_x);
@@ -437,6 +432,44 @@ sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, 
         I.ms_total = static_cast<float>(
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
         *info = I;
+    }
+}
+
+static void sas_check_args(const sia_graph *cg, int64_t *selected, uint64_t *gains, sia_sas_info *info,
+                           double eps, double delta)
+{
+    SIA_REQUIRE(cg != nullptr && selected != nullptr && gains != nullptr && info != nullptr, SIA_EINVAL,
+                "NULL argument");
+    SIA_REQUIRE(eps > 0.0 && eps < 1.0 - 1.0 / M_E, SIA_EINVAL, "eps must be in (0, 1 - 1/e)");
+    SIA_REQUIRE(delta > 0.0 && delta < 1.0, SIA_EINVAL, "delta must be in (0, 1)");
+}
+
+sia_status sia_sas_solve(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
+                         int64_t k, double eps, double delta, uint64_t seed, uint64_t max_attempts,
+                         int64_t *selected, uint64_t *gains, sia_sas_info *info, void *hip_stream)
+{
+    return guarded([&] {
+        sas_check_args(cg, selected, gains, info, eps, delta);
+        sia_graph *g = const_cast<sia_graph *>(cg);
+        check_query(g->n, g->m, mode, sources, n_sources, k, max_attempts, 0);
+        SIA_REQUIRE(k >= 1, SIA_EINVAL, "k must be >= 1");
+        sas_impl(g, mode, build_source_tables(g->n, sources, n_sources), k, eps, delta, seed, max_attempts,
+                 selected, gains, info, hip_stream);
+    });
+}
+
+sia_status sia_sas_solve_suspects(const sia_graph *cg, int mode, const int32_t *suspects, const float *p,
+                                  int64_t n_suspects, int64_t k, double eps, double delta, uint64_t seed,
+                                  uint64_t max_attempts, int64_t *selected, uint64_t *gains, sia_sas_info *info,
+                                  void *hip_stream)
+{
+    return guarded([&] {
+        sas_check_args(cg, selected, gains, info, eps, delta);
+        sia_graph *g = const_cast<sia_graph *>(cg);
+        const SourceTables st = build_suspect_tables(g->n, suspects, p, n_suspects);
+        check_query(g->n, g->m, mode, st.sorted.data(), 1, k, max_attempts, 0);  // mode, k, attempts
+        SIA_REQUIRE(k >= 1, SIA_EINVAL, "k must be >= 1");
+        sas_impl(g, mode, st, k, eps, delta, seed, max_attempts, selected, gains, info, hip_stream);
     });
 }
 

@@ -118,6 +118,7 @@ struct sia_batch {
     SlotDev *h_slots = nullptr;
     uint64_t *h_ctr_in = nullptr, *h_ctr_out = nullptr;
     DevBuf d_table, d_slots, d_ctr, d_jobs;
+    DevBuf d_ring;  // the sampler's walk ring (one launch at a time)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     SamplerConfig exec_cfg{};
@@ -334,7 +335,8 @@ struct sia_batch {
         SIA_HIP(hipMemcpyAsync(d_table.ptr, h_table, sizeof(WaveTable), hipMemcpyHostToDevice, s_sample));
         SIA_HIP(hipMemcpyAsync(d_slots.ptr, h_slots, sizeof(SlotDev) * n_slots, hipMemcpyHostToDevice, s_sample));
         SIA_HIP(hipMemcpyAsync(d_ctr.ptr, h_ctr_in, cb, hipMemcpyHostToDevice, s_sample));
-        launch_wave(g, d_slots.as<SlotDev>(), n_slots, d_table.as<WaveTable>(), sc, s_sample);
+        launch_wave(g, d_slots.as<SlotDev>(), n_slots, d_table.as<WaveTable>(), sc, d_ring.as<uint32_t>(),
+                    s_sample);
         SIA_HIP(hipMemcpyAsync(h_ctr_out, d_ctr.ptr, cb, hipMemcpyDeviceToHost, s_sample));
     }
 
@@ -1073,6 +1075,7 @@ sia_status sia_batch_create(const sia_graph *cg, uint64_t walk_budget_bytes, int
         raw->d_slots.ensure(sizeof(SlotDev) * raw->n_slots);
         raw->d_ctr.ensure(cb);
         raw->d_jobs.ensure(greedy_job_table_bytes(raw->n_slots));
+        raw->d_ring.ensure(sampler_ring_bytes(g));
         (void)sampler_max_blocks_per_cu(g);  // occupancy query before any capture
         raw->ctr.walk_budget = walk_budget_bytes;
         raw->ctr.slots = raw->n_slots;

@@ -142,6 +142,13 @@ def lib():
         L.sia_evaluate.argtypes = [p, i32, p, i64, p, i64, u64, u64, u64, C.POINTER(Stats), p]
         L.sia_sas_solve.argtypes = [p, i32, p, i64, i64, C.c_double, C.c_double, u64, u64, p, p,
                                     C.POINTER(SasInfo), p]
+        L.sia_sas_solve_suspects.argtypes = [p, i32, p, p, i64, i64, C.c_double, C.c_double, u64, u64, p, p,
+                                             C.POINTER(SasInfo), p]
+        L.sia_sas_solve_suspects.restype = C.c_int
+        L.sia_sample_suspects.argtypes = [p, i32, p, p, i64, u64, u64, u64, C.POINTER(_Walks), p]
+        L.sia_sample_suspects.restype = C.c_int
+        L.sia_solve_suspects.argtypes = [p, i32, p, p, i64, i64, u64, u64, u64, p, p, C.POINTER(Stats), i32, p]
+        L.sia_solve_suspects.restype = C.c_int
         L.sia_greedy_noalloc.argtypes = [i64, p, p, u64, i64, p, p, p]
         L.sia_greedy_noalloc.restype = C.c_int
         L.sia_test_fail_alloc.argtypes = [C.c_uint32]
@@ -264,12 +271,8 @@ class Walks:
         return self.ids[int(self.off[i]):int(self.off[i + 1])]
 
 
-def sample(graph: Graph, sources, mode, n_attempts, attempt_offset=0, seed=2017, stream=None):
-    src = _host(sources, np.int32)
-    w = _Walks()
+def _walks_of(w):
     L = lib()
-    _check(L.sia_sample(graph.handle, MODES[mode], _hptr(src), src.shape[0], n_attempts,
-                        attempt_offset, seed, C.byref(w), _stream(stream)))
     try:
         nw, ni = int(w.n_walks), int(w.n_ids)
         attempt = np.ctypeslib.as_array(w.attempt, (nw,)).copy() if nw else np.zeros(0, np.uint64)
@@ -278,6 +281,40 @@ def sample(graph: Graph, sources, mode, n_attempts, attempt_offset=0, seed=2017,
         return Walks(attempt, off, ids, w.stats.as_dict())
     finally:
         L.sia_walks_free(C.byref(w))
+
+
+def sample(graph: Graph, sources, mode, n_attempts, attempt_offset=0, seed=2017, stream=None):
+    src = _host(sources, np.int32)
+    w = _Walks()
+    _check(lib().sia_sample(graph.handle, MODES[mode], _hptr(src), src.shape[0], n_attempts,
+                            attempt_offset, seed, C.byref(w), _stream(stream)))
+    return _walks_of(w)
+
+
+def sample_suspects(graph: Graph, suspects, p, mode, n_attempts, attempt_offset=0, seed=2017, stream=None):
+    """Kept walks with probabilistic suspects (sia_sample_suspects)."""
+    sus = _host(suspects, np.int32)
+    pr = _host(p, np.float32)
+    assert sus.shape == pr.shape
+    w = _Walks()
+    _check(lib().sia_sample_suspects(graph.handle, MODES[mode], _hptr(sus), _hptr(pr), sus.shape[0], n_attempts,
+                                     attempt_offset, seed, C.byref(w), _stream(stream)))
+    return _walks_of(w)
+
+
+def solve_suspects(graph: Graph, suspects, p, mode, k, n_attempts, attempt_offset=0, seed=2017, timing=False,
+                   stream=None):
+    """The whole path with probabilistic suspects (sia_solve_suspects)."""
+    sus = _host(suspects, np.int32)
+    pr = _host(p, np.float32)
+    assert sus.shape == pr.shape
+    sel = np.zeros(k, dtype=np.int64)
+    gains = np.zeros(k, dtype=np.uint64)
+    st = Stats()
+    _check(lib().sia_solve_suspects(graph.handle, MODES[mode], _hptr(sus), _hptr(pr), sus.shape[0], k, n_attempts,
+                                    attempt_offset, seed, _hptr(sel), _hptr(gains), C.byref(st),
+                                    1 if timing else 0, _stream(stream)))
+    return dict(selected=sel, gains=gains, stats=st.as_dict())
 
 
 def greedy(id_space, walk_off, ids, k, stream=None):
@@ -358,6 +395,23 @@ def inject_alloc_failure(nth):
     """Fault injection (sia_test_fail_alloc): the nth device allocation from
     now fails with SIA_ENOMEM; 0 disables."""
     lib().sia_test_fail_alloc(int(nth))
+
+
+def sas_solve_suspects(graph: Graph, suspects, p, mode, k, eps=0.1, delta=None, seed=2017,
+                       max_attempts=(1 << 32) - 1, stream=None):
+    """Stop-and-Stare with probabilistic suspects (sia_sas_solve_suspects);
+    delta defaults to 1/n."""
+    sus = _host(suspects, np.int32)
+    pr = _host(p, np.float32)
+    if delta is None:
+        delta = 1.0 / graph.n
+    sel = np.zeros(k, dtype=np.int64)
+    gains = np.zeros(k, dtype=np.uint64)
+    info = SasInfo()
+    _check(lib().sia_sas_solve_suspects(graph.handle, MODES[mode], _hptr(sus), _hptr(pr), sus.shape[0], k,
+                                        float(eps), float(delta), seed, max_attempts, _hptr(sel), _hptr(gains),
+                                        C.byref(info), _stream(stream)))
+    return dict(selected=sel, gains=gains, info=info.as_dict())
 
 
 def sas_params(id_space, k, eps, delta):

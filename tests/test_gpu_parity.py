@@ -211,6 +211,49 @@ def test_sample_matches_oracle_tiny(sia, case, mode):
 
 
 @pytest.mark.parametrize("mode", ["edges", "nodes"])
+@pytest.mark.parametrize("weights", ["inv", "rand"])
+def test_long_walks_match_oracle(sia, mode, weights):
+    """Walks far longer than the sampler's walk ring (1024 positions) take
+    the ring-free paths (two-pointer cycle entry, re-walk emission), shorter
+    ones the ring: a chain of 3000 nodes into a source, a 2500-node cycle fed
+    by a 1500-node tail, and shortcuts that make lengths of every size."""
+    rng = np.random.default_rng(77 if weights == "inv" else 78)
+    L, C, T = 3000, 2500, 1500
+    n = L + 1 + C + T
+    edges = []
+    # chain: node i's live in-edge comes from i + 1; node L is the source
+    for i in range(L):
+        edges.append((i + 1, i, 1.0))
+    base = L + 1  # cycle base .. base + C - 1, tail base + C .. n - 1 feeding the cycle
+    for i in range(C):
+        edges.append((base + (i + 1) % C, base + i, 1.0))
+    for i in range(T - 1):
+        edges.append((base + C + i + 1, base + C + i, 1.0))
+    edges.append((base, base + C + T - 1, 1.0))  # the tail's last node is fed by the cycle
+    if weights == "rand":
+        # a few extra in-edges with split weights: walks branch between the parts
+        extra = rng.choice(n, 200, replace=False)
+        rebuilt = []
+        touched = set(int(v) for v in extra)
+        for (u, v, w) in edges:
+            rebuilt.append((u, v, 0.7 if v in touched else w))
+        for v in extra:
+            u = int(rng.integers(0, n))
+            if u != v:
+                rebuilt.append((u, int(v), 0.25))
+        edges = rebuilt
+    col, row, w = csc_from_edges(n, edges)
+    g = sia.Graph(col, row, w)
+    og = cpu.Graph(col, row, w)
+    src = [L]
+    got = sia.sample(g, src, mode, 20_000, 0, SEED)
+    ref = og.sample(np.array(src, np.int32), omode(mode), 20_000, 0, SEED)
+    assert_walks_equal(got, ref, (mode, weights))
+    assert ref.cycles > 0 and ref.hits > 0 and int(np.diff(ref.off.astype(np.int64)).max()) > 1024
+    g.close()
+
+
+@pytest.mark.parametrize("mode", ["edges", "nodes"])
 def test_sample_matches_oracle_random_graphs(sia, mode):
     for seed in range(20):
         n = 30 + seed * 7

@@ -127,3 +127,23 @@ def test_sas_driver_parameters_match_hand_derivation(sia, er1k, mode, eps, name)
     assert I["lambda_"] == pytest.approx(float(P["lam"]), rel=1e-13)
     assert I["lambda1"] == pytest.approx(float(P["lam1"]), rel=1e-13)
     assert I["n_t"] == math.ceil(float(P["lam"]) * 2 ** (I["t"] - 1))
+
+
+@pytest.mark.parametrize("mode", ["edges", "nodes"])
+def test_sas_suspects_matches_oracle(sia, er20k, mode):
+    """Stop-and-Stare over the probabilistic-suspect sampler (500 suspects
+    with random probabilities on the 20000-node graph): the same iteration,
+    sample sizes, bounds, picks, gains and coverages as the oracle's driver."""
+    wl, g, og = er20k
+    rng = np.random.default_rng(21)
+    sus = np.sort(rng.choice(wl.n, 500, replace=False)).astype(np.int32)
+    p = rng.uniform(0, 1, 500).astype(np.float32)
+    om = cpu.MODE_EDGES if mode == "edges" else cpu.MODE_NODES
+    say("er20k suspects", mode)
+    got = sia.sas_solve_suspects(g, sus, p, mode, wl.k, 0.1, None, wl.seed)
+    ref = sas.stop_and_stare(og, sus, om, wl.k, 0.1, None, wl.seed, p=p)
+    compare(got, ref)
+    I = got["info"]
+    assert I["suspension_est"] == pytest.approx(wl.n * ref["cov_r"] / ref["attempts_r"], rel=1e-12)
+    assert I["spread_est"] == pytest.approx(wl.n * ref["n_t"] / ref["attempts_r"], rel=1e-12)
+    assert I["suspension_nodes_est"] == I["suspension_est"]

@@ -113,3 +113,19 @@ def test_evaluation_on_the_greedy_sample_is_its_coverage(er1k, mode):
     p = other["covered"] / 200_000
     sd = math.sqrt(p * (1 - p) / 200_000) + math.sqrt(p * (1 - p) / 50_000)
     assert abs(same["covered"] / 50_000 - p) < 6 * sd + 1e-9
+
+
+def test_driver_with_suspects_follows_the_stream(er1k):
+    """With probabilistic suspects the stream is the probabilistic sampler's
+    kept walks in attempt order: R_t of the returned iteration is the first
+    N_t of one sampling run."""
+    wl, g = er1k
+    rng = np.random.default_rng(4)
+    sus = np.sort(rng.choice(g.n, 60, replace=False)).astype(np.int32)
+    p = rng.uniform(0, 1, 60).astype(np.float32)
+    r = sas.stop_and_stare(g, sus, cpu.MODE_NODES, wl.k, 0.1, None, wl.seed, chunk=1 << 12, p=p)
+    whole = g.sample_suspects(sus, p, cpu.MODE_NODES, r["attempts_rp"], 0, wl.seed)
+    assert whole.n_walks == 2 * r["n_t"]
+    o = whole.off[: r["n_t"] + 1].astype(np.int64)
+    sel, gains = cpu.greedy_csr(g.n, o.astype(np.uint64), whole.ids[:o[-1]], wl.k)
+    assert np.array_equal(sel, r["selected"]) and np.array_equal(gains, r["gains"])

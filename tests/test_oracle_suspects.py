@@ -1,6 +1,6 @@
 """Pins of the oracle with probabilistic suspects (Section 2.2: V_I = (V_I, p),
 seed sets drawn with the probability of equation "prob_src_set"; Algorithm 1's
-test "u in V_I and rand() <= p(u)").
+suspect test, which makes a suspect the walk meets a seed with probability p(u)).
 
 * The exact routes agree in rationals: HSAW path sums with the factor
   p(v_l) prod (1 - p(u)) of equation "compute_path_inf" against every
