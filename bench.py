@@ -180,8 +180,10 @@ def serve_measure(args, name, n_queries, loads, skip_plain=False):
     print(f"[serve] n={wl.n} m={wl.m}: {len(qs)} queries, {total_att} attempts", file=sys.stderr,
           flush=True)
 
+    cs = bool(getattr(args, "cycle_steps", False))  # cyclic walks stop at detection unless asked
+
     def submit_all(b, qlist):
-        return [b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"]) for q in qlist]
+        return [b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"], cs) for q in qlist]
 
     with sia.Batch(g, walk_budget_bytes=args.walk_budget << 20, use_graph=1,
                    greedy_mode=args.greedy_mode, greedy_cus=args.greedy_cus,
@@ -212,7 +214,7 @@ def serve_measure(args, name, n_queries, loads, skip_plain=False):
         for i, q in enumerate(qs if not skip_plain else []):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            r = sia.solve(g, q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"])
+            r = sia.solve(g, q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"], cycle_steps=cs)
             service.append(time.perf_counter() - t1)
             assert (r["selected"] == batched[i]["selected"]).all(), f"query {i}: batched != plain"
             assert (r["gains"] == batched[i]["gains"]).all(), f"query {i}: batched != plain"
@@ -233,7 +235,7 @@ def serve_measure(args, name, n_queries, loads, skip_plain=False):
                 delay = arrivals[i] - (time.perf_counter() - base)
                 if delay > 0:
                     time.sleep(delay)
-                ts.append(b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"]))
+                ts.append(b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"], cs))
             for t in ts:
                 r = b.wait(t)
                 lat.append(r["info"]["t_done"] - r["info"]["t_submit"])
@@ -254,7 +256,7 @@ def serve_measure(args, name, n_queries, loads, skip_plain=False):
         "plain_queries_per_s": rate_p, "speedup_vs_plain": rate_b / rate_p if rate_p else None,
         "plain_answers_checked": len(service),
         "closed_loop_p50_s": percentile(closed_lat, 50), "closed_loop_p99_s": percentile(closed_lat, 99),
-        "attempts_per_s_batched": total_att / makespan,
+        "attempts_per_s_batched": total_att / makespan, "cycle_steps": cs,
         "open_loop": open_loop, "batch_stats": bstats,
     }
 
@@ -412,6 +414,8 @@ def main():
     ap.add_argument("--mode", default=None)
     ap.add_argument("--attempts", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cycle-steps", action="store_true",
+                    help="timed runs also search cyclic walks for their entry (exact step counts)")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the batched-vs-plain block (mixed queries on R-MAT s22) of the default run")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
@@ -486,21 +490,34 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    for i in range(args.warmup):
-        sia.solve(g, wl.sources, mode, k, n_att, 0, wl.seed, timing=True)
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    # The first warm-up run (untimed) counts every walk's steps exactly,
+    # cyclic walks included: its counters give the algorithmic bytes.  The
+    # timed runs stop cyclic walks at detection unless --cycle-steps asks
+    # otherwise (the walk is discarded either way; picks and gains are
+    # checked equal to the exact run's).
+    exact = None
+    for i in range(max(args.warmup, 1)):
+        r = sia.solve(g, wl.sources, mode, k, n_att, 0, wl.seed, timing=True,
+                      cycle_steps=args.cycle_steps or i == 0)
+        exact = exact or r
+        print(f"[bench] warmup {i + 1}/{max(args.warmup, 1)} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
     for i in range(args.steps):
-        runs.append(sia.solve(g, wl.sources, mode, k, n_att, 0, wl.seed, timing=True))
+        runs.append(sia.solve(g, wl.sources, mode, k, n_att, 0, wl.seed, timing=True,
+                              cycle_steps=args.cycle_steps))
         print(f"[bench] step {i + 1}/{args.steps}: {runs[-1]['stats']['ms_total']:.1f} ms",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    st = runs[-1]["stats"]
-    for r in runs[1:]:
-        assert (r["selected"] == runs[0]["selected"]).all(), "non-deterministic selection"
+    st = dict(exact["stats"])  # exact counters (same walks, same picks)
+    st_timed = runs[-1]["stats"]
+    for r in runs:
+        assert (r["selected"] == exact["selected"]).all() and (r["gains"] == exact["gains"]).all(), \
+            "timed runs must select what the exact run selects"
+        for key in ("hits", "dead_ends", "cycles", "walk_ids", "covered"):
+            assert r["stats"][key] == st[key], key
     ms_sample = sum(r["stats"]["ms_sample"] for r in runs) / len(runs)
     ms_count = sum(r["stats"]["ms_count"] for r in runs) / len(runs)
     ms_greedy = sum(r["stats"]["ms_greedy"] for r in runs) / len(runs)
@@ -527,20 +544,25 @@ def main():
                    "k": k, "mode": mode, "weights": wl.desc.get("weights"), "seed": wl.seed},
         "hsaw_per_s": st["hits"] * args.steps / elapsed,
         "steps_per_s": st["steps"] * args.steps / elapsed,
-        "evaluations_per_s": st["evaluations"] * args.steps / elapsed,
+        "evaluations_per_s": st_timed["evaluations"] * args.steps / elapsed,
+        "cycle_steps_in_timed_runs": bool(args.cycle_steps),
+        "ms_sample_exact_cycle_steps": exact["stats"]["ms_sample"],
+        "evaluations_exact_cycle_steps": exact["stats"]["evaluations"],
         "sampler_attempts_per_s": n_att / (ms_sample * 1e-3),
         "ms_sample": ms_sample, "ms_count": ms_count, "ms_greedy": ms_greedy,
         "ingest_ms": ingest_ms,
         "arc_record_bytes": g.arc_bytes,
-        "counts": {key: st[key] for key in ("hits", "dead_ends", "cycles", "steps", "evaluations",
-                                            "walk_ids", "covered")},
+        "counts": {**{key: st[key] for key in ("hits", "dead_ends", "cycles", "steps", "walk_ids", "covered")},
+                   "evaluations": st_timed["evaluations"]},
         "suspension_est": st["suspension_est"],
         "roofline": {"bound": "hbm", "kernel": "k_sample", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": b_alg, "traffic": load_traffic(),
                      "frac_other_readings": {
-                         f"{sb} B/step flat": per_step_bytes(st, n_att, sb) / (ms_sample * 1e-3) / 1e9
-                         / HBM_PEAK_GBS for sb in (29, 21)}},
+                         **{f"{sb} B/step flat": per_step_bytes(st, n_att, sb) / (ms_sample * 1e-3) / 1e9
+                            / HBM_PEAK_GBS for sb in (29, 21)},
+                         "cycle entries searched (untimed exact run)":
+                             b_alg / (exact["stats"]["ms_sample"] * 1e-3) / 1e9 / HBM_PEAK_GBS}},
         "cpu_baseline": None,
     }
     g.close()

@@ -49,6 +49,23 @@ typedef enum {
     SIA_EBUSY = -7       /* batch: resource held (tag bits, or tuning while busy) */
 } sia_status;
 
+/*
+ * Flags of the solve calls (argument `flags` of sia_solve,
+ * sia_solve_candidates and sia_solve_suspects; sia_query.flags of a batch).
+ *  SIA_FLAG_TIMING           record HIP events around the phases into stats
+ *                            (solve calls; 1 keeps its old meaning of
+ *                            "timing requested")
+ *  SIA_FLAG_NO_CYCLE_STEPS   stop a walk that closes a cycle as soon as the
+ *                            cycle is detected.  Algorithm 1 discards such a
+ *                            walk, and which attempts end in a cycle does not
+ *                            change; only its exact length is not found (the
+ *                            search for where it entered the cycle is skipped).
+ *                            stats.steps then leaves out the draws of those
+ *                            walks; every other output is identical.
+ */
+#define SIA_FLAG_TIMING 1
+#define SIA_FLAG_NO_CYCLE_STEPS 2
+
 typedef enum {
     SIA_EDGES = 0, /* eSIA: ids are CSC edge positions (Definition "edge_remove") */
     SIA_NODES = 1  /* nSIA: ids are node ids (Definition "node_remove") */
@@ -64,7 +81,8 @@ typedef struct {
     uint64_t cycles;       /* attempts whose walk returned to a visited node */
     uint64_t steps;        /* live-edge draws of the plain walk (Algorithm 1):
                               a hit or dead end after t draws counts t; a walk
-                              whose t-th draw repeats a node counts t */
+                              whose t-th draw repeats a node counts t (0 under
+                              SIA_FLAG_NO_CYCLE_STEPS) */
     uint64_t evaluations;  /* live-edge evaluations the device performed
                               (cycle detection and re-walks make it >= steps) */
     uint64_t walk_ids;     /* ids over all kept walks */
@@ -73,7 +91,7 @@ typedef struct {
     double suspension_est; /* |V\X| * covered / N  (Theorem "lem:rr_edge") */
     double suspension_nodes_est; /* suspension_est + |selected & X| (nodes) */
     float ms_sample;       /* device time of the sampling kernel (HIP events,
-                              on hip_stream), 0 unless timing was requested */
+                              on hip_stream), 0 without SIA_FLAG_TIMING */
     float ms_count;        /* coverage counting and greedy set-up */
     float ms_greedy;       /* greedy: pool rebuilds, walk lists of pool
                               ids, rounds */
@@ -231,12 +249,13 @@ sia_status sia_greedy_noalloc(int64_t id_space, const uint64_t *walk_off, const 
  * walks, and the estimates of Theorem "lem:rr_edge" / "lem:rr_node".
  *   selected   host int64[k] (out); gains host uint64[k] (out)
  *   stats      host (out, may be NULL)
- *   timing     nonzero: record HIP events around the phases into stats
+ *   flags      SIA_FLAG_TIMING | SIA_FLAG_NO_CYCLE_STEPS (0: neither); other
+ *              bits: SIA_EINVAL
  */
 sia_status sia_solve(const sia_graph *g, int mode, const int32_t *sources,
                      int64_t n_sources, int64_t k, uint64_t n_attempts,
                      uint64_t attempt_offset, uint64_t seed, int64_t *selected,
-                     uint64_t *gains, sia_stats *stats, int timing, void *hip_stream);
+                     uint64_t *gains, sia_stats *stats, int flags, void *hip_stream);
 
 /*
  * sia_solve with a candidate set C (Definitions "edge_remove" /
@@ -253,7 +272,7 @@ sia_status sia_solve_candidates(const sia_graph *g, int mode, const int32_t *sou
                                 int64_t n_sources, const int64_t *candidates,
                                 int64_t n_candidates, int64_t k, uint64_t n_attempts,
                                 uint64_t attempt_offset, uint64_t seed, int64_t *selected,
-                                uint64_t *gains, sia_stats *stats, int timing,
+                                uint64_t *gains, sia_stats *stats, int flags,
                                 void *hip_stream);
 
 /*
@@ -281,7 +300,7 @@ sia_status sia_sample_suspects(const sia_graph *g, int mode, const int32_t *susp
 sia_status sia_solve_suspects(const sia_graph *g, int mode, const int32_t *suspects, const float *p,
                               int64_t n_suspects, int64_t k, uint64_t n_attempts, uint64_t attempt_offset,
                               uint64_t seed, int64_t *selected, uint64_t *gains, sia_stats *stats,
-                              int timing, void *hip_stream);
+                              int flags, void *hip_stream);
 
 /* Figures of a Stop-and-Stare run (sia_sas_solve). */
 typedef struct {
@@ -440,7 +459,7 @@ typedef struct sia_batch sia_batch; /* opaque */
 /* One query: the arguments of sia_solve. */
 typedef struct {
     int32_t mode;            /* SIA_EDGES or SIA_NODES */
-    int32_t reserved;        /* must be 0 */
+    int32_t flags;           /* 0 or SIA_FLAG_NO_CYCLE_STEPS */
     const int32_t *sources;  /* host; copied by sia_batch_submit */
     int64_t n_sources;
     int64_t k;               /* >= 1 */

@@ -390,12 +390,15 @@ sia_status sia_greedy(int64_t id_space, const uint64_t *walk_off, const uint32_t
 static sia_status solve_impl(const sia_graph *cg, int mode, const int32_t *sources, const float *p,
                              int64_t n_sources, const int64_t *candidates, int64_t n_candidates, int64_t k,
                              uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
-                             int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
+                             int64_t *selected, uint64_t *gains, sia_stats *stats, int flags,
                              void *hip_stream)
 {
     return guarded([&] {
         SIA_REQUIRE(cg != nullptr && selected != nullptr && gains != nullptr, SIA_EINVAL,
                     "NULL argument");
+        SIA_REQUIRE((flags & ~(SIA_FLAG_TIMING | SIA_FLAG_NO_CYCLE_STEPS)) == 0, SIA_EINVAL, "unknown flag bits");
+        const bool timing = (flags & SIA_FLAG_TIMING) != 0;
+        const bool cycle_steps = (flags & SIA_FLAG_NO_CYCLE_STEPS) == 0;
         sia_graph *g = const_cast<sia_graph *>(cg);
         const SourceTables st = p ? build_suspect_tables(g->n, sources, p, n_sources)
                                   : (check_query(g->n, g->m, mode, sources, n_sources, k, n_attempts, attempt_offset),
@@ -427,7 +430,7 @@ static sia_status solve_impl(const sia_graph *cg, int mode, const int32_t *sourc
         // counts are taken by the greedy's counting pass: atomics fused into the
         // sampler's emission cost it 15% on rmat24 (their random lines compete
         // with its gathers)
-        const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, timing != 0);
+        const SampleResult r = run_sampler(g, mode, st, n_attempts, attempt_offset, seed, s, timing, cycle_steps);
         const int64_t id_space = mode == SIA_EDGES ? g->m : g->n;
         DevBuf d_cand;
         if (candidates) {
@@ -435,7 +438,7 @@ static sia_status solve_impl(const sia_graph *cg, int mode, const int32_t *sourc
             SIA_HIP(hipMemcpyAsync(d_cand.ptr, cand_bits.data(), 4 * cand_bits.size(), hipMemcpyHostToDevice, s));
         }
         const GreedyResult gr = run_greedy(g->ws, id_space, r.walks, r.ids, k, selected, gains, s,
-                                           timing != 0, candidates ? d_cand.as<uint32_t>() : nullptr);
+                                           timing, candidates ? d_cand.as<uint32_t>() : nullptr);
         float ms_total = 0.f;
         if (timing) {
             SIA_HIP(hipEventRecord(e1, s));
@@ -464,16 +467,16 @@ static sia_status solve_impl(const sia_graph *cg, int mode, const int32_t *sourc
 
 sia_status sia_solve(const sia_graph *cg, int mode, const int32_t *sources, int64_t n_sources,
                      int64_t k, uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
-                     int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
+                     int64_t *selected, uint64_t *gains, sia_stats *stats, int flags,
                      void *hip_stream)
 {
     return solve_impl(cg, mode, sources, nullptr, n_sources, nullptr, 0, k, n_attempts, attempt_offset, seed,
-                      selected, gains, stats, timing, hip_stream);
+                      selected, gains, stats, flags, hip_stream);
 }
 
 sia_status sia_solve_suspects(const sia_graph *cg, int mode, const int32_t *suspects, const float *p,
                               int64_t n_suspects, int64_t k, uint64_t n_attempts, uint64_t attempt_offset,
-                              uint64_t seed, int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
+                              uint64_t seed, int64_t *selected, uint64_t *gains, sia_stats *stats, int flags,
                               void *hip_stream)
 {
     if (!p) {
@@ -481,13 +484,13 @@ sia_status sia_solve_suspects(const sia_graph *cg, int mode, const int32_t *susp
         return SIA_EINVAL;
     }
     return solve_impl(cg, mode, suspects, p, n_suspects, nullptr, 0, k, n_attempts, attempt_offset, seed,
-                      selected, gains, stats, timing, hip_stream);
+                      selected, gains, stats, flags, hip_stream);
 }
 
 sia_status sia_solve_candidates(const sia_graph *cg, int mode, const int32_t *sources,
                                 int64_t n_sources, const int64_t *candidates, int64_t n_candidates,
                                 int64_t k, uint64_t n_attempts, uint64_t attempt_offset, uint64_t seed,
-                                int64_t *selected, uint64_t *gains, sia_stats *stats, int timing,
+                                int64_t *selected, uint64_t *gains, sia_stats *stats, int flags,
                                 void *hip_stream)
 {
     if (!candidates) {
@@ -495,7 +498,7 @@ sia_status sia_solve_candidates(const sia_graph *cg, int mode, const int32_t *so
         return SIA_EINVAL;
     }
     return solve_impl(cg, mode, sources, nullptr, n_sources, candidates, n_candidates, k, n_attempts,
-                      attempt_offset, seed, selected, gains, stats, timing, hip_stream);
+                      attempt_offset, seed, selected, gains, stats, flags, hip_stream);
 }
 
 }  // extern "C"

@@ -182,8 +182,11 @@ struct SampleResult {
 // A single query (slot bit 31): upload sources, tag them, run one wave
 // (rerunning with larger buffers if the output did not fit), untag.
 // Results stay in g->ws; coverage counts are taken by the greedy.
+// cycle_steps: search cyclic walks for their entry so that the steps counter
+// is exact (false: such walks stop at detection and count no steps).
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
-                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing);
+                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing,
+                         bool cycle_steps = true);
 
 struct GreedyResult {
     float ms_count = 0.f, ms_greedy = 0.f;

@@ -117,6 +117,10 @@ struct SlotDev {
     const uint32_t *coin_thr; // probabilistic suspects: per node, the seed coin's
                               // threshold (read for tagged nodes only); NULL:
                               // the tagged nodes are sources, start over V\X
+    uint32_t cycle_steps;     // 1: search each cyclic walk for its cycle entry so
+                              // its draws count exactly in the steps counter;
+                              // 0: stop it at detection (its outcome is the same)
+    uint32_t pad;
 };
 
 // The work table a sampling launch reads from device memory: the wave's

@@ -344,7 +344,12 @@ __global__ __launch_bounds__(256, 5) void k_sample(const WaveArgs A)
                             lambda = lam;
                             const uint32_t lo = past ? (power >> 1) : 0u;  // mu in [lo, t - lam]
                             do_eval = false;
-                            if (ring && ((it0 + t - 1u) >> 2) - ((it0 + lo) >> 2) < kRingCells) {
+                            if (!sl[slot].cycle_steps) {
+                                // the walk is discarded whatever its length: done
+                                atomicAdd(&acc[slot][2], 1ull);
+                                atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
+                                active = false;
+                            } else if (ring && ((it0 + t - 1u) >> 2) - ((it0 + lo) >> 2) < kRingCells) {
                                 // the cells of positions lo .. t-1 are all in the ring
                                 ring_flush(it0 + t - 1u);
                                 mbase = lo;
@@ -856,7 +861,8 @@ struct SourceTagScope {
 }  // namespace
 
 SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_t n_attempts,
-                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing)
+                         uint64_t attempt_offset, uint64_t seed, hipStream_t s, bool timing,
+                         bool cycle_steps)
 {
     Workspace &ws = g->ws;
     const uint32_t n_src = static_cast<uint32_t>(st.sorted.size());
@@ -926,6 +932,7 @@ SampleResult run_sampler(sia_graph *g, int mode, const SourceTables &st, uint64_
         S.id_cap = ws.id_cap;
         S.counters = d_counters;
         S.coin_thr = st.probabilistic ? ws.coin_thr.as<uint32_t>() : nullptr;
+        S.cycle_steps = cycle_steps ? 1u : 0u;
         SIA_HIP(hipMemcpyAsync(d_slot, &S, sizeof(S), hipMemcpyHostToDevice, s));
         const WaveItem item{0u, 0u, launch_attempts};
         WaveTable table;

@@ -339,7 +339,8 @@ static void sas_impl(sia_graph *g, int mode, const SourceTables &st, int64_t k, 
                     c = static_cast<uint64_t>(std::min(want, static_cast<double>(uint64_t(1) << 30)));
                 }
                 c = std::min(c, max_attempts - end);
-                const SampleResult r = run_sampler(g, mode, st, c, end, seed, s, false);
+                // (the driver reports no step counts: cyclic walks stop at detection)
+                const SampleResult r = run_sampler(g, mode, st, c, end, seed, s, false, false);
                 grow_keep(s_att, 8 * s_n, 8 * (s_n + r.walks), s);
                 grow_keep(s_off, 8 * s_n, 8 * (s_n + r.walks), s);
                 grow_keep(s_len, 4 * s_n, 4 * (s_n + r.walks), s);

@@ -45,6 +45,7 @@ struct Ticket {
     int mode = SIA_EDGES;
     int64_t k = 0;
     uint64_t n_attempts = 0, offset = 0, seed = 0;
+    bool cycle_steps = true;  // search cyclic walks for their entry (exact steps)
     SourceTables st;
     TState state = TState::Pending;
     sia_status status = SIA_OK;
@@ -326,6 +327,7 @@ struct sia_batch {
         S.walk_cap = sl.walk_cap;
         S.id_cap = sl.id_cap;
         S.counters = d_ctr.as<uint64_t>() + static_cast<size_t>(i) * ST_COUNT;
+        S.cycle_steps = t.cycle_steps ? 1u : 0u;
         return S;
     }
 
@@ -1102,8 +1104,9 @@ sia_status sia_batch_submit(sia_batch *b, const sia_query *q, uint64_t *ticket)
         check_query(b->g->n, b->g->m, q->mode, q->sources, q->n_sources, q->k, q->n_attempts,
                     q->attempt_offset);
         SIA_REQUIRE(q->k >= 1, SIA_EINVAL, "k must be >= 1");
-        SIA_REQUIRE(q->reserved == 0, SIA_EINVAL, "reserved field must be 0");
+        SIA_REQUIRE((q->flags & ~SIA_FLAG_NO_CYCLE_STEPS) == 0, SIA_EINVAL, "unknown flag bits");
         auto t = std::make_shared<Ticket>();
+        t->cycle_steps = (q->flags & SIA_FLAG_NO_CYCLE_STEPS) == 0;
         t->mode = q->mode;
         t->k = q->k;
         t->n_attempts = q->n_attempts;

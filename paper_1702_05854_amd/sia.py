@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsia.so")
 EDGES = 0
 NODES = 1
 MODES = {"edges": EDGES, "nodes": NODES, EDGES: EDGES, NODES: NODES}
+FLAG_TIMING = 1           # SIA_FLAG_TIMING
+FLAG_NO_CYCLE_STEPS = 2   # SIA_FLAG_NO_CYCLE_STEPS
 
 STATUS = {0: "SIA_OK", -1: "SIA_EINVAL", -2: "SIA_EWEIGHTS", -3: "SIA_ENOMEM",
           -4: "SIA_EDEVICE", -5: "SIA_ENOTREADY", -6: "SIA_ECANCELLED", -7: "SIA_EBUSY"}
@@ -56,7 +58,7 @@ class SasInfo(C.Structure):
 
 
 class Query(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("reserved", C.c_int32), ("sources", C.c_void_p),
+    _fields_ = [("mode", C.c_int32), ("flags", C.c_int32), ("sources", C.c_void_p),
                 ("n_sources", C.c_int64), ("k", C.c_int64), ("n_attempts", C.c_uint64),
                 ("attempt_offset", C.c_uint64), ("seed", C.c_uint64)]
 
@@ -303,7 +305,7 @@ def sample_suspects(graph: Graph, suspects, p, mode, n_attempts, attempt_offset=
 
 
 def solve_suspects(graph: Graph, suspects, p, mode, k, n_attempts, attempt_offset=0, seed=2017, timing=False,
-                   stream=None):
+                   stream=None, cycle_steps=True):
     """The whole path with probabilistic suspects (sia_solve_suspects)."""
     sus = _host(suspects, np.int32)
     pr = _host(p, np.float32)
@@ -313,7 +315,7 @@ def solve_suspects(graph: Graph, suspects, p, mode, k, n_attempts, attempt_offse
     st = Stats()
     _check(lib().sia_solve_suspects(graph.handle, MODES[mode], _hptr(sus), _hptr(pr), sus.shape[0], k, n_attempts,
                                     attempt_offset, seed, _hptr(sel), _hptr(gains), C.byref(st),
-                                    1 if timing else 0, _stream(stream)))
+                                    _flags(timing, cycle_steps), _stream(stream)))
     return dict(selected=sel, gains=gains, stats=st.as_dict())
 
 
@@ -343,10 +345,16 @@ def greedy_noalloc(id_space, walk_off, ids, k, stream=None):
     return sel, gains
 
 
+def _flags(timing, cycle_steps):
+    return (FLAG_TIMING if timing else 0) | (0 if cycle_steps else FLAG_NO_CYCLE_STEPS)
+
+
 def solve(graph: Graph, sources, mode, k, n_attempts, attempt_offset=0, seed=2017, timing=False,
-          stream=None, candidates=None):
+          stream=None, candidates=None, cycle_steps=True):
     """The whole path for one query; candidates (ids the picks are drawn
-    from) calls sia_solve_candidates."""
+    from) calls sia_solve_candidates.  cycle_steps=False passes
+    SIA_FLAG_NO_CYCLE_STEPS: walks that close a cycle stop at detection and
+    stats["steps"] leaves out their draws; every other output is the same."""
     src = _host(sources, np.int32)
     sel = np.zeros(k, dtype=np.int64)
     gains = np.zeros(k, dtype=np.uint64)
@@ -354,13 +362,13 @@ def solve(graph: Graph, sources, mode, k, n_attempts, attempt_offset=0, seed=201
     if candidates is None:
         _check(lib().sia_solve(graph.handle, MODES[mode], _hptr(src), src.shape[0], k, n_attempts,
                                attempt_offset, seed, _hptr(sel), _hptr(gains), C.byref(st),
-                               1 if timing else 0, _stream(stream)))
+                               _flags(timing, cycle_steps), _stream(stream)))
     else:
         cand = _host(candidates, np.int64)
         _check(lib().sia_solve_candidates(graph.handle, MODES[mode], _hptr(src), src.shape[0],
                                           _hptr(cand), cand.shape[0], k, n_attempts, attempt_offset,
                                           seed, _hptr(sel), _hptr(gains), C.byref(st),
-                                          1 if timing else 0, _stream(stream)))
+                                          _flags(timing, cycle_steps), _stream(stream)))
     return dict(selected=sel, gains=gains, stats=st.as_dict())
 
 
@@ -433,9 +441,10 @@ def sas_check(cov_r, cov_rp, n_rp, t, eps, lam1):
     return bool(passed.value), tuple(terms)
 
 
-def _query(sources, mode, k, n_attempts, attempt_offset, seed):
+def _query(sources, mode, k, n_attempts, attempt_offset, seed, cycle_steps=True):
     src = _host(sources, np.int32)
-    q = Query(MODES[mode], 0, src.ctypes.data, src.shape[0], k, n_attempts, attempt_offset, seed)
+    q = Query(MODES[mode], _flags(False, cycle_steps), src.ctypes.data, src.shape[0], k, n_attempts,
+              attempt_offset, seed)
     return q, src  # src keeps the array alive while q is used
 
 
@@ -455,8 +464,8 @@ class Batch:
         self.graph = graph  # the graph must outlive the batch
         self._k = {}
 
-    def submit(self, sources, mode, k, n_attempts, attempt_offset=0, seed=2017):
-        q, src = _query(sources, mode, k, n_attempts, attempt_offset, seed)
+    def submit(self, sources, mode, k, n_attempts, attempt_offset=0, seed=2017, cycle_steps=True):
+        q, src = _query(sources, mode, k, n_attempts, attempt_offset, seed, cycle_steps)
         t = C.c_uint64()
         _check(lib().sia_batch_submit(self._h, C.byref(q), C.byref(t)))
         self._k[t.value] = k

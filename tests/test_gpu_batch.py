@@ -64,7 +64,7 @@ def mix(n, count, seed, **kw):
 
 def solo(sia, g, q):
     return sia.solve(g, q["sources"], q["mode"], q["k"], q["n_attempts"], q.get("offset", 0),
-                     q["seed"])
+                     q["seed"], cycle_steps=q.get("cycle_steps", True))
 
 
 def assert_same(got, ref, what):
@@ -85,7 +85,7 @@ def done(b, t, limit_ms=100_000):
 def serve(sia, g, queries, **kw):
     with sia.Batch(g, **kw) as b:
         tickets = [b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], q.get("offset", 0),
-                            q["seed"]) for q in queries]
+                            q["seed"], q.get("cycle_steps", True)) for q in queries]
         out = [done(b, t) for t in tickets]
         return out, b.stats()
 
@@ -127,6 +127,19 @@ def test_mix_matches_solo_general_records(sia, rmat16_general):
     """Batches on a graph with 32-byte records (per-slot tag bits in them)."""
     wl, g = rmat16_general
     qs = mix(wl.n, 20, 21, max_sources=1000, k_range=(10, 200), attempts_range=(10_000, 500_000))
+    got, st = serve(sia, g, qs, max_slots=8)
+    assert st["completed"] == len(qs) and st["failed"] == 0
+    for i, q in enumerate(qs):
+        assert_same(got[i], solo(sia, g, q), i)
+
+
+def test_mix_with_cycles_stopped_at_detection(sia, rmat16):
+    """Queries that skip the cycle-entry search share launches with queries
+    that do not; each equals its own single-query call with the same flag."""
+    wl, g = rmat16
+    qs = mix(wl.n, 16, 22, max_sources=1000, k_range=(10, 200), attempts_range=(10_000, 500_000))
+    for i, q in enumerate(qs):
+        q["cycle_steps"] = i % 2 == 0
     got, st = serve(sia, g, qs, max_slots=8)
     assert st["completed"] == len(qs) and st["failed"] == 0
     for i, q in enumerate(qs):

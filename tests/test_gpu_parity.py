@@ -526,6 +526,64 @@ def test_solve_edge_cases(sia):
     assert got["stats"]["dead_ends"] == 1000 and got["selected"].tolist() == [0, 1]
 
 
+# ---------------------------------------- cyclic walks stopped at detection
+SAME_WITHOUT_CYCLE_STEPS = ("attempts", "hits", "dead_ends", "cycles", "walk_ids", "covered", "spread_est",
+                            "suspension_est", "suspension_nodes_est")
+
+
+@pytest.mark.parametrize("weights", ["inv_indeg", "normalized"])
+def test_no_cycle_steps_changes_only_the_step_count(sia, weights):
+    """SIA_FLAG_NO_CYCLE_STEPS stops a walk that closes a cycle when the cycle
+    is detected (Algorithm 1 discards it either way).  Picks, gains and every
+    counter but steps and evaluations equal the exact run's and the oracle's;
+    the step count loses the cyclic walks' draws, at least one each, and
+    keeps the kept walks' draws and at least one per dead end."""
+    from paper_1702_05854_amd import workloads
+    wl = workloads.load("rmat22", scale=16, weights=weights)
+    col, row, w = wl.host()
+    g = sia.Graph(col, row, w)
+    og = cpu.Graph(col, row, w)
+    for mode in ("edges", "nodes"):
+        exact = sia.solve(g, wl.sources, mode, 50, 300_000, 77, SEED)
+        fast = sia.solve(g, wl.sources, mode, 50, 300_000, 77, SEED, cycle_steps=False)
+        ref = cpu.solve(og, wl.sources, omode(mode), 50, 300_000, 77, SEED)
+        assert np.array_equal(fast["selected"], ref["selected"]) and np.array_equal(fast["gains"], ref["gains"])
+        assert np.array_equal(exact["selected"], ref["selected"])
+        e, f = exact["stats"], fast["stats"]
+        for key in SAME_WITHOUT_CYCLE_STEPS:
+            assert f[key] == e[key], (mode, key)
+        assert e["steps"] == ref["walks"].steps and f["hits"] == ref["walks"].hits
+        assert f["cycles"] == ref["walks"].cycles > 0
+        kept_draws = f["walk_ids"] if mode == "edges" else f["walk_ids"] - f["hits"]
+        assert kept_draws + f["dead_ends"] <= f["steps"] <= e["steps"] - f["cycles"], mode
+        # 16-byte records search the entry by walking the graph again; 32-byte
+        # records bisect their walk ring, which takes no evaluation (walks
+        # longer than the ring excepted)
+        if g.arc_bytes == 16:
+            assert f["evaluations"] < e["evaluations"], mode
+        else:
+            assert f["evaluations"] <= e["evaluations"], mode
+    g.close()
+
+
+def test_no_cycle_steps_on_a_pure_cycle(sia):
+    """Two nodes feeding each other with weight 1 and an isolated source:
+    every attempt walks 0 -> 1 -> 0 (or 1 -> 0 -> 1), a cycle after two
+    draws.  Exact: 2 steps per attempt; stopped at detection: none."""
+    col, row, w = csc_from_edges(3, [(0, 1, 1.0), (1, 0, 1.0)])
+    g = sia.Graph(col, row, w)
+    for mode in ("edges", "nodes"):
+        exact = sia.solve(g, [2], mode, 1, 5000, 0, SEED)["stats"]
+        fast = sia.solve(g, [2], mode, 1, 5000, 0, SEED, cycle_steps=False)["stats"]
+        assert exact["cycles"] == fast["cycles"] == 5000 and exact["hits"] == fast["hits"] == 0
+        assert exact["steps"] == 10_000 and fast["steps"] == 0
+    # flag bits the library does not know are refused
+    sel, gains, src = np.zeros(1, np.int64), np.zeros(1, np.uint64), np.array([2], np.int32)
+    assert sia.lib().sia_solve(g.handle, 0, src.ctypes.data, 1, 1, 100, 0, SEED, sel.ctypes.data,
+                               gains.ctypes.data, None, 4, None) == -1
+    g.close()
+
+
 @pytest.mark.parametrize("layout", ["dense", "runs", "ends"])
 def test_start_ranks_with_dense_sources(sia, layout):
     """The start of an attempt is the idx-th non-source; its rank among the
