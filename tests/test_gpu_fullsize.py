@@ -7,10 +7,13 @@
   sampled attempt ids (kept and not kept) against the oracle walking those
   attempts one by one; counters against invariants; the greedy on a prefix
   of the kept walks against the oracle; and properties of the full solve
-  that hold at any size.
+  that hold at any size; and the whole query against the oracle's digest
+  (every counter, the kept walks in attempt order, the counts, all k picks
+  and gains).
 * rmat26 (R-MAT scale 26, edge factor 24, 1.6*10^9 edges, 10^5 sources,
-  N=2*10^8): the full solve's invariants, a window of kept walks against the
-  oracle attempt by attempt, and the greedy on a prefix of them.
+  N=2*10^8): the whole query against the oracle's digest as for rmat24; the
+  full solve's invariants, a window of kept walks against the oracle
+  attempt by attempt, and the greedy on a prefix of them.
 * rmat22 (R-MAT scale 22) with mixed queries: batched answers equal the
   single-query path's, the smallest also the oracle's.
 """
@@ -210,6 +213,15 @@ def rmat26(sia):
     torch.cuda.synchronize()
     yield wl, g
     g.close()
+
+
+def test_rmat26_whole_query_matches_oracle_digest(sia, rmat26):
+    """The billion-edge query (R-MAT scale 26, edge factor 24, 1.6*10^9
+    edges with 32-byte records, 10^5 sources, N = 2*10^8, k = 1000) equal to
+    the oracle as a whole: counters, the attempt-ordered kept walks, the
+    counts, all 1000 picks and gains."""
+    wl, g = rmat26
+    compare_with_digest(sia, g, wl, _digest("rmat26"))
 
 
 def test_rmat26_billion_edges(sia, rmat26):
