@@ -1,8 +1,9 @@
 """The oracle's range sampler over disjoint attempt ranges in worker
 processes, merged in attempt order.
 
-TEST INFRASTRUCTURE ONLY (the full-size digest script and the benchmark's
-multi-core CPU-baseline leg).
+TEST INFRASTRUCTURE ONLY (the full-size digest script, the benchmark's
+multi-core CPU-baseline leg, and the full-size tests that solve several
+queries with the oracle at once).
 
 Attempt ids key the random stream (Philox keyed by (seed, attempt id)), so
 the walks of a range do not depend on which process samples it, and the
@@ -85,3 +86,37 @@ def sample(graph, sources, mode, n_attempts, offset=0, seed=0, procs=None, shard
     off = np.concatenate(offs + [np.array([base], np.uint64)])
     ids = np.concatenate(idss)
     return MergedWalks(attempt, off, ids, counters)
+
+
+def _solve_worker(job):
+    d, q = job
+    g = cpu.Graph.from_tables(np.load(os.path.join(d, "col_off.npy"), mmap_mode="r"),
+                              np.load(os.path.join(d, "row_idx.npy"), mmap_mode="r"),
+                              np.load(os.path.join(d, "thr.npy"), mmap_mode="r"))
+    mode = cpu.MODE_EDGES if q["mode"] == "edges" else cpu.MODE_NODES
+    r = cpu.solve(g, np.asarray(q["sources"], np.int32), mode, q["k"], q["n_attempts"], q.get("offset", 0),
+                  q["seed"])
+    w = r["walks"]
+    return dict(selected=r["selected"], gains=r["gains"], covered=r["covered"], hits=w.hits,
+                dead_ends=w.dead_ends, cycles=w.cycles, steps=w.steps, walk_ids=int(w.ids.shape[0]))
+
+
+def solve_many(graph, queries, procs=None, log=None):
+    """cpu.solve of every query (dicts with sources, mode 'edges'/'nodes', k,
+    n_attempts, seed and optional offset) on `graph`, one query per worker
+    process at a time; returns, in query order, dicts with the picks, gains,
+    covered count and the walk counters."""
+    procs = max(1, procs or os.cpu_count() or 1)
+    base_dir = "/dev/shm" if os.path.isdir("/dev/shm") else None
+    with tempfile.TemporaryDirectory(prefix="sia_oracle_", dir=base_dir) as d:
+        np.save(os.path.join(d, "col_off.npy"), graph.col_off)
+        np.save(os.path.join(d, "row_idx.npy"), graph.row_idx)
+        np.save(os.path.join(d, "thr.npy"), graph.thr)
+        out = [None] * len(queries)
+        with ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as pool:
+            futs = {pool.submit(_solve_worker, (d, q)): i for i, q in enumerate(queries)}
+            for done, f in enumerate(as_completed(futs), 1):
+                out[futs[f]] = f.result()
+                if log:
+                    log(f"oracle query {done}/{len(queries)} done")
+    return out

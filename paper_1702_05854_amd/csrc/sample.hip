@@ -72,6 +72,9 @@ enum Phase : uint32_t {
 };
 
 constexpr uint32_t kRingCells = kRingRows / 4;  // a lane's 16-byte cells: positions 4c .. 4c+3
+// Depth of each lane's LDS stack of the stack cycle detector (Nivasch, IPL
+// 2004) used when cyclic walks stop at detection; a power of two.
+constexpr uint32_t kStack = 16;
 constexpr uint32_t kCellMask = kRingCells - 1;
 constexpr uint32_t kEmitPerIter = 4;  // ids a lane copies from the ring per iteration
 
@@ -210,6 +213,8 @@ __global__ __launch_bounds__(256, 5) void k_sample(const WaveArgs A)
     __shared__ uint32_t is[kMaxItems];
     // per-slot counters of this workgroup: hits, dead ends, cycles, steps, evaluations, faults
     __shared__ unsigned long long acc[kMaxSlots + 1][6];
+    // each lane's detector stack, entry e of thread i at stk[e][i] (bank-conflict free)
+    __shared__ uint32_t stk[kStack][256];
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t n_items = A.table->n_items;
     for (uint32_t i = threadIdx.x; i < A.n_slots; i += blockDim.x) sl[i] = A.slots[i];
@@ -263,6 +268,15 @@ __global__ __launch_bounds__(256, 5) void k_sample(const WaveArgs A)
     uint64_t a = 0, out_pos = 0, seed = 0;
     uint32_t slot = 0, mode = SIA_EDGES, tag_mask = 0;
     bool psus = false;  // the lane's query has probabilistic suspects
+    // Stack detector (walks of queries that stop cyclic walks at detection):
+    // the walk's nodes that no later node undercuts, increasing from the
+    // bottom; a node equal to the top after popping the larger ones was
+    // visited before.  The cycle's smallest node is never popped once pushed,
+    // so its second visit is caught -- within one lap past the first repeat
+    // instead of Brent's up to two.  A full stack drops its bottom (a ring:
+    // sb is the bottom's slot); what it then misses Brent still catches.
+    bool use_stack = false;
+    uint32_t sd = 0, sb = 0, stop = 0;  // depth, bottom slot, top value
     bool ck = false;    // cur is a suspect: its coin threshold is read with this evaluation
     uint32_t phase = PH_START, x1 = 0, cur = 0, tort = 0, power = 1, lam = 0, t = 0, lambda = 0,
              cnt = 0, pa = 0, pb = 0, evals = 0, ptort = 0, mbase = 0,
@@ -302,6 +316,9 @@ __global__ __launch_bounds__(256, 5) void k_sample(const WaveArgs A)
                 mode = S.mode;
                 tag_mask = S.tag_mask;
                 psus = S.coin_thr != nullptr;
+                use_stack = !S.cycle_steps;
+                sd = 0;
+                sb = 0;
                 ck = false;
                 phase = PH_START;
                 fetch = false;
@@ -332,7 +349,27 @@ __global__ __launch_bounds__(256, 5) void k_sample(const WaveArgs A)
                 do_eval = true;
                 if (phase == PH_DETECT) {
                     y = cur;
-                    if (t > 0 && !ck) {  // (a coin retry evaluates a position already checked)
+                    bool revisit = false;
+                    if (use_stack && !ck) {
+                        while (sd && stop > cur) {
+                            --sd;
+                            stop = sd ? stk[(sb + sd - 1u) & (kStack - 1u)][threadIdx.x] : 0u;
+                        }
+                        if (sd && stop == cur) {
+                            revisit = true;
+                        } else {
+                            if (sd == kStack) sb = (sb + 1u) & (kStack - 1u);
+                            else ++sd;
+                            stk[(sb + sd - 1u) & (kStack - 1u)][threadIdx.x] = cur;
+                            stop = cur;
+                        }
+                    }
+                    if (revisit) {  // a cycle, found by the stack: the walk is discarded
+                        do_eval = false;
+                        atomicAdd(&acc[slot][2], 1ull);
+                        atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
+                        active = false;
+                    } else if (t > 0 && !ck) {  // (a coin retry evaluates a position already checked)
                         ++lam;
                         if (cur == tort) {  // Brent: cycle of length lam (tort is never a source)
                             // The tortoise sits at positions 2^j - 1 with a window of
