@@ -349,27 +349,7 @@ __global__ __launch_bounds__(256, 5) void k_sample(const WaveArgs A)
                 do_eval = true;
                 if (phase == PH_DETECT) {
                     y = cur;
-                    bool revisit = false;
-                    if (use_stack && !ck) {
-                        while (sd && stop > cur) {
-                            --sd;
-                            stop = sd ? stk[(sb + sd - 1u) & (kStack - 1u)][threadIdx.x] : 0u;
-                        }
-                        if (sd && stop == cur) {
-                            revisit = true;
-                        } else {
-                            if (sd == kStack) sb = (sb + 1u) & (kStack - 1u);
-                            else ++sd;
-                            stk[(sb + sd - 1u) & (kStack - 1u)][threadIdx.x] = cur;
-                            stop = cur;
-                        }
-                    }
-                    if (revisit) {  // a cycle, found by the stack: the walk is discarded
-                        do_eval = false;
-                        atomicAdd(&acc[slot][2], 1ull);
-                        atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
-                        active = false;
-                    } else if (t > 0 && !ck) {  // (a coin retry evaluates a position already checked)
+                    if (t > 0 && !ck) {  // (a coin retry evaluates a position already checked)
                         ++lam;
                         if (cur == tort) {  // Brent: cycle of length lam (tort is never a source)
                             // The tortoise sits at positions 2^j - 1 with a window of
@@ -517,6 +497,25 @@ __global__ __launch_bounds__(256, 5) void k_sample(const WaveArgs A)
                 else v = *src;
             }
             const uint32_t cthr = (do_eval && ck) ? gp(sl[slot].coin_thr)[cur] : 0u;
+            // the stack detector runs while the gather is in flight (a walk it
+            // ends leaves that one record unused)
+            if (use_stack && do_eval && phase == PH_DETECT && !ck) {
+                while (sd && stop > cur) {
+                    --sd;
+                    stop = sd ? stk[(sb + sd - 1u) & (kStack - 1u)][threadIdx.x] : 0u;
+                }
+                if (sd && stop == cur) {  // a repeat: a cycle, the walk is discarded
+                    do_eval = false;
+                    atomicAdd(&acc[slot][2], 1ull);
+                    atomicAdd(&acc[slot][4], static_cast<unsigned long long>(evals));
+                    active = false;
+                } else {
+                    if (sd == kStack) sb = (sb + 1u) & (kStack - 1u);
+                    else ++sd;
+                    stk[(sb + sd - 1u) & (kStack - 1u)][threadIdx.x] = cur;
+                    stop = cur;
+                }
+            }
             if (fetch_now || tag_only) {
                 R = NodeRec{v.x, v.y, v.z, v.w};
             } else if (live) {
