@@ -65,15 +65,17 @@ def per_step_bytes(st, n_attempts, step_bytes):
     return step_bytes * st["steps"] + 4 * n_attempts + 4 * st["walk_ids"] + 16 * st["hits"]
 
 
-def load_traffic():
+def load_traffic(workload):
+    """Counter traffic of the sampler launch on this workload, if it was taken
+    on the current kernel sources: (fetch + write bytes, fetch bytes)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None
-    if t.get("kernel_sha") != kernel_sha():
-        return None
-    return t.get("traffic_bytes_per_launch")
+        return None, None
+    if t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload:
+        return None, None
+    return t.get("traffic_bytes_per_launch"), t.get("fetch_bytes_per_launch")
 
 
 def host_cpu():
@@ -524,6 +526,7 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     b_alg = algorithmic_bytes(st)
     achieved = b_alg / (ms_sample * 1e-3) / 1e9
+    traffic, fetched = load_traffic(args.workload)
 
     out = {
         "metric": "HSAW attempts/s (whole eSIA hot path: sample + count + greedy)",
@@ -557,7 +560,8 @@ def main():
         "suspension_est": st["suspension_est"],
         "roofline": {"bound": "hbm", "kernel": "k_sample", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_launch": b_alg, "traffic": load_traffic(),
+                     "algorithmic_bytes_per_launch": b_alg, "traffic": traffic,
+                     "gather_efficiency": b_alg / fetched if fetched else None,
                      "frac_other_readings": {
                          **{f"{sb} B/step flat": per_step_bytes(st, n_att, sb) / (ms_sample * 1e-3) / 1e9
                             / HBM_PEAK_GBS for sb in (29, 21)},
