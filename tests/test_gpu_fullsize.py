@@ -164,7 +164,8 @@ def compare_with_digest(sia, g, wl, D):
     written by tests/golden/make_fullsize_digest.py from the oracle alone, run
     over disjoint attempt ranges in several processes and merged in attempt
     order): the graph, the counters, the attempt-ordered kept walks, the
-    coverage counts, and the k picks and gains of the full solve."""
+    coverage counts, and the k picks and gains of the full solve, with
+    cyclic walks searched for their entry and stopped at detection."""
     assert (g.n, g.m, wl.seed) == (D["n"], D["m"], D["seed"])
     assert _sha(np.asarray(wl.sources, np.int32)) == D["sources_sha256"]
     col_off, row_idx, w = wl.host()
@@ -192,6 +193,14 @@ def compare_with_digest(sia, g, wl, D):
     assert res["gains"].tolist() == D["gains"]
     assert res["stats"]["covered"] == D["covered"]
     assert res["stats"]["hits"] == C["hits"] and res["stats"]["steps"] == C["steps"]
+    # the launch the benchmark times: cyclic walks stopped at detection
+    say("gpu solve k =", k, "(cyclic walks stopped at detection)")
+    res = sia.solve(g, wl.sources, D["mode"], k, N, D["attempt_offset"], wl.seed, cycle_steps=False)
+    st = res["stats"]
+    assert res["selected"].tolist() == D["selected"] and res["gains"].tolist() == D["gains"]
+    assert (st["covered"], st["hits"], st["dead_ends"], st["cycles"], st["walk_ids"]) == (
+        D["covered"], C["hits"], C["dead_ends"], C["cycles"], C["walk_ids"])
+    assert st["steps"] <= C["steps"] - C["cycles"]
 
 
 def test_rmat24_whole_query_matches_oracle_digest(sia, rmat24):

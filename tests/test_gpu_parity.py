@@ -569,7 +569,9 @@ def test_no_cycle_steps_changes_only_the_step_count(sia, weights):
 def test_no_cycle_steps_on_a_pure_cycle(sia):
     """Two nodes feeding each other with weight 1 and an isolated source:
     every attempt walks 0 -> 1 -> 0 (or 1 -> 0 -> 1), a cycle after two
-    draws.  Exact: 2 steps per attempt; stopped at detection: none."""
+    draws.  Exact: 2 steps per attempt; stopped at detection: none.  The
+    same on 40-node rings, whose walks visit more nodes than the stack
+    detector holds."""
     col, row, w = csc_from_edges(3, [(0, 1, 1.0), (1, 0, 1.0)])
     g = sia.Graph(col, row, w)
     for mode in ("edges", "nodes"):
@@ -577,6 +579,21 @@ def test_no_cycle_steps_on_a_pure_cycle(sia):
         fast = sia.solve(g, [2], mode, 1, 5000, 0, SEED, cycle_steps=False)["stats"]
         assert exact["cycles"] == fast["cycles"] == 5000 and exact["hits"] == fast["hits"] == 0
         assert exact["steps"] == 10_000 and fast["steps"] == 0
+    g.close()
+    # 40-node rings walked with increasing ids (the stack overflows and drops
+    # the cycle's smallest node, so Brent must end the walks) and with
+    # decreasing ids (the stack ends them); node 40 is an isolated source
+    for edges in ([((i + 1) % 40, i, 1.0) for i in range(40)], [(i, (i + 1) % 40, 1.0) for i in range(40)]):
+        col, row, w = csc_from_edges(41, edges)
+        g = sia.Graph(col, row, w)
+        for mode in ("edges", "nodes"):
+            exact = sia.solve(g, [40], mode, 1, 5000, 0, SEED)["stats"]
+            fast = sia.solve(g, [40], mode, 1, 5000, 0, SEED, cycle_steps=False)["stats"]
+            assert exact["cycles"] == fast["cycles"] == 5000 and exact["steps"] == 40 * 5000
+            assert fast["steps"] == 0 and fast["hits"] == 0
+        g.close()
+    col, row, w = csc_from_edges(3, [(0, 1, 1.0), (1, 0, 1.0)])
+    g = sia.Graph(col, row, w)
     # flag bits the library does not know are refused
     sel, gains, src = np.zeros(1, np.int64), np.zeros(1, np.uint64), np.array([2], np.int32)
     assert sia.lib().sia_solve(g.handle, 0, src.ctypes.data, 1, 1, 100, 0, SEED, sel.ctypes.data,
