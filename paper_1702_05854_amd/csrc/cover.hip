@@ -253,18 +253,6 @@ __device__ __forceinline__ uint64_t key_of(uint32_t c, uint32_t id)
     return c == kSelected ? 0ull : ((static_cast<uint64_t>(c) + 1ull) << 32) | (0xFFFFFFFFu - id);
 }
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
-{
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), d, kWave);
-        uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), d, kWave);
-        uint64_t o = (static_cast<uint64_t>(hi) << 32) | lo;
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
 __device__ __forceinline__ bool job_done(const GJob &J)
 {
     return J.st->error != 0 || static_cast<int64_t>(J.st->rounds) >= J.k;
@@ -1078,7 +1066,10 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
 {
     constexpr int kWaves = T / kWave;
     constexpr int kPer = kPoolMax / T;
-    __shared__ uint64_t sh[kWaves];
+    // each wave's best key and its list range, double-buffered by round parity
+    // (a wave can be one round ahead of the slowest reader, not two)
+    __shared__ uint64_t shk[2][kWaves];
+    __shared__ uint32_t shlo[2][kWaves], shhi[2][kWaves];
     __shared__ uint32_t sh32[kWaves];
     __shared__ uint32_t start[T];        // a pass's walks: first flattened position
     __shared__ uint64_t woff[T];         //                 and offset into ids
@@ -1086,7 +1077,6 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
     __shared__ uint32_t pids[kPoolMax];
     __shared__ uint32_t slot[kHash];
     __shared__ uint32_t filt[kFilterWords];
-    __shared__ uint32_t wlo, whi;        // list range of the chosen id
     const GJob J = view(jobs[blockIdx.x]);
     if (job_done(J)) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -1123,21 +1113,47 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
     int64_t r = r0;
     uint32_t cbase = st->n_claimed;  // uniform: next entry of the claimed list
     for (; r < J.k; ++r) {
-        // exact keys of the pool; the largest is this round's pick if it beats tau
+        // exact keys of the pool; the largest is this round's pick if it beats
+        // tau.  The key and the list range of each wave's best travel together,
+        // so every thread ends the reduction knowing the pick's list.
         uint64_t best = 0;
+        uint32_t blo = 0, bhi = 0;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const uint32_t i = threadIdx.x + j * T;
             if (i < P) {
                 const uint64_t key = key_of(pcnt[i], pid[j]);
-                best = key > best ? key : best;
+                if (key > best) {
+                    best = key;
+                    blo = plo[j];
+                    bhi = phi[j];
+                }
             }
         }
-        best = wave_max_u64(best);
-        if (lane == 0) sh[wid] = best;
+        const int par = static_cast<int>(r & 1);
+        // wave maximum of the 64-bit keys from two 32-bit wave reductions (the
+        // device library's, across lanes without LDS): the count part, then
+        // the id part among the lanes that hold that count
+        const uint32_t mh = __ockl_wfred_max_u32(static_cast<uint32_t>(best >> 32));
+        const uint32_t ml = __ockl_wfred_max_u32(static_cast<uint32_t>(best >> 32) == mh ? static_cast<uint32_t>(best) : 0u);
+        const uint64_t wbest = (static_cast<uint64_t>(mh) << 32) | ml;
+        // keys are distinct (an id is in the pool once), so one lane holds a
+        // nonzero wave maximum; lane 0 reports a wave without keys
+        if (wbest != 0 ? best == wbest : lane == 0) {
+            shk[par][wid] = wbest;
+            shlo[par][wid] = blo;
+            shhi[par][wid] = bhi;
+        }
         __syncthreads();
-        best = sh[0];
-        for (int w = 1; w < kWaves; ++w) best = sh[w] > best ? sh[w] : best;
+        best = 0;
+        uint32_t lo = 0, hi = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (shk[par][w] > best) {
+                best = shk[par][w];
+                lo = shlo[par][w];
+                hi = shhi[par][w];
+            }
+        }
         if (best <= tau) break;  // uniform: every thread saw the same values
         const uint32_t id = 0xFFFFFFFFu - static_cast<uint32_t>(best);
         const uint32_t g = static_cast<uint32_t>(best >> 32) - 1u;
@@ -1159,21 +1175,19 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             r += static_cast<int64_t>(taken < need ? taken : need);
             break;
         }
+        // the owner marks the pick (only the owner reads its count in later
+        // argmaxes; the covering below skips the pick's own id)
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const uint32_t i = threadIdx.x + j * T;
-            if (i < P && pid[j] == id) {  // the pool holds each id once
-                pcnt[i] = kSelected;
-                wlo = plo[j];
-                whi = phi[j];
-            }
+            if (i < P && pid[j] == id) pcnt[i] = kSelected;  // the pool holds each id once
         }
         if (threadIdx.x == 0) {
             J.sel[r] = id;
             J.gain[r] = g;
         }
-        __syncthreads();
         if (g == 0) {
+            __syncthreads();  // every thread reads the marks below
             // Every unselected pool id has count 0, and so has every id
             // outside the pool (this is a tie plan at count 0: all ids with a
             // count were collected), whose ids are all >= next_id when tied
@@ -1220,7 +1234,6 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             r += taken;
             break;
         }
-        const uint32_t lo = wlo, hi = whi;
         for (uint32_t b0 = lo; b0 < hi; b0 += T) {
             const uint32_t p = b0 + threadIdx.x;
             uint32_t len = 0, w = 0;
