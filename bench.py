@@ -66,16 +66,16 @@ def per_step_bytes(st, n_attempts, step_bytes):
 
 
 def load_traffic(workload):
-    """Counter traffic of the sampler launch on this workload, if it was taken
-    on the current kernel sources: (fetch + write bytes, fetch bytes)."""
+    """Counter figures of the sampler launch on this workload (the traffic
+    file's fields), if they were taken on the current kernel sources; else {}."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None, None
+        return {}
     if t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload:
-        return None, None
-    return t.get("traffic_bytes_per_launch"), t.get("fetch_bytes_per_launch")
+        return {}
+    return t
 
 
 def host_cpu():
@@ -526,7 +526,8 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     b_alg = algorithmic_bytes(st)
     achieved = b_alg / (ms_sample * 1e-3) / 1e9
-    traffic, fetched = load_traffic(args.workload)
+    counters = load_traffic(args.workload)
+    traffic, fetched = counters.get("traffic_bytes_per_launch"), counters.get("fetch_bytes_per_launch")
 
     out = {
         "metric": "HSAW attempts/s (whole eSIA hot path: sample + count + greedy)",
@@ -553,6 +554,7 @@ def main():
         "evaluations_exact_cycle_steps": exact["stats"]["evaluations"],
         "sampler_attempts_per_s": n_att / (ms_sample * 1e-3),
         "ms_sample": ms_sample, "ms_count": ms_count, "ms_greedy": ms_greedy,
+        "ms_sample_median": sorted(r["stats"]["ms_sample"] for r in runs)[len(runs) // 2],
         "ingest_ms": ingest_ms,
         "arc_record_bytes": g.arc_bytes,
         "counts": {**{key: st[key] for key in ("hits", "dead_ends", "cycles", "steps", "walk_ids", "covered")},
@@ -562,6 +564,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "algorithmic_bytes_per_launch": b_alg, "traffic": traffic,
                      "gather_efficiency": b_alg / fetched if fetched else None,
+                     "l2_hit_rate": counters.get("l2_hit_rate"),
                      "frac_other_readings": {
                          **{f"{sb} B/step flat": per_step_bytes(st, n_att, sb) / (ms_sample * 1e-3) / 1e9
                             / HBM_PEAK_GBS for sb in (29, 21)},

@@ -24,13 +24,13 @@ def test_algorithmic_bytes_by_hand():
 def test_traffic_only_for_its_workload_and_kernel():
     with open(bench.TRAFFIC_FILE) as f:
         t = json.load(f)
-    traffic, fetched = bench.load_traffic(t["workload"])
+    got = bench.load_traffic(t["workload"])
     if t["kernel_sha"] == bench.kernel_sha():
-        assert traffic == t["traffic_bytes_per_launch"] and fetched == t["fetch_bytes_per_launch"]
-        assert traffic == fetched + t["write_bytes_per_launch"]
+        assert got == t
+        assert t["traffic_bytes_per_launch"] == t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
     else:
-        assert traffic is None
-    assert bench.load_traffic("another workload") == (None, None)
+        assert got == {}
+    assert bench.load_traffic("another workload") == {}
 
 
 def test_host_cpu_fields():
