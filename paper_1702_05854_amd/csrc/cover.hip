@@ -49,8 +49,6 @@ constexpr uint32_t kPerOctave = 512;
 constexpr uint32_t kBins = kExact + 20 * kPerOctave;  // octaves 2^12 .. 2^31
 constexpr uint32_t kPoolTarget = 4096;
 constexpr uint32_t kPoolMax = 8192;        // the lazy rounds keep the pool in LDS
-constexpr uint32_t kHashBits = 14;         // id -> pool position hash, load <= 1/2
-constexpr uint32_t kHash = 1u << kHashBits;
 constexpr uint32_t kFilterBits = 17;       // LDS bit filter of pool ids (false positives <= 1/16)
 // Coverage counting by id ranges (k_bin_sort .. k_bin_count): fine bins of
 // 2^kCountSpanLog ids (the LDS counters of one workgroup); up to
@@ -66,7 +64,6 @@ constexpr uint32_t kFineMax = 1u << kFineLog;
 constexpr uint32_t kChunk = 8192;           // second level: ids sorted per LDS chunk
 static_assert(kCountSpanLog + kCoarseLog + kFineLog >= 32, "two levels span a 32-bit id space");
 constexpr uint32_t kFilterWords = (1u << kFilterBits) / 32;
-static_assert(kHash >= 2 * kPoolMax, "pool hash load factor");
 
 enum PlanKind : uint32_t { PLAN_COLLECT = 0, PLAN_TIES = 1, PLAN_REFINE = 2 };
 // An overfull wide bin (one above the exact counts) is split by one or two
@@ -94,7 +91,7 @@ struct GreedyState {
     uint32_t r_shift;       //   sub-bins of 2^r_shift counts
     uint32_t r_nbins;       //   sub-bins covering the range (<= kRefineBins)
     uint32_t r_above;       //   unselected ids with a count above the range
-    uint32_t pad;
+    uint32_t wp_total;      // entries of the per-walk pool lists handed out so far
 };
 
 static_assert(sizeof(GreedyState) % 8 == 0, "GreedyState is cleared in 8-byte words");
@@ -108,6 +105,9 @@ struct GreedyJob {
     uint32_t *bitmap;   // ceil(id_space / 32): marked ids
     uint32_t *covered;  // n_walks
     uint32_t *claimed;  // n_walks: covered walks in the order they were covered
+    uint32_t *wcnt;     // n_walks: marked pool ids in the walk (0 for walks in no list)
+    uint32_t *wcur;     // n_walks: end of the walk's pool positions in wpool
+    uint16_t *wpool;    // n_ids: pool positions of the listed walks' marked ids, walk by walk
     const uint64_t *walk_off;
     const uint32_t *walk_len;
     const uint32_t *ids;
@@ -150,6 +150,9 @@ struct GJob {
     GLOBAL uint32_t *bitmap;
     GLOBAL uint32_t *covered;
     GLOBAL uint32_t *claimed;
+    GLOBAL uint32_t *wcnt;
+    GLOBAL uint32_t *wcur;
+    GLOBAL uint16_t *wpool;
     const GLOBAL uint64_t *walk_off;
     const GLOBAL uint32_t *walk_len;
     const GLOBAL uint32_t *ids;
@@ -183,6 +186,9 @@ __device__ __forceinline__ GJob view(const GreedyJob &j)
     J.bitmap = gp(j.bitmap);
     J.covered = gp(j.covered);
     J.claimed = gp(j.claimed);
+    J.wcnt = gp(j.wcnt);
+    J.wcur = gp(j.wcur);
+    J.wpool = gp(j.wpool);
     J.walk_off = gp(j.walk_off);
     J.walk_len = gp(j.walk_len);
     J.ids = gp(j.ids);
@@ -318,7 +324,10 @@ __global__ void k_init(const GreedyJob *jobs)
     const GJob J = view(jobs[blockIdx.y]);
     const uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t i = t; i < J.n_walks; i += stride) J.covered[i] = 0;
+    for (uint64_t i = t; i < J.n_walks; i += stride) {
+        J.covered[i] = 0;
+        J.wcnt[i] = 0;
+    }
     if (J.c_parts > 1)
         for (uint64_t i = t; i < J.S; i += stride) J.cnt[i] = 0;
     for (uint64_t i = t; i < kBins; i += stride) J.hist[i] = 0;
@@ -957,6 +966,7 @@ __global__ __launch_bounds__(1024) void k_pool_mark(const GreedyJob *jobs)
     if (threadIdx.x == 0) {
         J.pstart[P] = carry;
         st->plist_total = carry;
+        st->wp_total = 0;
     }
 }
 
@@ -1021,39 +1031,88 @@ __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
     }
 }
 
-// ---------------------------------------------------------------- lazy rounds
-__device__ __forceinline__ uint32_t hash_of(uint32_t x) { return (x * 2654435761u) >> (32 - kHashBits); }
-
-// pool position of id x (slot holds position + 1), or -1 if x is not in the pool
-__device__ __forceinline__ int pool_find(const uint32_t *slot, const uint32_t *pids, uint32_t x)
+// Per-walk pool lists: the transpose of the pool ids' walk lists.  For every
+// walk in some list, the pool positions of its marked ids, so that covering
+// a walk decrements its pool ids' counts without reading its ids or looking
+// them up.  The lists are counted, given their ranges of wpool (one atomic
+// per wave), filled, and after the rounds their counts are cleared again.
+// One wave per pool id's list (count, fill, clear); one thread per walk
+// (ranges).
+__global__ __launch_bounds__(256) void k_wp_count(const GreedyJob *jobs)
 {
-    uint32_t h = hash_of(x);
-    for (uint32_t probe = 0; probe < kHash; ++probe) {
-        const uint32_t v = slot[h];
-        if (v == 0) return -1;
-        if (pids[v - 1] == x) return static_cast<int>(v - 1);
-        h = (h + 1) & (kHash - 1);
-    }
-    return -1;
+    const GJob J = view(jobs[blockIdx.y]);
+    if (job_done(J) || J.st->plist_total == 0) return;  // uniform per block
+    const uint32_t P = pool_size(J.st);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < P; i += waves)
+        for (uint32_t e = J.pstart[i] + lane; e < J.pstart[i + 1]; e += kWave) g_add(&J.wcnt[J.plist[e]], 1u);
 }
 
+__global__ __launch_bounds__(256) void k_wp_alloc(const GreedyJob *jobs)
+{
+    const GJob J = view(jobs[blockIdx.y]);
+    if (job_done(J) || J.st->plist_total == 0) return;  // uniform per block
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t base = blockIdx.x * static_cast<uint64_t>(blockDim.x); base < J.n_walks; base += step) {
+        const uint64_t w = base + threadIdx.x;
+        const uint32_t c = w < J.n_walks ? J.wcnt[w] : 0u;
+        uint32_t incl = c;  // inclusive scan of the wave's counts
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_up(incl, d, kWave);
+            if (lane >= d) incl += o;
+        }
+        const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+        uint32_t b = 0;
+        if (lane == kWave - 1 && tot) b = g_add(&J.st->wp_total, tot);
+        b = __shfl(b, kWave - 1, kWave);
+        if (c) J.wcur[w] = b + incl - c;  // the walk's range starts here; the fill advances it
+    }
+}
+
+__global__ __launch_bounds__(256) void k_wp_fill(const GreedyJob *jobs)
+{
+    const GJob J = view(jobs[blockIdx.y]);
+    if (job_done(J) || J.st->plist_total == 0) return;  // uniform per block
+    const uint32_t P = pool_size(J.st);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < P; i += waves)
+        for (uint32_t e = J.pstart[i] + lane; e < J.pstart[i + 1]; e += kWave)
+            J.wpool[g_add(&J.wcur[J.plist[e]], 1u)] = static_cast<uint16_t>(i);
+}
+
+// after the rounds: the next pool's lists count from zero
+__global__ __launch_bounds__(256) void k_wp_clear(const GreedyJob *jobs)
+{
+    const GJob J = view(jobs[blockIdx.y]);
+    if (J.st->error != 0 || J.st->plist_total == 0) return;  // (runs after the job's last rounds too)
+    const uint32_t P = pool_size(J.st);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+    for (uint32_t i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < P; i += waves)
+        for (uint32_t e = J.pstart[i] + lane; e < J.pstart[i + 1]; e += kWave) J.wcnt[J.plist[e]] = 0;
+}
+
+// ---------------------------------------------------------------- lazy rounds
 // One workgroup of T threads per job: rounds [rounds, k) while the pool
 // certifies the pick.
 //
-// The pool lives in LDS for the whole launch: its ids, their exact counts
+// The pool lives in LDS for the whole launch: its ids and their exact counts
 // (a walk covered now never holds an id chosen in an earlier round, so chosen
-// entries are never decremented) and a hash from id to pool position.  A
-// round's argmax is then an LDS scan.  The global counts are not touched
+// entries are never decremented).  A round's argmax is then an LDS scan.  The global counts are not touched
 // here: each covered walk is appended to the claimed list, and k_uncover
 // (all CUs) takes the list's walks off the global counts after the launch,
 // before k_mark marks this launch's picks selected.  Each pool id's list
 // range sits in registers of the thread that holds the id.
 //
 // Covering: each pass claims up to T of the chosen id's walks (one list
-// entry per thread); block scans rank the claimed walks and lay their ids end
-// to end; every thread reads the ids at its positions (finding each one's walk
-// by binary search over the claimed walks' first positions in LDS) and
-// decrements the LDS counts of pool ids.
+// entry per thread); block scans rank the claimed walks and lay their pool
+// positions (the per-walk pool lists) end to end; every thread reads the
+// positions at its slots (finding each one's walk by binary search over the
+// claimed walks' first slots in LDS) and decrements those LDS counts.
 //
 // Zero gains.  When the best key of the pool has gain 0, every unselected id
 // of the pool has count 0 (and the plan is a tie at count 0, so every id
@@ -1069,14 +1128,13 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
     // each wave's best key and its list range, double-buffered by round parity
     // (a wave can be one round ahead of the slowest reader, not two)
     __shared__ uint64_t shk[2][kWaves];
-    __shared__ uint32_t shlo[2][kWaves], shhi[2][kWaves];
+    __shared__ uint32_t shlo[2][kWaves], shhi[2][kWaves], shpos[2][kWaves];
     __shared__ uint32_t sh32[kWaves];
-    __shared__ uint32_t start[T];        // a pass's walks: first flattened position
-    __shared__ uint64_t woff[T];         //                 and offset into ids
+    __shared__ uint32_t start[T];        // a pass's walks: first flattened slot
+    __shared__ uint32_t woff[T];         //                 and start in wpool
     __shared__ uint32_t pcnt[kPoolMax];  // exact counts of the pool's ids
     __shared__ uint32_t pids[kPoolMax];
-    __shared__ uint32_t slot[kHash];
-    __shared__ uint32_t filt[kFilterWords];
+    __shared__ uint32_t sortbuf[kPoolMax];  // zero-gain tail: the open pool ids, sorted
     const GJob J = view(jobs[blockIdx.x]);
     if (job_done(J)) return;  // uniform per block
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -1087,8 +1145,6 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
                              ? ((static_cast<uint64_t>(st->c_tie) + 1) << 32) | (0xFFFFFFFFu - st->next_id)
                              : st->tau;
     const bool ordered_zeros = ties && st->c_tie == 0 && st->pool_n == 0;
-    for (uint32_t i = threadIdx.x; i < kHash; i += T) slot[i] = 0;
-    filter_build(filt, J.pool, P);  // (ends with a barrier)
     uint32_t pid[kPer], plo[kPer], phi[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -1101,11 +1157,6 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             pcnt[i] = J.cnt[x];
             plo[j] = J.pstart[i];
             phi[j] = J.pstart[i + 1];
-            uint32_t h = hash_of(x);
-            for (uint32_t probe = 0; probe < kHash; ++probe) {
-                if (atomicCAS(&slot[h], 0u, i + 1) == 0u) break;
-                h = (h + 1) & (kHash - 1);
-            }
         }
     }
     __syncthreads();
@@ -1117,7 +1168,7 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
         // tau.  The key and the list range of each wave's best travel together,
         // so every thread ends the reduction knowing the pick's list.
         uint64_t best = 0;
-        uint32_t blo = 0, bhi = 0;
+        uint32_t blo = 0, bhi = 0, bpos = 0;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const uint32_t i = threadIdx.x + j * T;
@@ -1127,6 +1178,7 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
                     best = key;
                     blo = plo[j];
                     bhi = phi[j];
+                    bpos = i;
                 }
             }
         }
@@ -1143,15 +1195,17 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             shk[par][wid] = wbest;
             shlo[par][wid] = blo;
             shhi[par][wid] = bhi;
+            shpos[par][wid] = bpos;
         }
         __syncthreads();
         best = 0;
-        uint32_t lo = 0, hi = 0;
+        uint32_t lo = 0, hi = 0, cpos = 0;  // the pick's list range and pool position
         for (int w = 0; w < kWaves; ++w) {
             if (shk[par][w] > best) {
                 best = shk[par][w];
                 lo = shlo[par][w];
                 hi = shhi[par][w];
+                cpos = shpos[par][w];
             }
         }
         if (best <= tau) break;  // uniform: every thread saw the same values
@@ -1192,9 +1246,9 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             // outside the pool (this is a tie plan at count 0: all ids with a
             // count were collected), whose ids are all >= next_id when tied
             // ids were left out.  The picks are the pool's unselected ids in
-            // ascending order, below next_id: sort them (the hash space is no
-            // longer needed) and take them.  (The id just chosen is the first.)
-            uint32_t *buf = slot;
+            // ascending order, below next_id: sort them and take them.  (The
+            // id just chosen is the first.)
+            uint32_t *buf = sortbuf;
             uint32_t N = 1;
             while (N < P) N <<= 1;
             for (uint32_t i = threadIdx.x; i < N; i += T)
@@ -1236,16 +1290,16 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
         }
         for (uint32_t b0 = lo; b0 < hi; b0 += T) {
             const uint32_t p = b0 + threadIdx.x;
-            uint32_t len = 0, w = 0;
-            uint64_t off = 0;
+            uint32_t len = 0, w = 0, off = 0;
             if (p < hi) {
                 w = J.plist[p];
-                // the walk record is read beside the claim (used only if claimed)
-                const uint64_t o = J.walk_off[w];
-                const uint32_t l = J.walk_len[w];
-                if (g_xchg(&J.covered[w], 1u) == 0u) {  // a kept walk has >= 1 id
-                    off = o;
-                    len = l;
+                // the walk's pool list is read beside the claim (used only if
+                // claimed); it holds the pick's own position, so len >= 1
+                const uint32_t c = J.wcnt[w];
+                const uint32_t e = J.wcur[w];
+                if (g_xchg(&J.covered[w], 1u) == 0u) {
+                    off = e - c;
+                    len = c;
                 }
             }
             uint32_t n_new;
@@ -1260,35 +1314,31 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             const uint32_t mylen = threadIdx.x < n_new ? start[threadIdx.x] : 0u;
             uint32_t total;
             const uint32_t first = block_excl_scan<T>(mylen, sh32, total);  // ends with a barrier
-            start[threadIdx.x] = first;  // first position of claimed walk threadIdx.x
+            start[threadIdx.x] = first;  // first slot of claimed walk threadIdx.x
             __syncthreads();
-            // positions f = threadIdx.x + u*T, kSpan at a time: every id load of
-            // a group is issued before its LDS updates
+            // slots f = threadIdx.x + u*T, kSpan at a time: every load of a
+            // group is issued before its LDS updates
             constexpr uint32_t kSpan = 8;
             for (uint32_t f0 = threadIdx.x; f0 < total; f0 += kSpan * T) {
                 uint32_t x[kSpan];
 #pragma unroll
                 for (uint32_t u = 0; u < kSpan; ++u) {
                     const uint32_t f = f0 + u * T;
-                    x[u] = id;
+                    x[u] = cpos;
                     if (f < total) {
-                        // the last claimed walk whose first position is <= f holds f
+                        // the last claimed walk whose first slot is <= f holds f
                         uint32_t a = 0, b = n_new - 1;
                         while (a < b) {
                             const uint32_t m = (a + b + 1) >> 1;
                             if (start[m] <= f) a = m;
                             else b = m - 1;
                         }
-                        x[u] = J.ids[woff[a] + (f - start[a])];
+                        x[u] = J.wpool[woff[a] + (f - start[a])];
                     }
                 }
 #pragma unroll
-                for (uint32_t u = 0; u < kSpan; ++u) {
-                    if (x[u] != id && filter_has(filt, x[u])) {
-                        const int pos = pool_find(slot, pids, x[u]);
-                        if (pos >= 0) atomicSub(&pcnt[pos], 1u);
-                    }
-                }
+                for (uint32_t u = 0; u < kSpan; ++u)
+                    if (x[u] != cpos) atomicSub(&pcnt[x[u]], 1u);
             }
             __syncthreads();  // LDS counts final and LDS free before the next pass / round
         }
@@ -1413,6 +1463,9 @@ GreedyJob carve(const GreedyInput &g)
     J.bitmap = reinterpret_cast<uint32_t *>(take(4 * ((S + 31) / 32)));
     J.covered = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
     J.claimed = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
+    J.wcnt = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
+    J.wcur = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
+    J.wpool = reinterpret_cast<uint16_t *>(take(2 * std::max<uint64_t>(g.n_ids, 1)));
     J.sel = reinterpret_cast<int64_t *>(take(8 * g.k));
     J.gain = reinterpret_cast<uint64_t *>(take(8 * g.k));
     J.hist = reinterpret_cast<uint32_t *>(take(4 * kBins));
@@ -1462,7 +1515,8 @@ size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids,
     const uint64_t S = id_space;
     return al256(4 * S) + al256(4 * std::max<uint64_t>(n_ids, 1)) + al256(4 * (kPoolMax + 1)) +
            al256(4 * kPoolMax) + al256(4 * ((S + 31) / 32)) +
-           2 * al256(4 * std::max<uint64_t>(n_walks, 1)) + 2 * al256(8 * static_cast<uint64_t>(k)) +
+           4 * al256(4 * std::max<uint64_t>(n_walks, 1)) + al256(2 * std::max<uint64_t>(n_ids, 1)) +
+           2 * al256(8 * static_cast<uint64_t>(k)) +
            al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile)) +
            count_scratch_bytes(S, n_ids);
 }
@@ -1538,6 +1592,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
         std::min(grid_for(max_S, T * 8, base), std::max(1u, base / std::min<unsigned>(Q, 8)));
     const unsigned collect_blocks = grid_for(max_S, 256 * 8, cus * 4);
     const unsigned fill_blocks = grid_for(max_walks, 256, cus * 8);
+    const unsigned list_blocks = grid_for(static_cast<uint64_t>(kPoolMax) * kWave, 256, cus * 2);  // a wave per list
     std::vector<GreedyState> hs(Q);
     for (int group = 1;; group = std::min(group * 2, 8)) {
         for (int gen = 0; gen < group; ++gen) {
@@ -1553,7 +1608,11 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
             hipLaunchKernelGGL(k_tie_emit, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_pool_mark, dim3(Q), dim3(1024), 0, s, d_jobs);
             hipLaunchKernelGGL(k_pool_fill, dim3(fill_blocks, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_wp_count, dim3(list_blocks, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_wp_alloc, dim3(fill_blocks, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_wp_fill, dim3(list_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_lazy<T>, dim3(Q), dim3(T), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_wp_clear, dim3(list_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_uncover, dim3(cus * 4, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_mark, dim3(Q), dim3(256), 0, s, d_jobs);
             SIA_HIP(hipGetLastError());

@@ -943,7 +943,7 @@ sia_batch_config defaults(const sia_batch_config *c)
     if (!d.refill_chunk) d.refill_chunk = 256;
     if (!d.wave_attempts) d.wave_attempts = uint64_t(1) << 23;
     if (!d.min_share) d.min_share = uint64_t(1) << 16;
-    if (!d.greedy_batch) d.greedy_batch = 16;
+    if (!d.greedy_batch) d.greedy_batch = 32;
     return d;
 }
 
