@@ -427,7 +427,7 @@ def main():
                     help="batched/served queries vs plain on the mixed-query workload (rmat22)")
     ap.add_argument("--queries", type=int, default=512)
     ap.add_argument("--walk-budget", type=int, default=16384, help="MiB of walk buffers (--serve)")
-    ap.add_argument("--wave-ms", type=float, default=25.0, help="target sampling launch (--serve)")
+    ap.add_argument("--wave-ms", type=float, default=50.0, help="target sampling launch (--serve)")
     ap.add_argument("--loads", type=float, nargs="*", default=[0.5, 0.8, 1.0])
     ap.add_argument("--greedy-mode", type=int, default=0,
                     help="0: greedy between sampling launches, 1: on a second stream (--serve)")
