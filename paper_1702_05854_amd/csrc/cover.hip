@@ -1006,21 +1006,26 @@ __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
         woff[threadIdx.x] = off;
         wid[threadIdx.x] = static_cast<uint32_t>(w);
         __syncthreads();
-        for (uint32_t f0 = threadIdx.x; f0 < total; f0 += U * T) {
+        // each thread takes U consecutive positions: one search for the
+        // first, then the walk index only moves forward
+        for (uint32_t f0 = 0; f0 < total; f0 += U * T) {
+            const uint32_t fb = f0 + threadIdx.x * U;
             uint32_t x[U], k[U];
+            uint32_t kk = fb < total ? last_le(start, T, fb) : 0u;  // empty (covered) walks share their start
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const uint32_t f = f0 + u * T;
+                const uint32_t f = fb + u;
                 x[u] = 0u;
                 k[u] = 0u;
                 if (f < total) {
-                    k[u] = last_le(start, T, f);  // empty (covered) walks share their start
-                    x[u] = J.ids[woff[k[u]] + (f - start[k[u]])];
+                    while (kk + 1 < static_cast<uint32_t>(T) && start[kk + 1] <= f) ++kk;
+                    k[u] = kk;
+                    x[u] = J.ids[woff[kk] + (f - start[kk])];
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (f0 + u * T < total && filter_has(filt, x[u]) &&
+                if (fb + u < total && filter_has(filt, x[u]) &&
                     (J.bitmap[x[u] >> 5] & (1u << (x[u] & 31)))) {
                     const uint32_t i = J.pidx[x[u]];
                     J.plist[J.pstart[i] + g_add(&J.pfill[i], 1u)] = wid[k[u]];
@@ -1051,24 +1056,47 @@ __global__ __launch_bounds__(256) void k_wp_count(const GreedyJob *jobs)
 
 __global__ __launch_bounds__(256) void k_wp_alloc(const GreedyJob *jobs)
 {
+    constexpr uint32_t T = 256, kPer = 8;  // consecutive walks per thread
+    __shared__ uint32_t wsum[T / kWave];
+    __shared__ uint32_t bbase;
     const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J) || J.st->plist_total == 0) return;  // uniform per block
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t step = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t base = blockIdx.x * static_cast<uint64_t>(blockDim.x); base < J.n_walks; base += step) {
-        const uint64_t w = base + threadIdx.x;
-        const uint32_t c = w < J.n_walks ? J.wcnt[w] : 0u;
-        uint32_t incl = c;  // inclusive scan of the wave's counts
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const uint64_t span = static_cast<uint64_t>(T) * kPer;
+    // one atomic per block and span: the ranges of T * kPer walks at a time
+    for (uint64_t base = blockIdx.x * span; base < J.n_walks; base += static_cast<uint64_t>(gridDim.x) * span) {
+        const uint64_t w0 = base + static_cast<uint64_t>(threadIdx.x) * kPer;
+        uint32_t c[kPer], mine = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) {
+            c[j] = w0 + j < J.n_walks ? J.wcnt[w0 + j] : 0u;
+            mine += c[j];
+        }
+        uint32_t incl = mine;  // inclusive scan of the wave's sums
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) {
             const uint32_t o = __shfl_up(incl, d, kWave);
             if (lane >= d) incl += o;
         }
-        const uint32_t tot = __shfl(incl, kWave - 1, kWave);
-        uint32_t b = 0;
-        if (lane == kWave - 1 && tot) b = g_add(&J.st->wp_total, tot);
-        b = __shfl(b, kWave - 1, kWave);
-        if (c) J.wcur[w] = b + incl - c;  // the walk's range starts here; the fill advances it
+        if (lane == kWave - 1) wsum[wid] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t tot = 0;
+            for (uint32_t w = 0; w < T / kWave; ++w) {
+                const uint32_t v = wsum[w];
+                wsum[w] = tot;
+                tot += v;
+            }
+            bbase = tot ? g_add(&J.st->wp_total, tot) : 0u;
+        }
+        __syncthreads();
+        uint32_t at = bbase + wsum[wid] + incl - mine;  // the walks' ranges start here; the fill advances them
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) {
+            if (c[j]) J.wcur[w0 + j] = at;
+            at += c[j];
+        }
+        __syncthreads();  // wsum and bbase are rewritten next
     }
 }
 
@@ -1592,6 +1620,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
         std::min(grid_for(max_S, T * 8, base), std::max(1u, base / std::min<unsigned>(Q, 8)));
     const unsigned collect_blocks = grid_for(max_S, 256 * 8, cus * 4);
     const unsigned fill_blocks = grid_for(max_walks, 256, cus * 8);
+    const unsigned alloc_blocks = grid_for(max_walks, 256 * 8, cus * 8);  // 8 walks per thread
     const unsigned list_blocks = grid_for(static_cast<uint64_t>(kPoolMax) * kWave, 256, cus * 2);  // a wave per list
     std::vector<GreedyState> hs(Q);
     for (int group = 1;; group = std::min(group * 2, 8)) {
@@ -1609,7 +1638,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
             hipLaunchKernelGGL(k_pool_mark, dim3(Q), dim3(1024), 0, s, d_jobs);
             hipLaunchKernelGGL(k_pool_fill, dim3(fill_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_wp_count, dim3(list_blocks, Q), dim3(256), 0, s, d_jobs);
-            hipLaunchKernelGGL(k_wp_alloc, dim3(fill_blocks, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_wp_alloc, dim3(alloc_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_wp_fill, dim3(list_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_lazy<T>, dim3(Q), dim3(T), 0, s, d_jobs);
             hipLaunchKernelGGL(k_wp_clear, dim3(list_blocks, Q), dim3(256), 0, s, d_jobs);
