@@ -1226,16 +1226,19 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             shpos[par][wid] = bpos;
         }
         __syncthreads();
-        best = 0;
-        uint32_t lo = 0, hi = 0, cpos = 0;  // the pick's list range and pool position
-        for (int w = 0; w < kWaves; ++w) {
-            if (shk[par][w] > best) {
-                best = shk[par][w];
-                lo = shlo[par][w];
-                hi = shhi[par][w];
-                cpos = shpos[par][w];
+        // the waves' keys first, then only the winning wave's range and position
+        int bw = 0;
+        best = shk[par][0];
+#pragma unroll 3
+        for (int w = 1; w < kWaves; ++w) {
+            const uint64_t kw = shk[par][w];
+            if (kw > best) {
+                best = kw;
+                bw = w;
             }
         }
+        const uint32_t lo = shlo[par][bw], hi = shhi[par][bw];
+        const uint32_t cpos = shpos[par][bw];  // the pick's list range and pool position
         if (best <= tau) break;  // uniform: every thread saw the same values
         const uint32_t id = 0xFFFFFFFFu - static_cast<uint32_t>(best);
         const uint32_t g = static_cast<uint32_t>(best >> 32) - 1u;
