@@ -2,7 +2,9 @@
 // for nodes) over the kept walks of one or more queries ("jobs").
 //
 //   cnt[id] = number of not-yet-covered walks holding id (Cov of one id),
-//             exact at all times; 0xFFFFFFFF once id is selected;
+//             exact between launches of the rounds kernel (inside one, the
+//             pool's counts are kept in LDS and the walks it covers are taken
+//             off cnt after it ends); 0xFFFFFFFF once id is selected;
 //   key(id) = ((cnt+1) << 32) | (2^32-1-id) for an unselected id, 0 once
 //             selected: the largest key is the largest marginal gain with the
 //             lowest id on ties, and once every gain is zero the lowest id not
@@ -11,10 +13,10 @@
 // Lazy greedy.  Covering walks only lowers counts, so a key computed once is
 // an upper bound forever.  A pool holds the ids whose keys may be the
 // largest, and tau bounds the key of every id outside the pool.  One
-// workgroup per job runs rounds back to back: recompute the pool's keys from
-// the exact counts, and while the best exceeds tau it is the true argmax of
-// the round -- record it, mark its walks covered and decrement the counts of
-// their ids.  When the best no longer exceeds tau, grid-wide kernels rebuild
+// workgroup per job runs rounds back to back: take the pool's keys from its
+// exact counts, and while the best exceeds tau it is the true argmax of the
+// round -- record it, mark its walks covered and decrement the counts of
+// their pool ids.  When the best no longer exceeds tau, grid-wide kernels rebuild
 // the pool from the current counts: a histogram of counts, read on the
 // device, chooses the threshold, and ties at the threshold are taken by
 // ascending id (ordered compaction).  The result is exactly the greedy of
@@ -23,8 +25,10 @@
 // Walk lists.  Covering needs the walks holding the chosen id, and only pool
 // ids can be chosen, so with each pool the lists of its ids that still hold
 // uncovered walks are built (a bitmap marks them; one pass over the
-// uncovered walks appends each walk to the lists of its marked ids).  No
-// inverted index over the whole id space is built.
+// uncovered walks appends each walk to the lists of its marked ids), and
+// their transpose: for each listed walk, the pool positions of its ids, so
+// that covering a walk touches only its pool ids.  No inverted index over
+// the whole id space is built.
 //
 // Every kernel takes the job table; blockIdx.y (blockIdx.x for the
 // one-workgroup kernels) selects the job, so the greedies of a batch of
@@ -1040,9 +1044,9 @@ __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
 // walk in some list, the pool positions of its marked ids, so that covering
 // a walk decrements its pool ids' counts without reading its ids or looking
 // them up.  The lists are counted, given their ranges of wpool (one atomic
-// per wave), filled, and after the rounds their counts are cleared again.
-// One wave per pool id's list (count, fill, clear); one thread per walk
-// (ranges).
+// per block of 2048 walks), filled, and after the rounds their counts are
+// cleared again.  One wave per pool id's list (count, fill, clear); eight
+// consecutive walks per thread (ranges).
 __global__ __launch_bounds__(256) void k_wp_count(const GreedyJob *jobs)
 {
     const GJob J = view(jobs[blockIdx.y]);

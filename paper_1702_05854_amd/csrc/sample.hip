@@ -13,19 +13,23 @@
 //    the cycle length lambda in O(1) state, and the first-repeat step of the
 //    plain walk, mu + lambda, follows from a two-pointer pass from the start
 //    (the paper's heuristics had false negatives because its draws depended
-//    on the step, not the node).
-//  * Each wave keeps a ring of what its lanes evaluated: position t of a
-//    lane's walk goes to row it0 + t (it0: the iteration of its first
-//    evaluation).  A lane evaluates in consecutive iterations, so a row is
-//    mostly the same iteration of all 64 lanes and is written whole.  With
-//    the cycle length lambda known, the entry
-//    mu is the first position i with x_i == x_{i+lambda} -- false before mu,
-//    true from mu on -- found by bisection over the ring (two 4-byte reads
-//    per probe instead of walking the graph again), and a kept walk's ids are
-//    copied from the ring.  Walks longer than the ring fall back to a
-//    two-pointer pass from the start and a re-walk.  Coverage counts are
-//    taken afterwards, in one pass over the written ids (atomics here would
-//    compete with the gathers).
+//    on the step, not the node).  A query that does not need the step count
+//    of cyclic walks (SIA_FLAG_NO_CYCLE_STEPS) ends such a walk as soon as a
+//    repeat is seen, with no entry search; its lanes also run Nivasch's stack
+//    detector (a 16-entry stack per lane in LDS), which sees the repeat
+//    within one lap of the cycle where Brent may take two.
+//  * With 32-byte records (the format that searches), each wave keeps a ring
+//    of what its lanes evaluated: position t of a lane's walk goes to row
+//    it0 + t (it0: the iteration of its first evaluation).  A lane evaluates
+//    in consecutive iterations, so a row is mostly the same iteration of all
+//    64 lanes and is written whole.  With the cycle length lambda known, the
+//    entry mu is the first position i with x_i == x_{i+lambda} -- false
+//    before mu, true from mu on -- found by bisection over the ring (two
+//    4-byte reads per probe instead of walking the graph again), and a kept
+//    walk's ids are copied from the ring.  Walks longer than the ring, and
+//    every walk with 16-byte records, use a two-pointer pass from the start
+//    and a re-walk instead.  Coverage counts are taken afterwards, in one
+//    pass over the written ids (atomics here would compete with the gathers).
 //
 // One launch samples a wave: attempt ranges of up to 31 queries ("slots",
 // each with its own sources, seed, mode and output buffers) laid end to end.
@@ -35,8 +39,9 @@
 // wave.  A query with probabilistic suspects (a per-node coin threshold
 // array) starts uniformly over V and, at a tagged node, reads its threshold
 // in the next iteration: the node is a seed when the low half of its draw
-// word is below it (a seed start gives a walk without edges).  Every iteration a lane computes one Philox block (its start draw,
-// or the draw of the node it evaluates) and issues at most one 16-byte gather:
+// word is below it (a seed start gives a walk without edges).  Every
+// iteration a lane computes one Philox block (its start draw, or the draw of
+// the node it evaluates) and issues at most one 16-byte gather:
 // mostly the in-edge record the draw selects, which says whether the evaluated
 // node is a source and carries the next node's offset and degree -- so a step
 // costs one random line.  With 32-byte records (any weights) the record sits

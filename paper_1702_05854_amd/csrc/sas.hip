@@ -9,7 +9,8 @@
 // bound A and R'_t those in [A, A'): the bounds are read off histograms of
 // the stored attempt ids, R_t is compacted into the greedy's input, and the
 // coverage of the picks is counted over the store's walks in [A, A').  The
-// scalar steps of Check run on the host.
+// scalar steps of Check run on the host.  The driver reports no step counts,
+// so its sampling ends cyclic walks as soon as a repeat is seen.
 #include "common.hpp"
 
 #include <chrono>

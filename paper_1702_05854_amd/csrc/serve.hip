@@ -10,10 +10,12 @@
 //    size the counters report.  Shares are deterministic functions of their
 //    attempt ids, so a query's walks -- and its answer -- do not depend on
 //    how it was cut into shares or what it shared launches with.
-//  * the greedy thread takes every query whose attempts are all sampled and
-//    runs their greedies in shared launches (one job each) on its own
-//    stream, overlapping the next sampling launch.  Coverage is counted
-//    there from the kept walks.
+//  * a query whose attempts are all sampled waits for its greedy, which runs
+//    with others in shared launches (one job each; coverage is counted there
+//    from the kept walks).  By default (time-sliced) the sampler thread runs
+//    them between sampling launches, once greedy_batch of them wait or
+//    sampling cannot go on without them; in the concurrent mode the greedy
+//    thread runs them on its own stream, overlapping the sampling launches.
 //
 // Walk memory: slot buffers grow on demand within the budget and are kept
 // for the slot's next query; buffers of idle slots are released when a busy
