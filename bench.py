@@ -65,15 +65,18 @@ def per_step_bytes(st, n_attempts, step_bytes):
     return step_bytes * st["steps"] + 4 * n_attempts + 4 * st["walk_ids"] + 16 * st["hits"]
 
 
-def load_traffic(workload):
-    """Counter figures of the sampler launch on this workload (the traffic
-    file's fields), if they were taken on the current kernel sources; else {}."""
+def load_traffic(workload, mode, n_attempts, cycle_steps):
+    """Counter figures of the sampler launch of this query (the traffic file's
+    fields), if they were taken on the same workload, mode, attempt count and
+    cycle handling and on the current kernel sources; else {}."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return {}
     if t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload:
+        return {}
+    if (t.get("mode"), t.get("n_attempts"), t.get("cycle_steps")) != (mode, n_attempts, bool(cycle_steps)):
         return {}
     return t
 
@@ -526,11 +529,11 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     b_alg = algorithmic_bytes(st)
     achieved = b_alg / (ms_sample * 1e-3) / 1e9
-    counters = load_traffic(args.workload)
+    counters = load_traffic(args.workload, mode, n_att, args.cycle_steps)
     traffic, fetched = counters.get("traffic_bytes_per_launch"), counters.get("fetch_bytes_per_launch")
 
     out = {
-        "metric": "HSAW attempts/s (whole eSIA hot path: sample + count + greedy)",
+        "metric": f"HSAW attempts/s (whole {'eSIA' if mode == 'edges' else 'nSIA'} hot path: sample + count + greedy)",
         "value": n_att * args.steps / elapsed,
         "unit": "attempts/s",
         "n_gpus": 1,

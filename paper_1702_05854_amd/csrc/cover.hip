@@ -1388,6 +1388,23 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
         if (threadIdx.x + j * T < P) g_and(&J.bitmap[pid[j] >> 5], ~(1u << (pid[j] & 31)));
 }
 
+// After a k_lazy launch, cnt must again hold, for every unselected id, the
+// number of uncovered walks holding it.  Either the walks the launch covered
+// are taken off (k_uncover), or, when they outweigh the walks still
+// uncovered (queries whose picks cover most walks, as node removal of
+// well-hit sources does), the counts are recomputed from the uncovered walks
+// (k_recount_zero, then k_recount_add).  Estimated work in atomics: an id of
+// a walk costs one, clearing an id and testing a walk a sixteenth.
+__device__ __forceinline__ bool recount_cheaper(const GJob &J, const GLOBAL GreedyState *st)
+{
+    if (J.n_walks == 0) return false;
+    const double per_walk = static_cast<double>(J.n_ids) / static_cast<double>(J.n_walks);
+    const double covered_now = static_cast<double>(st->n_claimed - st->claimed_done);
+    const double open = static_cast<double>(J.n_walks - st->n_claimed);
+    return open * per_walk + (static_cast<double>(J.S) + static_cast<double>(J.n_walks)) / 16.0 <
+           covered_now * per_walk;
+}
+
 // Take the walks covered by the last k_lazy launch off the global counts:
 // one wave per claimed walk, its lanes along the walk's ids.  The picks'
 // own counts drop too; k_mark overwrites them next.
@@ -1395,6 +1412,7 @@ __global__ __launch_bounds__(256) void k_uncover(const GreedyJob *jobs)
 {
     const GJob J = view(jobs[blockIdx.y]);
     const GLOBAL GreedyState *st = J.st;
+    if (recount_cheaper(J, st)) return;  // uniform per block
     const uint32_t lo = st->claimed_done, hi = st->n_claimed;
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
@@ -1415,8 +1433,45 @@ __global__ __launch_bounds__(256) void k_uncover(const GreedyJob *jobs)
     }
 }
 
+// Recount, first pass: every unselected id's count to zero (selected ids,
+// and ids outside a candidate set, keep their mark).
+__global__ __launch_bounds__(256) void k_recount_zero(const GreedyJob *jobs)
+{
+    const GJob J = view(jobs[blockIdx.y]);
+    if (!recount_cheaper(J, J.st)) return;  // uniform per block
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < J.S; i += stride)
+        if (J.cnt[i] != kSelected) J.cnt[i] = 0;
+}
+
+// Recount, second pass: each wave tests 64 walks at a time and adds the ids
+// of the uncovered ones, its lanes along each walk.  No uncovered walk holds
+// a selected id; ids outside a candidate set keep their mark.
+__global__ __launch_bounds__(256) void k_recount_add(const GreedyJob *jobs)
+{
+    const GJob J = view(jobs[blockIdx.y]);
+    if (!recount_cheaper(J, J.st)) return;  // uniform per block
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t waves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
+    for (uint64_t base = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave * kWave;
+         base < J.n_walks; base += waves * kWave) {
+        const uint64_t w = base + lane;
+        uint64_t open = __ballot(w < J.n_walks && J.covered[w] == 0u);
+        while (open != 0) {
+            const uint64_t v = base + static_cast<uint64_t>(__ffsll(static_cast<long long>(open)) - 1);
+            open &= open - 1;
+            const uint64_t o = J.walk_off[v];
+            const uint32_t L = J.walk_len[v];
+            for (uint32_t e = lane; e < L; e += kWave) {
+                const uint32_t x = J.ids[o + e];
+                if (J.cnt[x] != kSelected) g_add(&J.cnt[x], 1u);
+            }
+        }
+    }
+}
+
 // Mark the picks of the rounds since the last call selected in the global
-// counts (after k_uncover) and retire the claimed entries.
+// counts (after k_uncover or the recount) and retire the claimed entries.
 __global__ __launch_bounds__(256) void k_mark(const GreedyJob *jobs)
 {
     const GJob J = view(jobs[blockIdx.x]);
@@ -1629,6 +1684,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     const unsigned fill_blocks = grid_for(max_walks, 256, cus * 8);
     const unsigned alloc_blocks = grid_for(max_walks, 256 * 8, cus * 8);  // 8 walks per thread
     const unsigned list_blocks = grid_for(static_cast<uint64_t>(kPoolMax) * kWave, 256, cus * 2);  // a wave per list
+    const unsigned zero_blocks = grid_for(max_S, 256, cus * 8);
+    const unsigned recount_blocks = grid_for(max_walks, 256, cus * 8);  // a wave per 64 walks
     std::vector<GreedyState> hs(Q);
     for (int group = 1;; group = std::min(group * 2, 8)) {
         for (int gen = 0; gen < group; ++gen) {
@@ -1650,6 +1707,8 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
             hipLaunchKernelGGL(k_lazy<T>, dim3(Q), dim3(T), 0, s, d_jobs);
             hipLaunchKernelGGL(k_wp_clear, dim3(list_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_uncover, dim3(cus * 4, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_recount_zero, dim3(zero_blocks, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_recount_add, dim3(recount_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_mark, dim3(Q), dim3(256), 0, s, d_jobs);
             SIA_HIP(hipGetLastError());
         }

@@ -21,16 +21,21 @@ def test_algorithmic_bytes_by_hand():
     assert bench.per_step_bytes(st, 100, 21) == 21 * 10 + 4 * 100 + 4 * 4 + 16 * 2
 
 
-def test_traffic_only_for_its_workload_and_kernel():
+def test_traffic_only_for_its_query_and_kernel():
     with open(bench.TRAFFIC_FILE) as f:
         t = json.load(f)
-    got = bench.load_traffic(t["workload"])
+    q = (t["workload"], t["mode"], t["n_attempts"], t["cycle_steps"])
+    got = bench.load_traffic(*q)
     if t["kernel_sha"] == bench.kernel_sha():
         assert got == t
         assert t["traffic_bytes_per_launch"] == t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
     else:
         assert got == {}
-    assert bench.load_traffic("another workload") == {}
+    other_mode = "nodes" if t["mode"] == "edges" else "edges"
+    assert bench.load_traffic("another workload", *q[1:]) == {}
+    assert bench.load_traffic(q[0], other_mode, *q[2:]) == {}
+    assert bench.load_traffic(q[0], q[1], q[2] // 2, q[3]) == {}
+    assert bench.load_traffic(*q[:3], not q[3]) == {}
 
 
 def test_host_cpu_fields():

@@ -46,6 +46,22 @@ def test_candidates_match_oracle(sia, er20k, mode, frac, k):
     assert np.isin(got["selected"], cand).all()
 
 
+def test_candidates_nodes_with_every_source(sia, er20k):
+    """Node removal with every source and half the other nodes as candidates:
+    the first picks (sources) cover most walks, so the counts are recomputed
+    from the walks left, whose ids outside C must keep their mark."""
+    wl, g, og = er20k
+    rng = np.random.default_rng(77)
+    others = np.setdiff1d(np.arange(g.n), wl.sources)
+    cand = np.concatenate([wl.sources, rng.choice(others, others.shape[0] // 2, replace=False)])
+    got = sia.solve(g, wl.sources, "nodes", 150, wl.n_attempts, 0, wl.seed, candidates=cand)
+    ref = candidates.solve_candidates(og, wl.sources, cpu.MODE_NODES, 150, wl.n_attempts, 0, wl.seed, cand)
+    assert np.array_equal(got["selected"], ref["selected"])
+    assert np.array_equal(got["gains"], ref["gains"])
+    assert got["stats"]["covered"] == ref["covered"]
+    assert np.isin(got["selected"], cand).all()
+
+
 def test_candidates_every_id_equals_plain_solve(sia, er20k):
     wl, g, og = er20k
     a = sia.solve(g, wl.sources, "edges", 50, wl.n_attempts, 0, wl.seed)

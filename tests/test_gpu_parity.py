@@ -319,6 +319,29 @@ def test_greedy_matches_oracle(sia, seed):
     assert np.array_equal(got_gain, ref_gain)
 
 
+def test_greedy_recount_when_picks_cover_most_walks(sia):
+    """Five hub ids, one of them in 95% of the walks (as the sources are in
+    node removal): the rounds that pick them cover far more walks than stay
+    uncovered, so the counts are recomputed from the uncovered walks instead
+    of decremented; the later rounds then run on the recomputed counts."""
+    rng = np.random.default_rng(21)
+    id_space, n_walks = 50_000, 40_000
+    hubs = rng.choice(id_space, 5, replace=False)
+    walks = []
+    for i in range(n_walks):
+        body = rng.choice(id_space, int(rng.integers(3, 20)), replace=False)
+        if rng.random() < 0.95:
+            body = np.unique(np.concatenate([body, hubs[rng.integers(0, 5, 1)]]))
+        walks.append(rng.permutation(body).astype(np.uint32))
+    off = np.zeros(n_walks + 1, np.uint64)
+    off[1:] = np.cumsum([w.shape[0] for w in walks])
+    ids = np.concatenate(walks)
+    got = sia.greedy(id_space, off, ids, 200)
+    ref = cpu.greedy_csr(id_space, off, ids, 200)
+    assert set(got[0][:5].tolist()) == set(hubs.tolist())
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
 def test_greedy_large_id_space(sia):
     """id space above 64^3 (more than 64 top-level entries) with a ragged tail."""
     rng = np.random.default_rng(9)
