@@ -232,7 +232,7 @@ sia_status sia_greedy(int64_t id_space, const uint64_t *walk_off, const uint32_t
  *              ids device uint32[walk_off[n_walks]], each walk holding an id
  *              at most once
  *   selected   device int64[k] (out); gains device uint64[k] (out)
- * Limit: about 8.2 id_space + 10 n_ids + 20 n_walks + 16 k bytes plus 3 MB
+ * Limit: about 8.2 id_space + 10 n_ids + 16 n_walks + 16 k bytes plus 3 MB
  * of scratch must fit in 64 MiB (for example id_space = 10^6, 3.5 * 10^6
  * ids in 5 * 10^5 walks); larger inputs are rejected with SIA_EINVAL and a
  * message giving the bytes needed.  Malformed walks (decreasing offsets, an

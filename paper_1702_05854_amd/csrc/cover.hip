@@ -107,10 +107,8 @@ struct GreedyJob {
     uint32_t *pstart;   // kPoolMax + 1: list starts (pool order)
     uint32_t *pfill;    // kPoolMax: list fill counters
     uint32_t *bitmap;   // ceil(id_space / 32): marked ids
-    uint32_t *covered;  // n_walks
     uint32_t *claimed;  // n_walks: covered walks in the order they were covered
-    uint32_t *wcnt;     // n_walks: marked pool ids in the walk (0 for walks in no list)
-    uint32_t *wcur;     // n_walks: end of the walk's pool positions in wpool
+    uint64_t *wst;      // n_walks: walk state, see kCovered
     uint16_t *wpool;    // n_ids: pool positions of the listed walks' marked ids, walk by walk
     const uint64_t *walk_off;
     const uint32_t *walk_len;
@@ -152,10 +150,8 @@ struct GJob {
     GLOBAL uint32_t *pstart;
     GLOBAL uint32_t *pfill;
     GLOBAL uint32_t *bitmap;
-    GLOBAL uint32_t *covered;
     GLOBAL uint32_t *claimed;
-    GLOBAL uint32_t *wcnt;
-    GLOBAL uint32_t *wcur;
+    GLOBAL uint64_t *wst;
     GLOBAL uint16_t *wpool;
     const GLOBAL uint64_t *walk_off;
     const GLOBAL uint32_t *walk_len;
@@ -188,10 +184,8 @@ __device__ __forceinline__ GJob view(const GreedyJob &j)
     J.pstart = gp(j.pstart);
     J.pfill = gp(j.pfill);
     J.bitmap = gp(j.bitmap);
-    J.covered = gp(j.covered);
     J.claimed = gp(j.claimed);
-    J.wcnt = gp(j.wcnt);
-    J.wcur = gp(j.wcur);
+    J.wst = gp(j.wst);
     J.wpool = gp(j.wpool);
     J.walk_off = gp(j.walk_off);
     J.walk_len = gp(j.walk_len);
@@ -229,10 +223,6 @@ __device__ __forceinline__ uint32_t g_add(GLOBAL uint32_t *p, uint32_t v)
 {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t g_xchg(GLOBAL uint32_t *p, uint32_t v)
-{
-    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ uint32_t g_or(GLOBAL uint32_t *p, uint32_t v)
 {
     return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -241,6 +231,26 @@ __device__ __forceinline__ uint32_t g_and(GLOBAL uint32_t *p, uint32_t v)
 {
     return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint64_t g_add64(GLOBAL uint64_t *p, uint64_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t g_or64(GLOBAL uint64_t *p, uint64_t v)
+{
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t g_and64(GLOBAL uint64_t *p, uint64_t v)
+{
+    return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Walk state, one 64-bit word per walk, so that one atomic claims a walk and
+// returns its pool list: bit 63 the walk is covered; bits 32..62 the marked
+// pool ids it holds (0 for walks in no list); bits 0..31 the end of its pool
+// positions in wpool (their start until the lists are filled).
+constexpr uint64_t kCovered = 1ull << 63;
+constexpr uint64_t kWsCountOne = 1ull << 32;
+__device__ __forceinline__ uint32_t ws_count(uint64_t s) { return static_cast<uint32_t>(s >> 32) & 0x7FFFFFFFu; }
 
 __device__ __forceinline__ uint32_t count_bin(uint32_t c)
 {
@@ -320,7 +330,7 @@ __device__ void scan_tiles_256(GLOBAL uint32_t *tiles, uint64_t n)
 }
 
 // ---------------------------------------------------------------- set-up
-// Zero the per-job state, histogram, covered flags and, when the counting
+// Zero the per-job state, histogram, walk states and, when the counting
 // pass adds partial counts, the counts (else it writes every count).  A
 // kernel rather than memsets, so a captured graph holds no memset nodes.
 __global__ void k_init(const GreedyJob *jobs)
@@ -328,10 +338,7 @@ __global__ void k_init(const GreedyJob *jobs)
     const GJob J = view(jobs[blockIdx.y]);
     const uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t i = t; i < J.n_walks; i += stride) {
-        J.covered[i] = 0;
-        J.wcnt[i] = 0;
-    }
+    for (uint64_t i = t; i < J.n_walks; i += stride) J.wst[i] = 0;
     if (J.c_parts > 1)
         for (uint64_t i = t; i < J.S; i += stride) J.cnt[i] = 0;
     for (uint64_t i = t; i < kBins; i += stride) J.hist[i] = 0;
@@ -999,7 +1006,7 @@ __global__ __launch_bounds__(256) void k_pool_fill(const GreedyJob *jobs)
         if (w < J.n_walks) {
             const uint64_t o = J.walk_off[w];
             const uint32_t l = J.walk_len[w];
-            if (!J.covered[w]) {
+            if (!(J.wst[w] & kCovered)) {
                 off = o;
                 len = l;
             }
@@ -1055,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_wp_count(const GreedyJob *jobs)
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t waves = gridDim.x * (blockDim.x / kWave);
     for (uint32_t i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < P; i += waves)
-        for (uint32_t e = J.pstart[i] + lane; e < J.pstart[i + 1]; e += kWave) g_add(&J.wcnt[J.plist[e]], 1u);
+        for (uint32_t e = J.pstart[i] + lane; e < J.pstart[i + 1]; e += kWave) g_add64(&J.wst[J.plist[e]], kWsCountOne);
 }
 
 __global__ __launch_bounds__(256) void k_wp_alloc(const GreedyJob *jobs)
@@ -1070,10 +1077,12 @@ __global__ __launch_bounds__(256) void k_wp_alloc(const GreedyJob *jobs)
     // one atomic per block and span: the ranges of T * kPer walks at a time
     for (uint64_t base = blockIdx.x * span; base < J.n_walks; base += static_cast<uint64_t>(gridDim.x) * span) {
         const uint64_t w0 = base + static_cast<uint64_t>(threadIdx.x) * kPer;
+        uint64_t ws[kPer];
         uint32_t c[kPer], mine = 0;
 #pragma unroll
         for (uint32_t j = 0; j < kPer; ++j) {
-            c[j] = w0 + j < J.n_walks ? J.wcnt[w0 + j] : 0u;
+            ws[j] = w0 + j < J.n_walks ? J.wst[w0 + j] : 0ull;
+            c[j] = ws_count(ws[j]);
             mine += c[j];
         }
         uint32_t incl = mine;  // inclusive scan of the wave's sums
@@ -1097,7 +1106,7 @@ __global__ __launch_bounds__(256) void k_wp_alloc(const GreedyJob *jobs)
         uint32_t at = bbase + wsum[wid] + incl - mine;  // the walks' ranges start here; the fill advances them
 #pragma unroll
         for (uint32_t j = 0; j < kPer; ++j) {
-            if (c[j]) J.wcur[w0 + j] = at;
+            if (c[j]) J.wst[w0 + j] = (ws[j] & ~0xFFFFFFFFull) | at;  // (no other writer now)
             at += c[j];
         }
         __syncthreads();  // wsum and bbase are rewritten next
@@ -1113,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_wp_fill(const GreedyJob *jobs)
     const uint32_t waves = gridDim.x * (blockDim.x / kWave);
     for (uint32_t i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < P; i += waves)
         for (uint32_t e = J.pstart[i] + lane; e < J.pstart[i + 1]; e += kWave)
-            J.wpool[g_add(&J.wcur[J.plist[e]], 1u)] = static_cast<uint16_t>(i);
+            J.wpool[static_cast<uint32_t>(g_add64(&J.wst[J.plist[e]], 1ull))] = static_cast<uint16_t>(i);
 }
 
 // after the rounds: the next pool's lists count from zero
@@ -1125,7 +1134,8 @@ __global__ __launch_bounds__(256) void k_wp_clear(const GreedyJob *jobs)
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t waves = gridDim.x * (blockDim.x / kWave);
     for (uint32_t i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < P; i += waves)
-        for (uint32_t e = J.pstart[i] + lane; e < J.pstart[i + 1]; e += kWave) J.wcnt[J.plist[e]] = 0;
+        for (uint32_t e = J.pstart[i] + lane; e < J.pstart[i + 1]; e += kWave)
+            g_and64(&J.wst[J.plist[e]], kCovered | 0xFFFFFFFFull);
 }
 
 // ---------------------------------------------------------------- lazy rounds
@@ -1328,13 +1338,12 @@ __global__ __launch_bounds__(T) void k_lazy(const GreedyJob *jobs)
             uint32_t len = 0, w = 0, off = 0;
             if (p < hi) {
                 w = J.plist[p];
-                // the walk's pool list is read beside the claim (used only if
-                // claimed); it holds the pick's own position, so len >= 1
-                const uint32_t c = J.wcnt[w];
-                const uint32_t e = J.wcur[w];
-                if (g_xchg(&J.covered[w], 1u) == 0u) {
-                    off = e - c;
-                    len = c;
+                // one atomic claims the walk and returns its pool list, which
+                // holds the pick's own position, so len >= 1
+                const uint64_t old = g_or64(&J.wst[w], kCovered);
+                if (!(old & kCovered)) {
+                    len = ws_count(old);
+                    off = static_cast<uint32_t>(old) - len;
                 }
             }
             uint32_t n_new;
@@ -1456,7 +1465,7 @@ __global__ __launch_bounds__(256) void k_recount_add(const GreedyJob *jobs)
     for (uint64_t base = (blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x) / kWave * kWave;
          base < J.n_walks; base += waves * kWave) {
         const uint64_t w = base + lane;
-        uint64_t open = __ballot(w < J.n_walks && J.covered[w] == 0u);
+        uint64_t open = __ballot(w < J.n_walks && !(J.wst[w] & kCovered));
         while (open != 0) {
             const uint64_t v = base + static_cast<uint64_t>(__ffsll(static_cast<long long>(open)) - 1);
             open &= open - 1;
@@ -1551,10 +1560,8 @@ GreedyJob carve(const GreedyInput &g)
     J.pstart = reinterpret_cast<uint32_t *>(take(4 * (kPoolMax + 1)));
     J.pfill = reinterpret_cast<uint32_t *>(take(4 * kPoolMax));
     J.bitmap = reinterpret_cast<uint32_t *>(take(4 * ((S + 31) / 32)));
-    J.covered = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
     J.claimed = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
-    J.wcnt = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
-    J.wcur = reinterpret_cast<uint32_t *>(take(4 * std::max<uint64_t>(g.n_walks, 1)));
+    J.wst = reinterpret_cast<uint64_t *>(take(8 * std::max<uint64_t>(g.n_walks, 1)));
     J.wpool = reinterpret_cast<uint16_t *>(take(2 * std::max<uint64_t>(g.n_ids, 1)));
     J.sel = reinterpret_cast<int64_t *>(take(8 * g.k));
     J.gain = reinterpret_cast<uint64_t *>(take(8 * g.k));
@@ -1605,7 +1612,8 @@ size_t greedy_scratch_bytes(uint64_t id_space, uint64_t n_walks, uint64_t n_ids,
     const uint64_t S = id_space;
     return al256(4 * S) + al256(4 * std::max<uint64_t>(n_ids, 1)) + al256(4 * (kPoolMax + 1)) +
            al256(4 * kPoolMax) + al256(4 * ((S + 31) / 32)) +
-           4 * al256(4 * std::max<uint64_t>(n_walks, 1)) + al256(2 * std::max<uint64_t>(n_ids, 1)) +
+           al256(4 * std::max<uint64_t>(n_walks, 1)) + al256(8 * std::max<uint64_t>(n_walks, 1)) +
+           al256(2 * std::max<uint64_t>(n_ids, 1)) +
            2 * al256(8 * static_cast<uint64_t>(k)) +
            al256(4 * kBins) + al256(4 * kPoolMax) + al256(4 * ((S + kScanTile - 1) / kScanTile)) +
            count_scratch_bytes(S, n_ids);

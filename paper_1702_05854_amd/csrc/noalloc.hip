@@ -100,7 +100,7 @@ extern "C" sia_status sia_greedy_noalloc(int64_t id_space, const uint64_t *walk_
         SIA_REQUIRE(need <= kScratchBytes, SIA_EINVAL,
                     "input too large for the allocation-free greedy: it needs " + std::to_string(need) +
                         " bytes of scratch, the limit is " + std::to_string(kScratchBytes) +
-                        " (about 8.2 S + 10 n_ids + 20 n_walks + 16 k bytes plus 3 MB)");
+                        " (about 8.2 S + 10 n_ids + 16 n_walks + 16 k bytes plus 3 MB)");
         uint32_t *flags = reinterpret_cast<uint32_t *>(base);
         uint32_t *len = reinterpret_cast<uint32_t *>(base + o_len);
 
