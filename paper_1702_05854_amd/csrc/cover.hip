@@ -868,12 +868,30 @@ __global__ __launch_bounds__(256) void k_collect(const GreedyJob *jobs)
     }
 }
 
+// Tiles the tie scan must count.  Ties at count 0 (the pool has room for
+// more than the ids that hold a count, as small queries give) take the
+// lowest unselected ids of count 0, and the first n_tie + 1 of them lie below
+// n_tie + 1 + n_ids + rounds: no more ids than n_ids hold a count and no more
+// than rounds are selected (unless a candidate set marks its excluded ids
+// selected too).  Past that the tiles need no scan.
+__device__ __forceinline__ uint64_t tie_tiles(const GJob &J)
+{
+    const GLOBAL GreedyState *st = J.st;
+    const uint64_t all = n_tiles_of(J.S);
+    if (st->c_tie != 0 || J.cand) return all;
+    return min(all, n_tiles_of(static_cast<uint64_t>(st->n_tie) + 1 + J.n_ids + st->rounds));
+}
+
 // Ties: per tile of 4096 ids, how many have cnt == c_tie.
 __global__ __launch_bounds__(256) void k_tie_count(const GreedyJob *jobs)
 {
     __shared__ uint32_t sh[4];
     const GJob J = view(jobs[blockIdx.y]);
     if (blockIdx.x >= n_tiles_of(J.S) || job_done(J) || J.st->plan != PLAN_TIES) return;
+    if (blockIdx.x >= tie_tiles(J)) {  // uniform per block: the ties end before this tile
+        if (threadIdx.x == 0) J.tiles[blockIdx.x] = 0;
+        return;
+    }
     const uint32_t c = J.st->c_tie;
     const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
     uint32_t k = 0;
