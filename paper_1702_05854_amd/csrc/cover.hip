@@ -882,54 +882,60 @@ __device__ __forceinline__ uint64_t tie_tiles(const GJob &J)
     return min(all, n_tiles_of(static_cast<uint64_t>(st->n_tie) + 1 + J.n_ids + st->rounds));
 }
 
-// Ties: per tile of 4096 ids, how many have cnt == c_tie.
+// Ties: per tile of 4096 ids, how many have cnt == c_tie.  Each workgroup
+// takes tiles gridDim.x apart, up to the job's tie_tiles (later tiles are
+// neither counted nor read).
 __global__ __launch_bounds__(256) void k_tie_count(const GreedyJob *jobs)
 {
     __shared__ uint32_t sh[4];
     const GJob J = view(jobs[blockIdx.y]);
-    if (blockIdx.x >= n_tiles_of(J.S) || job_done(J) || J.st->plan != PLAN_TIES) return;
-    if (blockIdx.x >= tie_tiles(J)) {  // uniform per block: the ties end before this tile
-        if (threadIdx.x == 0) J.tiles[blockIdx.x] = 0;
-        return;
-    }
+    if (job_done(J) || J.st->plan != PLAN_TIES) return;  // uniform per block
     const uint32_t c = J.st->c_tie;
-    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
-    uint32_t k = 0;
-    for (int i = 0; i < 16; ++i)
-        if (base + i < J.S && J.cnt[base + i] == c) ++k;
-    uint32_t total;
-    block_excl_scan_256(k, sh, total);
-    if (threadIdx.x == 0) J.tiles[blockIdx.x] = total;
+    const uint64_t lim = tie_tiles(J);
+    for (uint64_t b = blockIdx.x; b < lim; b += gridDim.x) {
+        const uint64_t base = b * kScanTile + threadIdx.x * 16ull;
+        uint32_t k = 0;
+        for (int i = 0; i < 16; ++i)
+            if (base + i < J.S && J.cnt[base + i] == c) ++k;
+        uint32_t total;
+        block_excl_scan_256(k, sh, total);  // ends with a barrier
+        if (threadIdx.x == 0) J.tiles[b] = total;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_tie_scan(const GreedyJob *jobs)
 {
     const GJob J = view(jobs[blockIdx.y]);
     if (job_done(J) || J.st->plan != PLAN_TIES) return;  // uniform per block
-    scan_tiles_256(J.tiles, n_tiles_of(J.S));
+    scan_tiles_256(J.tiles, tie_tiles(J));
 }
 
 // Ties: the first n_tie ids (ascending) with cnt == c_tie go to the pool after
-// the collected ones; the next tied id is recorded in next_id.
+// the collected ones; the next tied id is recorded in next_id.  Tiles as in
+// k_tie_count; a tile whose first tied id ranks past n_tie is skipped.
 __global__ __launch_bounds__(256) void k_tie_emit(const GreedyJob *jobs)
 {
     __shared__ uint32_t sh[4];
     const GJob J = view(jobs[blockIdx.y]);
-    if (blockIdx.x >= n_tiles_of(J.S) || job_done(J) || J.st->plan != PLAN_TIES) return;
+    if (job_done(J) || J.st->plan != PLAN_TIES) return;  // uniform per block
     const uint32_t R = J.st->n_tie, c = J.st->c_tie;
-    if (J.tiles[blockIdx.x] > R) return;  // uniform per block
     const uint32_t pool_base = J.st->pool_n;  // complete: written by an earlier kernel
-    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * kScanTile + threadIdx.x * 16ull;
-    uint32_t k = 0;
-    for (int i = 0; i < 16; ++i)
-        if (base + i < J.S && J.cnt[base + i] == c) ++k;
-    uint32_t total;
-    uint32_t q = J.tiles[blockIdx.x] + block_excl_scan_256(k, sh, total);
-    for (int i = 0; i < 16; ++i) {
-        if (base + i < J.S && J.cnt[base + i] == c) {
-            if (q < R) J.pool[pool_base + q] = static_cast<uint32_t>(base + i);
-            else if (q == R) J.st->next_id = static_cast<uint32_t>(base + i);
-            ++q;
+    const uint64_t lim = tie_tiles(J);
+    for (uint64_t b = blockIdx.x; b < lim; b += gridDim.x) {
+        const uint32_t first = J.tiles[b];
+        if (first > R) continue;  // uniform per block
+        const uint64_t base = b * kScanTile + threadIdx.x * 16ull;
+        uint32_t k = 0;
+        for (int i = 0; i < 16; ++i)
+            if (base + i < J.S && J.cnt[base + i] == c) ++k;
+        uint32_t total;
+        uint32_t q = first + block_excl_scan_256(k, sh, total);  // ends with a barrier
+        for (int i = 0; i < 16; ++i) {
+            if (base + i < J.S && J.cnt[base + i] == c) {
+                if (q < R) J.pool[pool_base + q] = static_cast<uint32_t>(base + i);
+                else if (q == R) J.st->next_id = static_cast<uint32_t>(base + i);
+                ++q;
+            }
         }
     }
 }
@@ -1711,6 +1717,7 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
     const unsigned alloc_blocks = grid_for(max_walks, 256 * 8, cus * 8);  // 8 walks per thread
     const unsigned list_blocks = grid_for(static_cast<uint64_t>(kPoolMax) * kWave, 256, cus * 2);  // a wave per list
     const unsigned zero_blocks = grid_for(max_S, 256, cus * 8);
+    const unsigned tie_blocks = std::max(1u, std::min(tiles, static_cast<unsigned>(cus) * 8));  // tiles apart
     const unsigned recount_blocks = grid_for(max_walks, 256, cus * 8);  // a wave per 64 walks
     std::vector<GreedyState> hs(Q);
     for (int group = 1;; group = std::min(group * 2, 8)) {
@@ -1722,9 +1729,9 @@ void run_greedy_jobs(std::vector<GreedyInput> &in, void *d_job_table, hipStream_
                 hipLaunchKernelGGL(k_refine_plan<T>, dim3(Q), dim3(T), 0, s, d_jobs);
             }
             hipLaunchKernelGGL(k_collect, dim3(collect_blocks, Q), dim3(256), 0, s, d_jobs);
-            hipLaunchKernelGGL(k_tie_count, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_tie_count, dim3(tie_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_tie_scan, dim3(1, Q), dim3(256), 0, s, d_jobs);
-            hipLaunchKernelGGL(k_tie_emit, dim3(tiles, Q), dim3(256), 0, s, d_jobs);
+            hipLaunchKernelGGL(k_tie_emit, dim3(tie_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_pool_mark, dim3(Q), dim3(1024), 0, s, d_jobs);
             hipLaunchKernelGGL(k_pool_fill, dim3(fill_blocks, Q), dim3(256), 0, s, d_jobs);
             hipLaunchKernelGGL(k_wp_count, dim3(list_blocks, Q), dim3(256), 0, s, d_jobs);
