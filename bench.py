@@ -193,9 +193,12 @@ def serve_measure(args, name, n_queries, loads, skip_plain=False):
     with sia.Batch(g, walk_budget_bytes=args.walk_budget << 20, use_graph=1,
                    greedy_mode=args.greedy_mode, greedy_cus=args.greedy_cus,
                    greedy_batch=args.greedy_batch) as b:
+        # the tuner samples the largest query's sources for 1.6*10^7 attempts per candidate
+        # shape, cyclic walks handled as they will be served: shorter probes let launch tails
+        # decide the choice, and the exact-steps rate sized launches at 40% of the target
         probe = qs[int(np.argmax([q["n_attempts"] for q in qs]))]
-        cfg = b.tune(probe["sources"], probe["mode"], min(probe["n_attempts"], 4_000_000),
-                     seed=probe["seed"], target_ms=args.wave_ms)
+        cfg = b.tune(probe["sources"], probe["mode"], 16_000_000,
+                     seed=probe["seed"], target_ms=args.wave_ms, cycle_steps=cs)
         print(f"[serve] tuned {cfg}", file=sys.stderr, flush=True)
         # warm-up: a few queries through every path
         for t in submit_all(b, qs[:8]):

@@ -575,7 +575,9 @@ sia_status sia_batch_stats_get(sia_batch *b, sia_batch_stats *out);
 
 /*
  * Autotune the launch shapes on a probe query: sample its attempts once per
- * candidate (workgroups per CU x refill chunk) and keep the fastest; size
+ * candidate (workgroups per CU x refill chunk), with the probe's flags (set
+ * SIA_FLAG_NO_CYCLE_STEPS when the queries to be served will), and keep the
+ * fastest; size
  * wave_attempts for launches of about target_ms; then run the greedy on the
  * probe's walks (k = the probe's k, or 1000 if 0) once per histogram tiling
  * candidate and keep the fastest.  The batch must be idle (no unfinished

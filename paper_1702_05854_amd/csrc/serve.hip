@@ -826,6 +826,7 @@ struct sia_batch {
         t->n_attempts = q.n_attempts;
         t->offset = q.attempt_offset;
         t->seed = q.seed;
+        t->cycle_steps = (q.flags & SIA_FLAG_NO_CYCLE_STEPS) == 0;  // measured as it will run
         t->st = build_source_tables(g->n, q.sources, q.n_sources);
         {
             std::lock_guard<std::mutex> l(mu);
@@ -1212,6 +1213,7 @@ sia_status sia_batch_tune(sia_batch *b, const sia_query *probe, double target_ms
         SIA_REQUIRE(b != nullptr && probe != nullptr, SIA_EINVAL, "NULL argument");
         check_query(b->g->n, b->g->m, probe->mode, probe->sources, probe->n_sources, 0,
                     probe->n_attempts, probe->attempt_offset);
+        SIA_REQUIRE((probe->flags & ~SIA_FLAG_NO_CYCLE_STEPS) == 0, SIA_EINVAL, "unknown flag bits");
         DeviceScope ds(b->g->device);
         const sia_batch_config c = b->tune(*probe, target_ms);
         if (chosen) *chosen = c;

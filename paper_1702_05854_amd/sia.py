@@ -498,8 +498,9 @@ class Batch:
         _check(lib().sia_batch_stats_get(self._h, C.byref(s)))
         return s.as_dict()
 
-    def tune(self, sources, mode, n_attempts, attempt_offset=0, seed=2017, target_ms=50.0, k=0):
-        q, src = _query(sources, mode, k, n_attempts, attempt_offset, seed)
+    def tune(self, sources, mode, n_attempts, attempt_offset=0, seed=2017, target_ms=50.0, k=0,
+             cycle_steps=True):
+        q, src = _query(sources, mode, k, n_attempts, attempt_offset, seed, cycle_steps)
         cfg = BatchConfig()
         _check(lib().sia_batch_tune(self._h, C.byref(q), target_ms, C.byref(cfg)))
         return cfg.as_dict()

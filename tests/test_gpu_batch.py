@@ -263,6 +263,27 @@ def test_tune_then_serve(sia, rmat16):
             assert_same(done(b, t), solo(sia, g, qs[i]), i)
 
 
+def test_tune_with_the_served_flags(sia, rmat16):
+    """Tuning on a probe whose cyclic walks stop at detection (as the queries
+    served after it), then fast-mode queries equal to single calls; unknown
+    probe flag bits are rejected."""
+    import ctypes
+    wl, g = rmat16
+    from paper_1702_05854_amd import sia as S
+    with S.Batch(g) as b:
+        cfg = b.tune(wl.sources[:100], "edges", 1_000_000, target_ms=10.0, cycle_steps=False)
+        assert cfg["sampler_blocks_per_cu"] >= 1 and cfg["wave_attempts"] >= 1 << 20
+        q, keep = S._query(wl.sources[:100], "edges", 0, 100_000, 0, 7)
+        q.flags = 4
+        assert S.lib().sia_batch_tune(b._h, ctypes.byref(q), 10.0, None) == -1
+        qs = mix(wl.n, 8, 23, max_sources=300, k_range=(5, 100), attempts_range=(20_000, 500_000))
+        for q in qs:
+            q["cycle_steps"] = False
+        ts = [b.submit(q["sources"], q["mode"], q["k"], q["n_attempts"], 0, q["seed"], False) for q in qs]
+        for i, t in enumerate(ts):
+            assert_same(done(b, t), solo(sia, g, qs[i]), i)
+
+
 def test_batch_and_solo_calls_share_a_graph(sia, rmat16):
     wl, g = rmat16
     qs = mix(wl.n, 12, 18, max_sources=500, k_range=(10, 100), attempts_range=(100_000, 1_000_000))
