@@ -408,6 +408,25 @@ def test_greedy_zero_gain_tails(sia, case):
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
+@pytest.mark.parametrize("layout", ["low_ids", "high_ids", "spread"])
+def test_greedy_zero_ties_in_a_large_id_space(sia, layout):
+    """Few walks in a 2^22 id space and k well past the ids they hold: the
+    zero-count ties are counted only up to the bound where the ids they take
+    must end (the lowest unselected ids of count 0), with the walks' ids at the
+    bottom of the id space, at its top, or spread over it."""
+    rng = np.random.default_rng({"low_ids": 31, "high_ids": 32, "spread": 33}[layout])
+    S, n_walks, k = 1 << 22, 500, 6000
+    lo, hi = {"low_ids": (0, 3000), "high_ids": (S - 3000, S), "spread": (0, S)}[layout]
+    walks = [(lo + rng.choice(hi - lo, int(rng.integers(1, 6)), replace=False)).astype(np.uint32)
+             for _ in range(n_walks)]
+    off = np.zeros(n_walks + 1, np.uint64)
+    off[1:] = np.cumsum([w.shape[0] for w in walks])
+    ids = np.concatenate(walks)
+    got = sia.greedy(S, off, ids, k)
+    ref = cpu.greedy_csr(S, off, ids, k)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
 def test_greedy_empty_and_exhaustive(sia):
     sel, gains = sia.greedy(5, np.zeros(1, np.uint64), np.zeros(0, np.uint32), 5)
     assert sel.tolist() == [0, 1, 2, 3, 4] and gains.tolist() == [0] * 5
