@@ -146,6 +146,25 @@ def test_rmat24_solve_properties(sia, rmat24):
     assert int(hit.sum()) == st["covered"]
 
 
+def test_rmat24_nodes_greedy_equals_oracle_greedy(sia, rmat24):
+    """Node removal on the same query (10^8 attempts, k = 1000): every kept
+    walk holds its terminal source, so the first picks cover nearly all
+    walks (the counts are recomputed instead of decremented) and the picks'
+    walk lists run to 10^5 entries.  The library's picks and gains equal the
+    oracle's greedy (Algorithm 7) over the same kept walks."""
+    wl, g, og, host = rmat24
+    say("gpu sample (nodes)")
+    walks = sia.sample(g, wl.sources, "nodes", wl.n_attempts, 0, wl.seed)
+    say("gpu solve (nodes)")
+    r = sia.solve(g, wl.sources, "nodes", wl.k, wl.n_attempts, 0, wl.seed, cycle_steps=False)
+    assert r["stats"]["hits"] == walks.n_walks and r["stats"]["walk_ids"] == walks.ids.shape[0]
+    say("oracle greedy over", walks.n_walks, "walks,", walks.ids.shape[0], "ids")
+    sel, gains = cpu.greedy_csr(g.n, walks.off, walks.ids, wl.k)
+    say("compare")
+    assert np.array_equal(r["selected"], sel) and np.array_equal(r["gains"], gains)
+    assert r["stats"]["covered"] == int(gains.sum())
+
+
 def _digest(name):
     import json
     import os
